@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for the Newton-Stokes operator -- TEST INFRASTRUCTURE ONLY.
+
+This package is the slow, plain reference that the GPU engine is checked
+against.  Only the test-suite, the smoke check in ``__graft_entry__`` and the
+CPU-baseline leg of ``bench.py`` may import it; the engine itself never does,
+and it shares no code, tables or helpers with the engine.
+
+What it computes, by definition (no sum factorisation, no blocking):
+
+* reference tables: tensor Gauss-Lobatto Lagrange basis on Gauss points,
+  the mapped P_{k-1} pressure basis (Sec. 3.2.1-3.2.2);
+* element restrictions R_e by point location in a coarse neighbour and
+  evaluation of its Lagrange basis (Sec. 3.2.1, figure "hanging");
+* dense element residuals and Jacobians by full tensor quadrature of
+  eq. (weak) and eq. (newton) with the tensor of eq. (rank4) (Sec. 2.2-2.3);
+* the basal Robin term (eq. (robin), eq. (weak));
+* global assembly A = sum_e R_e^T A_e R_e (Sec. 3.2.1) with scipy.sparse;
+* the residual VJP and the energy functional of the appendix.
+
+Every function carries "parity unpinned" in its docstring where no
+independent pin exists; the pins live in ``tests/test_oracle_*.py``.
+"""
+from .reference import ReferenceElement
+from .restriction import build_restriction
+from .stokes import StokesOracle
+
+__all__ = ["ReferenceElement", "build_restriction", "StokesOracle"]
