@@ -1,0 +1,179 @@
+"""Throughput of the Newton-Stokes Jacobian apply on one MI355X.
+
+A step is one application y = J_c x of the Newton-linearised Stokes operator
+(gather with hanging-node interpolation, sum-factorised gradients, the fused
+quadrature-point Newton-tensor step, pressure terms, transposed contractions,
+basal Robin term, scatter, Dirichlet rows) on the workload "slab 64x64x8, Q3 x P2,
+element aspect ratio 125, 20% of the columns refined 2:1" with inputs resident in
+HBM.  The headline value is the mixed-precision (FP32) apply; the FP64 apply, the
+FP32-vs-FP64 error, the linearisation (set_state), residual and VJP times are
+reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDoF/s of Newton-Stokes Jacobian apply, mixed vs FP64 at stated rel. error"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(sz, geo_kind, word):
+    """Bytes one Jacobian apply must move with stored linearisation data:
+    8 values per quadrature point (mu', kappa, Sigma0), x read and y written once, per-element
+    geometry (affine) or per-point geometry (column-mapped), basal face data and beta."""
+    k = sz["k"]
+    nq = sz["n_el"] * (k + 1) ** 3
+    nvec = 3 * sz["n_nodes"] + sz["n_el"] * sz["n_p"]
+    geo = 4 * sz["n_el"] if geo_kind == "affine" else 2 * sz["n_el"] + 4 * nq
+    face = sz["n_bface"] * (1 + 4 * (k + 1) ** 2)
+    return word * (8 * nq + 2 * nvec + geo + face)
+
+
+def cpu_baseline(seed=0):
+    """The FP64 oracle as it stands: assemble the Jacobian and apply it once, on a reduced
+    sample of the same workload (12x12x2 columns, same element shape, 20% refined)."""
+    import threadpoolctl
+    from meshgen import make_config
+    from oracle import StokesOracle
+    w = make_config(2, seed=seed, nx=12, ny=12, nz=2)
+    m = w.mesh
+    t0 = time.perf_counter()
+    o = StokesOracle(m, w.n, w.eps, w.B0, w.logA, w.beta)
+    o.set_state(w.u, w.p)
+    xu, xp = w.directions[0]
+    o.jacobian_apply(xu, xp)
+    t1 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        o.jacobian_apply(xu, xp)
+    t2 = time.perf_counter()
+    threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] + [1])
+    return {"value": m.n_dof / (t1 - t0) / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"slab 12x12x2 Q3xP2 (aspect 125, 20% refined), {m.n_el} elements, {m.n_dof} DoF: "
+                       f"dense-quadrature element matrices + CSR assembly + one SpMV = {t1 - t0:.2f} s; "
+                       f"SpMV alone with the assembled matrix {(t2 - t1) / reps * 1e3:.2f} ms "
+                       f"({m.n_dof / ((t2 - t1) / reps) / 1e9:.4f} GDoF/s)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is "
+              f"not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from meshgen import make_config
+    from paper_1406_6573_amd import Engine
+
+    print(f"[bench] building workload config{args.config}", file=sys.stderr, flush=True)
+    w = make_config(args.config, n_dirs=1) if args.config != 5 else make_config(5, n_dirs=1)
+    m = w.mesh
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    eng = Engine(0)
+    eng.upload_mesh(m)
+    eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
+    u, p = t(w.u), t(w.p)
+    xu, xp = w.directions[0]
+    x64u, x64p = t(xu), t(xp)
+    x32u, x32p = x64u.float(), x64p.float()
+    y64 = (torch.empty_like(x64u), torch.empty_like(x64p))
+    y32 = (torch.empty_like(x32u), torch.empty_like(x32p))
+    sz = dict(eng.sizes)
+    sz["k"] = m.k
+    geo = eng.geometry_kind()
+    print(f"[bench] n_el={sz['n_el']} n_dof={sz['n_dof']} geometry={geo}", file=sys.stderr, flush=True)
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    ms_state = timed(lambda: eng.set_state(u, p), 5, 1)
+    ms_res = timed(lambda: eng.residual(), 10, 2)
+    ms_vjp = timed(lambda: eng.residual_vjp(x64u, x64p), 10, 2)
+    out = {}
+    for prec, (xa, xb, yy) in (("fp64", (x64u, x64p, y64)), ("fp32", (x32u, x32p, y32)),
+                              ("bf16ops", (x32u, x32p, y32))):
+        fn = lambda: eng.jacobian_apply(xa, xb, prec, out=yy)
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        eng.set_kernel_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        kms, nk = eng.kernel_time()
+        eng.set_kernel_timing(False)
+        out[prec] = dict(ms=ms, kernel_ms=kms / max(nk, 1))
+        print(f"[bench] {prec}: {ms:.4f} ms/apply, element kernel {kms / max(nk, 1):.4f} ms", file=sys.stderr,
+              flush=True)
+    # accuracy of the mixed paths against the FP64 apply (which matches the FP64 oracle to ~1e-14)
+    r64u, r64p = eng.jacobian_apply(x64u, x64p, "fp64")
+    ref = torch.cat([r64u.reshape(-1), r64p.reshape(-1)])
+    errs = {}
+    for prec in ("fp32", "bf16ops"):
+        a, b = eng.jacobian_apply(x32u, x32p, prec)
+        got = torch.cat([a.reshape(-1), b.reshape(-1)]).double()
+        errs[prec] = float((got - ref).norm() / ref.norm())
+    n_dof = sz["n_dof"]
+    gdofs = {k: n_dof / (v["ms"] * 1e-3) / 1e9 for k, v in out.items()}
+    b32 = algorithmic_bytes(sz, geo, 4)
+    b64 = algorithmic_bytes(sz, geo, 8)
+    ach32 = b32 / (out["fp32"]["kernel_ms"] * 1e-3) / 1e9
+    ach64 = b64 / (out["fp64"]["kernel_ms"] * 1e-3) / 1e9
+    rec = {
+        "metric": METRIC, "value": gdofs["fp32"], "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": out["fp32"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"config{args.config}: " + {2: "slab 64x64x8 Q3xP2, aspect 125, 20% columns refined 2:1",
+                                                            3: "terrain slab 128x128x16 Q4xP3",
+                                                            4: "slab 96x96x12 Q3xP2, 20% refined",
+                                                            5: "dome 256x256x8 Q2xP1, margin refined",
+                                                            1: "unit box 8x8x2 Q2xP1"}[args.config],
+                   "k": m.k, "n_el": sz["n_el"], "n_dof": n_dof, "geometry": geo},
+        "rel_err_vs_fp64": errs["fp32"],
+        "fp64": {"value": gdofs["fp64"], "ms_per_step": out["fp64"]["ms"],
+                 "roofline_frac": ach64 / HBM_PEAK_GBS},
+        "speedup_mixed_vs_fp64": out["fp64"]["ms"] / out["fp32"]["ms"],
+        "bf16ops_trial": {"value": gdofs["bf16ops"], "rel_err_vs_fp64": errs["bf16ops"]},
+        "set_state_ms": ms_state, "residual_ms": ms_res, "vjp_fp64_ms": ms_vjp,
+        "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach32 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_apply<float,4,affine>", "kernel_ms": out["fp32"]["kernel_ms"],
+                     "algorithmic_bytes": b32},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a reduced sample", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline()
+    eng.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * nsmf.h -- matrix-free Newton-Stokes operator engine for AMD MI355X (gfx950).
+ *
+ * C ABI of the engine that applies, matrix-free on hexahedral Q_k x P_{k-1}^disc
+ * meshes (k = 2, 3, 4) with 2:1 hanging nodes:
+ *   - the nonlinear residual of the Glen-law Stokes problem, eq. (weak) with the
+ *     viscosity of eq. (glen) (Sec. 2.1-2.2 of the paper);
+ *   - the Newton-linearised saddle-point operator A(u) = [[F(u), B^T], [B, 0]]
+ *     of Sec. 4.1, F built from the 4th-order tensor of eq. (rank4) and the basal
+ *     Robin term of eq. (robin) (eq. (newton), Sec. 2.3);
+ *   - the vector-Jacobian product of the residual with respect to u, p, the
+ *     per-element log rate factor and the per-face basal friction.
+ *
+ * Conventions (all entry points):
+ *   - Every vector argument is a DEVICE pointer on the context's device, owned by
+ *     the caller, contiguous and at least 8-byte aligned; it must stay alive until
+ *     the work enqueued on the context's stream has completed.  Host arrays appear
+ *     only in nsmf_mesh and are copied during nsmf_upload_mesh.
+ *   - Velocity vectors are structure-of-arrays [3][n_nodes] (x, y, z components),
+ *     pressure vectors are element-major [n_el][n_p], n_p = k(k+1)(k+2)/6, with the
+ *     basis of normalised Legendre products Lhat_i(xi) Lhat_j(eta) Lhat_l(zeta),
+ *     i+j+l <= k-1, ordered by (i+j+l, l, j, i) on each element's reference cube.
+ *   - Work is enqueued asynchronously on the stream given by nsmf_set_stream
+ *     (default: the null stream); no call synchronises except nsmf_upload_mesh
+ *     (which validates the geometry on the device) and nsmf_kernel_time.
+ *   - Errors are returned as nsmf_status codes; a message is kept per context
+ *     (nsmf_last_error).  Argument and mesh errors are detected before any work is
+ *     enqueued.  A device fault surfaces as NSMF_EHIP on the same or a later call.
+ *   - Calls on one context are not thread-safe.
+ *
+ * Normal Dirichlet condition (eq. (robin), second line): velocity components flagged
+ * in nsmf_mesh.dmask are eliminated.  The state and residual use P u (P zeroes the
+ * flagged components), residual rows of flagged components equal u itself, and
+ * the Jacobian is J_c = P K P + (I - P), which keeps it symmetric.
+ */
+#ifndef NSMF_H
+#define NSMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsmf_ctx nsmf_ctx;
+
+typedef enum {
+  NSMF_OK = 0,
+  NSMF_EINVAL = -1,  /* bad argument: NULL pointer, size or precision out of range   */
+  NSMF_EHIP = -2,    /* HIP runtime error (allocation, launch, device fault)          */
+  NSMF_EMESH = -3,   /* invalid mesh: node id out of range, inconsistent hanging mask,
+                        inverted element (det J <= 0 at a quadrature point)            */
+  NSMF_ESTATE = -4,  /* call order: no mesh uploaded or no state set                   */
+  NSMF_EUNSUP = -5,  /* unsupported: k outside 2..4, geometry that is not column-mapped */
+  NSMF_ENOMEM = -6   /* device memory exhausted                                        */
+} nsmf_status;
+
+typedef enum {
+  NSMF_FP64 = 0,          /* double vectors, FP64 arithmetic                              */
+  NSMF_FP32 = 1,          /* float vectors; quadrature-point data rounded once from FP64;
+                             FP32 contractions and FP32 accumulation                       */
+  NSMF_FP32_BF16OPS = 2   /* as NSMF_FP32 with the 1D reference-element operators (basis
+                             values and derivatives at Gauss points) rounded to bfloat16  */
+} nsmf_prec;
+
+/* Mesh description (host memory, copied by nsmf_upload_mesh).
+ *
+ * Elements are hexahedra with (k+1)^3 Gauss-Lobatto nodes each (Sec. 3.2.1); element
+ * slot a = a0 + P*(a1 + P*a2), P = k+1, a_d the node index along reference axis d.
+ * The isoparametric map of an element is its Q_k interpolant of the slot coordinates
+ * obtained through the same restriction R_e as the velocity (so hanging faces follow
+ * the coarse neighbour: the mesh is watertight).
+ *
+ * Hanging nodes (Sec. 3.2.1, figure "hanging"): a slot lying on a face or edge of a
+ * coarser neighbour holds in elem_nodes the id of the neighbour's node at the SAME
+ * local index along the face/edge tangent directions; the engine interpolates those
+ * values in place with the 1D child-interval interpolation matrices.  cmask bits:
+ *   0..2   child position (hx, hy, hz) of the element inside its refined parent;
+ *   3..8   hanging face -x, +x, -y, +y, -z, +z;
+ *   9..20  hanging edge 4*dir + s0 + 2*s1, dir 0/1/2 = parallel to x/y/z, (s0, s1)
+ *          the side (0 low / 1 high) along the two other axes in increasing order.
+ */
+typedef struct {
+  int32_t k;                    /* polynomial degree of velocity: 2, 3 or 4                 */
+  int64_t n_el;                 /* number of elements (> 0)                                  */
+  int64_t n_nodes;              /* number of independent (global) velocity nodes, < 2^28     */
+  int64_t n_bface;              /* number of basal faces (>= 0)                              */
+  const int32_t *elem_nodes;    /* [n_el][(k+1)^3] global node ids (see above)               */
+  const uint32_t *cmask;        /* [n_el] hanging-constraint bits (see above)                */
+  const double *coords;         /* [3][n_nodes] node coordinates                             */
+  const int32_t *bface_elem;    /* [n_bface] elements whose zeta = -1 face lies on the base  */
+  const uint8_t *dmask;         /* [3][n_nodes] 1 = Dirichlet-constrained component; may be NULL */
+} nsmf_mesh;
+
+/* Glen law (eq. (glen)): mu = B0 * exp(-logA_e / n) * (II + eps)^((1-n)/(2n)),
+ * II = D(u):D(u)/2; constant body-force density b gives f(v) = int b.v. */
+typedef struct {
+  double n;        /* flow-law exponent, >= 1          */
+  double eps;      /* regularisation, > 0              */
+  double B0;       /* rate-factor scale, > 0           */
+  double body[3];  /* body-force density (b_x, b_y, b_z) */
+} nsmf_params;
+
+/* Create a context on HIP device `hip_device`.  *out is set to NULL on failure. */
+int nsmf_create(nsmf_ctx **out, int hip_device);
+/* Release all device memory owned by the context (waits for its stream). */
+void nsmf_destroy(nsmf_ctx *ctx);
+/* Stream on which all subsequent work is enqueued (a hipStream_t, e.g. torch's
+ * current stream handle); NULL selects the null stream. */
+int nsmf_set_stream(nsmf_ctx *ctx, void *hip_stream);
+
+/* Copy and validate the mesh, build the per-element/per-quadrature-point geometry in
+ * FP64 on the device (Sec. 3.2.1 isoparametric map; Gauss quadrature with k+1 points
+ * per direction).  Synchronises.  Errors: NSMF_EINVAL, NSMF_EUNSUP (k, or geometry not
+ * column-mapped: x and y must depend only on (xi, eta) affinely per element),
+ * NSMF_EMESH (ids out of range, hanging bits on a level without parent, det J <= 0). */
+int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *mesh);
+
+/* Flow-law parameters, per-element logA [n_el] and per-basal-face beta [n_bface]
+ * (DEVICE pointers, FP64; NULL means all zeros; copied).  Invalidates the state. */
+int nsmf_set_params(nsmf_ctx *ctx, const nsmf_params *params, const double *logA, const double *beta);
+
+/* Linearisation point (u [3][n_nodes], p [n_el][n_p]; DEVICE, FP64; copied).  Computes
+ * per quadrature point, in FP64, the viscosity and Newton-tensor data of eq. (rank4)
+ * (and their FP32 roundings for the mixed path).  Requires mesh and params. */
+int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p);
+
+/* Residual at the state (eq. (weak)), FP64: r_u [3][n_nodes], r_p [n_el][n_p].
+ * f_u (nullable, [3][n_nodes]) is an extra load subtracted from the momentum rows. */
+int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p);
+
+/* y = J_c x with J_c the Newton Jacobian at the state (eq. (newton), eq. (rank4)).
+ * x_u, y_u [3][n_nodes]; x_p, y_p [n_el][n_p]; double for NSMF_FP64, float otherwise.
+ * x and y must not overlap. */
+int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p);
+
+/* Vector-Jacobian product of the residual at the state for cotangent w = (w_u, w_p):
+ * g_u, g_p = J_c^T w (= J_c w, the operator is symmetric); g_logA[e] = d<w, r>/dlogA_e;
+ * g_beta[f] = d<w, r>/dbeta_f.  w and g_u/g_p are double for NSMF_FP64, float otherwise;
+ * g_logA [n_el] and g_beta [n_bface] are always double.  Any g_* may be NULL. */
+int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
+                      double *g_logA, double *g_beta);
+
+/* Sizes of the uploaded mesh; any pointer may be NULL. */
+int nsmf_query(nsmf_ctx *ctx, int64_t *n_nodes, int64_t *n_el, int64_t *n_p, int64_t *n_dof, int64_t *n_bface);
+
+/* Geometry kind chosen at upload: 0 affine axis-aligned boxes, 1 column-mapped. */
+int nsmf_geometry_kind(nsmf_ctx *ctx);
+
+/* Event timing of the element kernel of jacobian_apply / residual_vjp.  While enabled,
+ * each such call records a HIP event pair around its element kernel on the context's
+ * stream; nsmf_kernel_time synchronises and returns the summed milliseconds and the
+ * number of launches since enabling, then resets. */
+int nsmf_set_kernel_timing(nsmf_ctx *ctx, int enable);
+int nsmf_kernel_time(nsmf_ctx *ctx, double *ms_total, int64_t *launches);
+
+/* Last error message of the context (never NULL). */
+const char *nsmf_last_error(const nsmf_ctx *ctx);
+/* Library version string. */
+const char *nsmf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSMF_H */

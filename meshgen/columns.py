@@ -126,9 +126,11 @@ def _axis_tables(k: int):
     fr[1, 1] = 0.5 + (xi + 1.0) / 4.0
     off = (fr >= 1.0 - 1e-14).astype(np.int64)
     frac = np.where(off == 1, 0.0, fr)
-    U = np.unique(np.round(frac.ravel(), 13))
-    idx = np.searchsorted(U, np.round(frac, 13))
-    assert np.allclose(U[idx], np.round(frac, 13))
+    # merge equal fractions through a rounded key, but keep the unrounded values
+    keys, first = np.unique(np.round(frac.ravel(), 13), return_index=True)
+    U = frac.ravel()[first]
+    idx = np.searchsorted(keys, np.round(frac, 13))
+    assert np.allclose(U[idx], frac, rtol=0, atol=1e-15)
     return U, off, idx
 
 

@@ -27,7 +27,13 @@ def gll_nodes(k: int) -> np.ndarray:
     """Gauss-Lobatto nodes of degree k on [-1, 1]: -1, roots of P_k', +1."""
     c = np.zeros(k + 1)
     c[k] = 1.0
-    inner = np.sort(np.real(npleg.legroots(npleg.legder(c)))) if k >= 2 else np.array([])
+    d1 = npleg.legder(c)
+    d2 = npleg.legder(d1)
+    inner = np.sort(np.real(npleg.legroots(d1))) if k >= 2 else np.array([])
+    # companion-matrix roots are accurate to a few ulp; polish them as roots of P_k'
+    for _ in range(3):
+        inner = inner - npleg.legval(inner, d1) / npleg.legval(inner, d2)
+    inner = 0.5 * (inner - inner[::-1])          # the roots are symmetric about 0
     return np.concatenate([[-1.0], inner, [1.0]])
 
 

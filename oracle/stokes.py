@@ -68,6 +68,9 @@ class StokesOracle:
         self.R = build_restriction(mesh, ref, self.elems)          # [E*S, n_nodes]
         # geometry: X_e = R_e X (watertight), J = dX/dxi at quadrature points
         Xs = (self.R @ mesh.coords.T).reshape(E, self.S, 3)
+        # the map's derivative is translation invariant: differentiate coordinates relative
+        # to each element's first node so that rounding stays relative to the element size
+        Xs = Xs - Xs[:, :1, :]
         J = np.einsum("esi,qsr->eqir", Xs, ref.dPhi)
         self.detJ = np.linalg.det(J)
         if np.any(self.detJ <= 0):

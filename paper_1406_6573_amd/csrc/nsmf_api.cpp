@@ -1,0 +1,397 @@
+// C ABI of the engine: context, mesh upload and validation, parameters, state, and the
+// residual / Jacobian-apply / VJP entry points declared in include/nsmf.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nsmf.h"
+#include "nsmf_internal.h"
+
+using namespace nsmf;
+
+namespace {
+
+template <typename T> struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  hipError_t alloc(size_t count) {
+    free();
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void **)&p, count * sizeof(T));
+  }
+  void free() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+int launch_threads(int P) { return P == 5 ? Launch<5>::NT : (P == 4 ? Launch<4>::NT : Launch<3>::NT); }
+int launch_elems(int P) { return P == 5 ? Launch<5>::E : (P == 4 ? Launch<4>::E : Launch<3>::E); }
+
+}  // namespace
+
+struct nsmf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err = "";
+  // mesh
+  bool have_mesh = false;
+  int k = 0, P = 0, n_p = 0, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0;
+  int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_masked = 0;
+  HostTables tab;
+  DevBuf<uint32_t> en, cmask;
+  DevBuf<int32_t> bface_of, mask_list;
+  DevBuf<uint8_t> dmask;
+  DevBuf<double> geo_el64, geo_qp64, face64;
+  DevBuf<float> geo_el32, geo_qp32, face32;
+  // params
+  bool have_params = false;
+  nsmf_params prm;
+  DevBuf<double> logA, beta64;
+  DevBuf<float> beta32;
+  // state
+  bool have_state = false;
+  DevBuf<double> st64, fst64, u, p;
+  DevBuf<float> st32, fst32;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+
+  int fail(int code, const std::string &msg) {
+    err = msg;
+    return code;
+  }
+  int hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return NSMF_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? NSMF_ENOMEM : NSMF_EHIP;
+  }
+  MeshView mesh_view() const {
+    MeshView m;
+    m.en = en.p;
+    m.cmask = cmask.p;
+    m.bface_of = bface_of.p;
+    m.n_el = n_el;
+    m.n_nodes = n_nodes;
+    m.nblocks = nblocks;
+    return m;
+  }
+  GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p}; }
+  GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p}; }
+  void free_mesh() {
+    en.free(); cmask.free(); bface_of.free(); mask_list.free(); dmask.free();
+    geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
+    logA.free(); beta64.free(); beta32.free();
+    st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free();
+    have_mesh = have_params = have_state = false;
+  }
+};
+
+#define NSMF_TRY(ctx, expr, what)                    \
+  do {                                               \
+    int _rc = (ctx)->hip((expr), (what));            \
+    if (_rc != NSMF_OK) return _rc;                  \
+  } while (0)
+
+extern "C" {
+
+const char *nsmf_version(void) { return "nsmf 0.1 (gfx950)"; }
+
+const char *nsmf_last_error(const nsmf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int nsmf_create(nsmf_ctx **out, int hip_device) {
+  if (!out) return NSMF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return NSMF_EINVAL;
+  if (hipSetDevice(hip_device) != hipSuccess) return NSMF_EHIP;
+  nsmf_ctx *c = new nsmf_ctx();
+  c->device = hip_device;
+  *out = c;
+  return NSMF_OK;
+}
+
+void nsmf_destroy(nsmf_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &ev : ctx->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  ctx->free_mesh();
+  delete ctx;
+}
+
+int nsmf_set_stream(nsmf_ctx *ctx, void *stream) {
+  if (!ctx) return NSMF_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return NSMF_OK;
+}
+
+int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
+  if (!ctx || !m) return NSMF_EINVAL;
+  NSMF_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (m->k < 2 || m->k > 4) return ctx->fail(NSMF_EUNSUP, "k must be 2, 3 or 4");
+  if (m->n_el <= 0 || m->n_nodes <= 0 || m->n_bface < 0) return ctx->fail(NSMF_EINVAL, "sizes must be positive");
+  if (m->n_nodes >= (int64_t)NODE_MASK) return ctx->fail(NSMF_EINVAL, "n_nodes must be below 2^28");
+  if (!m->elem_nodes || !m->cmask || !m->coords || (m->n_bface > 0 && !m->bface_elem))
+    return ctx->fail(NSMF_EINVAL, "NULL mesh array");
+  ctx->free_mesh();
+  const int P = m->k + 1, P2 = P * P, P3 = P2 * P;
+  const int64_t n_el = m->n_el, N = m->n_nodes, NB = m->n_bface;
+  // ---- host validation and node words
+  std::vector<uint32_t> words((size_t)n_el * P3);
+  for (int64_t i = 0; i < n_el * P3; ++i) {
+    const int32_t id = m->elem_nodes[i];
+    if (id < 0 || id >= N) return ctx->fail(NSMF_EMESH, "elem_nodes entry out of range");
+    uint32_t wd = (uint32_t)id;
+    if (m->dmask)
+      for (int c = 0; c < 3; ++c)
+        if (m->dmask[c * N + id]) wd |= 1u << (MASK_SHIFT + c);
+    words[i] = wd;
+  }
+  for (int64_t e = 0; e < n_el; ++e)
+    if (m->cmask[e] >> 21) return ctx->fail(NSMF_EMESH, "cmask has bits above 20");
+  std::vector<int32_t> bof((size_t)n_el, -1);
+  for (int64_t f = 0; f < NB; ++f) {
+    const int32_t e = m->bface_elem[f];
+    if (e < 0 || e >= n_el) return ctx->fail(NSMF_EMESH, "bface_elem entry out of range");
+    if (bof[e] >= 0) return ctx->fail(NSMF_EMESH, "element listed twice in bface_elem");
+    bof[e] = (int32_t)f;
+  }
+  std::vector<int32_t> mlist;
+  std::vector<uint8_t> dm((size_t)3 * N, 0);
+  if (m->dmask)
+    for (int64_t i = 0; i < 3 * N; ++i)
+      if (m->dmask[i]) {
+        mlist.push_back((int32_t)i);
+        dm[i] = 1;
+      }
+  if (3 * N >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EINVAL, "3*n_nodes must fit in int32");
+
+  ctx->k = m->k;
+  ctx->P = P;
+  build_tables(m->k, &ctx->tab);
+  ctx->n_p = ctx->tab.n_p;
+  ctx->n_el = n_el;
+  ctx->n_nodes = N;
+  ctx->n_bface = NB;
+  ctx->n_masked = (int64_t)mlist.size();
+  ctx->nt = launch_threads(P);
+  ctx->epb = launch_elems(P);
+  ctx->nblocks = (int)((n_el + ctx->epb - 1) / ctx->epb);
+  hipStream_t s = ctx->stream;
+
+  NSMF_TRY(ctx, ctx->en.alloc(words.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->cmask.alloc(n_el), "hipMalloc");
+  NSMF_TRY(ctx, ctx->bface_of.alloc(n_el), "hipMalloc");
+  NSMF_TRY(ctx, ctx->dmask.alloc(3 * N), "hipMalloc");
+  NSMF_TRY(ctx, ctx->mask_list.alloc(mlist.size()), "hipMalloc");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->en.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->cmask.p, m->cmask, n_el * 4, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->bface_of.p, bof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->dmask.p, dm.data(), 3 * N, hipMemcpyHostToDevice, s), "copy");
+  if (!mlist.empty())
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->mask_list.p, mlist.data(), mlist.size() * 4, hipMemcpyHostToDevice, s), "copy");
+
+  DevBuf<double> X;
+  DevBuf<unsigned> flags;
+  NSMF_TRY(ctx, X.alloc(3 * N), "hipMalloc");
+  NSMF_TRY(ctx, flags.alloc(1), "hipMalloc");
+  NSMF_TRY(ctx, hipMemcpyAsync(X.p, m->coords, 3 * N * 8, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, launch_fill(s, flags.p, 1), "fill");
+  MeshView mv = ctx->mesh_view();
+  NSMF_TRY(ctx, launch_geometry_impl(P, 0, s, mv, ctx->tab, X.p, nullptr, nullptr, nullptr, flags.p), "geometry");
+  unsigned hflags = 0;
+  NSMF_TRY(ctx, hipMemcpyAsync(&hflags, flags.p, 4, hipMemcpyDeviceToHost, s), "copy");
+  NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry check");
+  flags.free();
+  if (hflags & 4u) {
+    X.free();
+    return ctx->fail(NSMF_EMESH, "inverted or degenerate element (det J <= 0 at a quadrature point)");
+  }
+  if (hflags & 8u) {
+    X.free();
+    return ctx->fail(NSMF_EMESH, "degenerate basal face");
+  }
+  if (hflags & 1u) {
+    X.free();
+    return ctx->fail(NSMF_EUNSUP, "geometry is not column-mapped (x, y must be affine in xi, eta per element)");
+  }
+  ctx->geo = (hflags & 2u) ? GEO_COLUMN : GEO_AFFINE;
+  const size_t nqp = (size_t)ctx->nblocks * P * ctx->nt;
+  const size_t nel_geo = (size_t)n_el * (ctx->geo == GEO_AFFINE ? 4 : 2);
+  NSMF_TRY(ctx, ctx->geo_el64.alloc(nel_geo), "hipMalloc");
+  NSMF_TRY(ctx, ctx->geo_el32.alloc(nel_geo), "hipMalloc");
+  if (ctx->geo == GEO_COLUMN) {
+    NSMF_TRY(ctx, ctx->geo_qp64.alloc(4 * nqp), "hipMalloc");
+    NSMF_TRY(ctx, ctx->geo_qp32.alloc(4 * nqp), "hipMalloc");
+    NSMF_TRY(ctx, launch_fill(s, ctx->geo_qp64.p, 8 * nqp), "fill");
+  }
+  NSMF_TRY(ctx, ctx->face64.alloc((size_t)NB * 4 * P2), "hipMalloc");
+  NSMF_TRY(ctx, ctx->face32.alloc((size_t)NB * 4 * P2), "hipMalloc");
+  NSMF_TRY(ctx, launch_geometry_impl(P, ctx->geo == GEO_AFFINE ? 1 : 2, s, mv, ctx->tab, X.p, ctx->geo_el64.p,
+                                     ctx->geo_qp64.p, ctx->face64.p, nullptr),
+           "geometry");
+  NSMF_TRY(ctx, launch_d2f(s, ctx->geo_el64.p, ctx->geo_el32.p, nel_geo), "convert");
+  if (ctx->geo == GEO_COLUMN) NSMF_TRY(ctx, launch_d2f(s, ctx->geo_qp64.p, ctx->geo_qp32.p, 4 * nqp), "convert");
+  NSMF_TRY(ctx, launch_d2f(s, ctx->face64.p, ctx->face32.p, (size_t)NB * 4 * P2), "convert");
+  NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry");
+  X.free();
+
+  NSMF_TRY(ctx, ctx->st64.alloc(8 * nqp), "hipMalloc");
+  NSMF_TRY(ctx, ctx->st32.alloc(8 * nqp), "hipMalloc");
+  NSMF_TRY(ctx, launch_fill(s, ctx->st64.p, 16 * nqp), "fill");
+  NSMF_TRY(ctx, launch_fill(s, ctx->st32.p, 8 * nqp), "fill");
+  NSMF_TRY(ctx, ctx->fst64.alloc((size_t)NB * 3 * P2), "hipMalloc");
+  NSMF_TRY(ctx, ctx->fst32.alloc((size_t)NB * 3 * P2), "hipMalloc");
+  NSMF_TRY(ctx, ctx->u.alloc(3 * N), "hipMalloc");
+  NSMF_TRY(ctx, ctx->p.alloc((size_t)n_el * ctx->n_p), "hipMalloc");
+  NSMF_TRY(ctx, ctx->logA.alloc(n_el), "hipMalloc");
+  NSMF_TRY(ctx, ctx->beta64.alloc(NB > 0 ? NB : 1), "hipMalloc");
+  NSMF_TRY(ctx, ctx->beta32.alloc(NB > 0 ? NB : 1), "hipMalloc");
+  ctx->have_mesh = true;
+  ctx->err = "";
+  return NSMF_OK;
+}
+
+int nsmf_set_params(nsmf_ctx *ctx, const nsmf_params *prm, const double *logA, const double *beta) {
+  if (!ctx || !prm) return NSMF_EINVAL;
+  if (!ctx->have_mesh) return ctx->fail(NSMF_ESTATE, "no mesh uploaded");
+  if (!(prm->n >= 1.0) || !(prm->eps > 0.0) || !(prm->B0 > 0.0))
+    return ctx->fail(NSMF_EINVAL, "need n >= 1, eps > 0, B0 > 0");
+  hipStream_t s = ctx->stream;
+  ctx->prm = *prm;
+  if (logA)
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->logA.p, logA, ctx->n_el * 8, hipMemcpyDeviceToDevice, s), "copy");
+  else
+    NSMF_TRY(ctx, launch_fill(s, ctx->logA.p, 2 * ctx->n_el), "fill");
+  if (ctx->n_bface > 0) {
+    if (beta)
+      NSMF_TRY(ctx, hipMemcpyAsync(ctx->beta64.p, beta, ctx->n_bface * 8, hipMemcpyDeviceToDevice, s), "copy");
+    else
+      NSMF_TRY(ctx, launch_fill(s, ctx->beta64.p, 2 * ctx->n_bface), "fill");
+    NSMF_TRY(ctx, launch_d2f(s, ctx->beta64.p, ctx->beta32.p, ctx->n_bface), "convert");
+  }
+  ctx->have_params = true;
+  ctx->have_state = false;
+  return NSMF_OK;
+}
+
+int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p) {
+  if (!ctx || !u || !p) return NSMF_EINVAL;
+  if (!ctx->have_mesh || !ctx->have_params) return ctx->fail(NSMF_ESTATE, "set_state needs mesh and params");
+  hipStream_t s = ctx->stream;
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->u.p, u, 3 * ctx->n_nodes * 8, hipMemcpyDeviceToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->p.p, p, ctx->n_el * ctx->n_p * 8, hipMemcpyDeviceToDevice, s), "copy");
+  NSMF_TRY(ctx,
+           launch_state(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->u.p, ctx->logA.p,
+                        ctx->prm.n, ctx->prm.eps, ctx->prm.B0, ctx->st64.p, ctx->st32.p, ctx->fst64.p, ctx->fst32.p),
+           "state kernel");
+  ctx->have_state = true;
+  return NSMF_OK;
+}
+
+int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p) {
+  if (!ctx || !r_u || !r_p) return NSMF_EINVAL;
+  if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "residual needs a state");
+  hipStream_t s = ctx->stream;
+  NSMF_TRY(ctx, launch_fill(s, r_u, 6 * ctx->n_nodes), "fill");
+  NSMF_TRY(ctx,
+           launch_residual(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->st64.p, ctx->fst64.p,
+                           ctx->beta64.p, ctx->p.p, ctx->prm.body, r_u, r_p),
+           "residual kernel");
+  NSMF_TRY(ctx, launch_residual_fixup(s, ctx->dmask.p, 3 * ctx->n_nodes, ctx->u.p, f_u, r_u), "fixup");
+  return NSMF_OK;
+}
+
+static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, const void *x_p, void *y_u, void *y_p,
+                        double *g_logA, double *g_beta) {
+  if (!ctx || !x_u || !x_p) return NSMF_EINVAL;
+  if (!vjp && (!y_u || !y_p)) return NSMF_EINVAL;
+  if (prec < 0 || prec > 2) return ctx->fail(NSMF_EINVAL, "precision must be 0, 1 or 2");
+  if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "Jacobian apply needs a state");
+  hipStream_t s = ctx->stream;
+  const size_t esz = prec == 0 ? 8 : 4;
+  if (y_u) NSMF_TRY(ctx, launch_fill(s, y_u, 3 * ctx->n_nodes * esz / 4), "fill");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    NSMF_TRY(ctx, hipEventCreate(&e0), "event");
+    NSMF_TRY(ctx, hipEventCreate(&e1), "event");
+    NSMF_TRY(ctx, hipEventRecord(e0, s), "event");
+  }
+  GeoView<double> g64 = ctx->geo64();
+  GeoView<float> g32 = ctx->geo32();
+  const void *gv = prec == 0 ? (const void *)&g64 : (const void *)&g32;
+  const void *st = prec == 0 ? (const void *)ctx->st64.p : (const void *)ctx->st32.p;
+  const void *fst = prec == 0 ? (const void *)ctx->fst64.p : (const void *)ctx->fst32.p;
+  const void *beta = prec == 0 ? (const void *)ctx->beta64.p : (const void *)ctx->beta32.p;
+  NSMF_TRY(ctx,
+           launch_apply(ctx->P, ctx->geo, prec, vjp, s, ctx->mesh_view(), gv, ctx->tab, st, fst, beta, x_u, x_p, y_u,
+                        y_p, 1.0 / ctx->prm.n, g_logA, g_beta),
+           "apply kernel");
+  if (ctx->timing) {
+    NSMF_TRY(ctx, hipEventRecord(e1, s), "event");
+    ctx->events.emplace_back(e0, e1);
+  }
+  if (y_u) NSMF_TRY(ctx, launch_copy_masked(s, prec, ctx->mask_list.p, ctx->n_masked, x_u, y_u), "mask");
+  return NSMF_OK;
+}
+
+int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p) {
+  return apply_common(ctx, prec, false, x_u, x_p, y_u, y_p, nullptr, nullptr);
+}
+
+int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
+                      double *g_logA, double *g_beta) {
+  return apply_common(ctx, prec, true, w_u, w_p, g_u, g_p, g_logA, g_beta);
+}
+
+int nsmf_query(nsmf_ctx *ctx, int64_t *n_nodes, int64_t *n_el, int64_t *n_p, int64_t *n_dof, int64_t *n_bface) {
+  if (!ctx) return NSMF_EINVAL;
+  if (!ctx->have_mesh) return ctx->fail(NSMF_ESTATE, "no mesh uploaded");
+  if (n_nodes) *n_nodes = ctx->n_nodes;
+  if (n_el) *n_el = ctx->n_el;
+  if (n_p) *n_p = ctx->n_p;
+  if (n_dof) *n_dof = 3 * ctx->n_nodes + ctx->n_el * ctx->n_p;
+  if (n_bface) *n_bface = ctx->n_bface;
+  return NSMF_OK;
+}
+
+int nsmf_geometry_kind(nsmf_ctx *ctx) {
+  if (!ctx || !ctx->have_mesh) return NSMF_ESTATE;
+  return ctx->geo;
+}
+
+int nsmf_set_kernel_timing(nsmf_ctx *ctx, int enable) {
+  if (!ctx) return NSMF_EINVAL;
+  ctx->timing = enable != 0;
+  return NSMF_OK;
+}
+
+int nsmf_kernel_time(nsmf_ctx *ctx, double *ms_total, int64_t *launches) {
+  if (!ctx) return NSMF_EINVAL;
+  double tot = 0.0;
+  for (auto &ev : ctx->events) {
+    NSMF_TRY(ctx, hipEventSynchronize(ev.second), "event");
+    float ms = 0.0f;
+    NSMF_TRY(ctx, hipEventElapsedTime(&ms, ev.first, ev.second), "event");
+    tot += ms;
+  }
+  if (ms_total) *ms_total = tot;
+  if (launches) *launches = (int64_t)ctx->events.size();
+  for (auto &ev : ctx->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  ctx->events.clear();
+  return NSMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Internal declarations shared by the host API (nsmf_api.cpp) and the kernels (nsmf_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsmf {
+
+// Geometry kinds detected at upload.
+enum GeoKind { GEO_AFFINE = 0, GEO_COLUMN = 1 };
+
+// Node-id word of the device connectivity: bits 0..27 node id, bits 28..30 the
+// Dirichlet mask of components x, y, z of that node.
+constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;
+constexpr int MASK_SHIFT = 28;
+
+// Threads per block and elements per block for P = k+1 nodes per direction.  One
+// thread owns one line of P values of an element, so an element occupies P*P threads.
+template <int P> struct Launch;
+template <> struct Launch<3> { static constexpr int NT = 64;  static constexpr int E = 7; };
+template <> struct Launch<4> { static constexpr int NT = 64;  static constexpr int E = 4; };
+template <> struct Launch<5> { static constexpr int NT = 128; static constexpr int E = 5; };
+
+// Reference-element tables (passed by value as kernel arguments, read through the
+// scalar cache).  Indices: q = Gauss point, a = Gauss-Lobatto node.
+template <typename T, int P> struct Tab {
+  T B[P][P];        // B[q][a]  = l_a(g_q)         Lagrange basis at Gauss points
+  T D[P][P];        // D[q][a]  = l_a'(g_q)        its derivative
+  T I[2][P][P];     // I[h][i][m] = l_m(child node i of half h)  child-interval interpolation
+  T L[P - 1][P];    // L[j][q]  = sqrt((2j+1)/2) P_j(g_q)  normalised Legendre at Gauss points
+  T w[P];           // Gauss weights
+  int8_t pe[(P - 1) * P * (P + 1) / 6][3];  // pressure basis exponents (i, j, l)
+};
+
+// FP64 tables for degree k = P-1 computed on the host (Newton iterations for the nodes).
+struct HostTables {
+  int P;
+  double xi[5], g[5], w[5];
+  double B[5][5], D[5][5], I[2][5][5], L[4][5];
+  int n_p;
+  int8_t pe[20][3];
+};
+void build_tables(int k, HostTables *t);
+
+template <typename T, int P> Tab<T, P> make_tab(const HostTables &h, bool bf16_ops);
+
+// Device views used by the kernels.
+struct MeshView {
+  const uint32_t *en;        // [n_el][P^3] node word (id | mask bits)
+  const uint32_t *cmask;     // [n_el]
+  const int32_t *bface_of;   // [n_el] basal face id or -1
+  int64_t n_el, n_nodes;
+  int nblocks;
+};
+
+template <typename T> struct GeoView {
+  const T *el;     // AFFINE: [n_el][4] (1/J00, 1/J11, 1/J22, detJ); COLUMN: [n_el][2] (1/J00, 1/J11)
+  const T *qp;     // COLUMN: [nblocks][4][P][NT] (dzeta/dx, dzeta/dy, dzeta/dz, w detJ)
+  const T *face;   // [n_bface][4][P*P] (w |S|, n_x, n_y, n_z) at the face Gauss points
+};
+
+// Launchers (defined in nsmf_kernels.hip).  Return hipError_t of the launch.
+hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const HostTables &tab,
+                                const double *coords, double *el_out, double *qp_out, double *face_out,
+                                unsigned *flags);
+hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
+                        const HostTables &tab, const double *u, const double *logA, double n, double eps,
+                        double B0, double *st64, float *st32, double *fst64, float *fst32);
+hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *geo_view,
+                        const HostTables &tab, const void *state, const void *fstate, const void *beta,
+                        const void *x_u, const void *x_p, void *y_u, void *y_p, double inv_n,
+                        double *g_logA, double *g_beta);
+hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
+                           const HostTables &tab, const double *st64, const double *fst64, const double *beta,
+                           const double *p, const double *body, double *r_u, double *r_p);
+hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
+hipError_t launch_copy_masked(hipStream_t s, int prec, const int32_t *list, int64_t n, const void *x, void *y);
+hipError_t launch_residual_fixup(hipStream_t s, const uint8_t *dmask, int64_t n, const double *u, const double *f,
+                                 double *r);
+hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);
+
+}  // namespace nsmf

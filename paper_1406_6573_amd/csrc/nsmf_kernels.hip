@@ -1,0 +1,1112 @@
+// Element kernels of the matrix-free Newton-Stokes operator for gfx950.
+//
+// Work decomposition: a block of NT threads processes E elements; an element owns P*P
+// threads (P = k+1), each holding one line of P values of a 3D tensor-product field in
+// registers.  A 1D contraction along the line a thread holds runs in registers; the
+// other directions are reached by passing the field through LDS, where each thread
+// picks up a line in the next direction (Sec. 3.3: all element work reduces to
+// repeated 1D kernels, and the same 1D kernels apply the hanging-node restriction).
+//
+// Thread t of an element holds, depending on the phase,
+//   z-line  (i, j) = (t % P, t / P): points (i, j, 0..P-1)   -- gather / scatter layout
+//   y-line  (i, z) = (t % P, t / P): points (i, 0..P-1, z)
+//   x-line  (j, z) = (t % P, t / P): points (0..P-1, j, z)   -- quadrature-point layout
+// with point (x, y, z) stored at LDS offset x + P*y + P*P*z.
+//
+// Per-quadrature-point data are stored in the x-line layout of the kernel itself:
+// index ((block * F + field) * P + i) * NT + thread, so that each load of a field is one
+// contiguous NT-wide access.
+#include <hip/hip_runtime.h>
+
+#include "nsmf_internal.h"
+
+namespace nsmf {
+
+constexpr int NSTATE = 8;   // mu', kappa, Sigma_xx, Sigma_yy, Sigma_zz, Sigma_xy, Sigma_xz, Sigma_yz
+constexpr int NFACEGEO = 4; // w|S|, n_x, n_y, n_z
+constexpr int NFACEST = 3;  // w|S| T u
+
+// Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous range of
+// element groups so neighbouring elements (sharing nodes) hit the same L2.
+__device__ __forceinline__ int logical_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+  return x * q + (x < r ? x : r) + j;
+}
+
+template <int P> __device__ __forceinline__ int side_of(int a) { return a == 0 ? 0 : (a == P - 1 ? 1 : -1); }
+
+template <int P> __device__ __forceinline__ bool edge_on(uint32_t cm, int dir, int a, int b) {
+  const int s0 = side_of<P>(a), s1 = side_of<P>(b);
+  if (s0 < 0 || s1 < 0) return false;
+  return (cm >> (9 + 4 * dir + s0 + 2 * s1)) & 1u;
+}
+// Lines of the element that lie on a hanging face or edge having the line's direction
+// as a tangent direction; those are interpolated from the parent values.
+template <int P> __device__ __forceinline__ bool xline_hanging(uint32_t cm, int j, int z) {
+  const uint32_t f = cm >> 3;
+  return ((f >> 2) & 1u && j == 0) || ((f >> 3) & 1u && j == P - 1) || ((f >> 4) & 1u && z == 0) ||
+         ((f >> 5) & 1u && z == P - 1) || edge_on<P>(cm, 0, j, z);
+}
+template <int P> __device__ __forceinline__ bool yline_hanging(uint32_t cm, int i, int z) {
+  const uint32_t f = cm >> 3;
+  return ((f >> 0) & 1u && i == 0) || ((f >> 1) & 1u && i == P - 1) || ((f >> 4) & 1u && z == 0) ||
+         ((f >> 5) & 1u && z == P - 1) || edge_on<P>(cm, 1, i, z);
+}
+template <int P> __device__ __forceinline__ bool zline_hanging(uint32_t cm, int i, int j) {
+  const uint32_t f = cm >> 3;
+  return ((f >> 0) & 1u && i == 0) || ((f >> 1) & 1u && i == P - 1) || ((f >> 2) & 1u && j == 0) ||
+         ((f >> 3) & 1u && j == P - 1) || edge_on<P>(cm, 2, i, j);
+}
+
+template <typename T, int P> __device__ __forceinline__ void interp_line(const T (&I)[P][P], T *v) {
+  T o[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T a = 0;
+#pragma unroll
+    for (int m = 0; m < P; ++m) a += I[i][m] * v[m];
+    o[i] = a;
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] = o[i];
+}
+template <typename T, int P> __device__ __forceinline__ void interp_line_t(const T (&I)[P][P], T *v) {
+  T o[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    T a = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) a += I[i][m] * v[i];
+    o[m] = a;
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] = o[i];
+}
+
+// Element workspace: NB buffers of P^3 values.
+template <typename T, int P> struct Ws {
+  static constexpr int P2 = P * P, P3 = P * P * P, NB = 5;
+  T *s;
+  __device__ T *b(int k) const { return s + k * P3; }
+};
+
+// ---------------------------------------------------------------- hanging restriction R_e
+// In: v[c][z] = the values named by elem_nodes on the z-line (parent values in hanging
+// slots).  Out: R_e x on the z-line.  Interpolates along x, then y (through LDS), then z
+// (in registers), each on the flagged lines only.  All threads of the block must call.
+template <typename T, int P>
+__device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
+  constexpr int P2 = P * P;
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < P; ++z) w.b(c)[t + P2 * z] = v[c][z];
+  __syncthreads();
+  if (act) {
+    const int j = t % P, z = t / P;
+    if (xline_hanging<P>(cm, j, z)) {
+      const int h = cm & 1u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T l[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + P * t];
+        interp_line<T, P>(tb.I[h], l);
+#pragma unroll
+        for (int m = 0; m < P; ++m) w.b(c)[m + P * t] = l[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int i = t % P, z = t / P;
+    if (yline_hanging<P>(cm, i, z)) {
+      const int h = (cm >> 1) & 1u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T l[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + P2 * z];
+        interp_line<T, P>(tb.I[h], l);
+#pragma unroll
+        for (int m = 0; m < P; ++m) w.b(c)[i + P * m + P2 * z] = l[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < P; ++z) v[c][z] = w.b(c)[t + P2 * z];
+    const int i = t % P, j = t / P;
+    if (zline_hanging<P>(cm, i, j)) {
+      const int h = (cm >> 2) & 1u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) interp_line<T, P>(tb.I[h], v[c]);
+    }
+  }
+  __syncthreads();
+}
+
+// Transpose R_e^T on the z-line: z (registers), then y, then x (through LDS).
+template <typename T, int P>
+__device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
+  constexpr int P2 = P * P;
+  if (act) {
+    const int i = t % P, j = t / P;
+    if (zline_hanging<P>(cm, i, j)) {
+      const int h = (cm >> 2) & 1u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) interp_line_t<T, P>(tb.I[h], v[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < P; ++z) w.b(c)[t + P2 * z] = v[c][z];
+  }
+  __syncthreads();
+  if (act) {
+    const int i = t % P, z = t / P;
+    if (yline_hanging<P>(cm, i, z)) {
+      const int h = (cm >> 1) & 1u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T l[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + P2 * z];
+        interp_line_t<T, P>(tb.I[h], l);
+#pragma unroll
+        for (int m = 0; m < P; ++m) w.b(c)[i + P * m + P2 * z] = l[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int j = t % P, z = t / P;
+    if (xline_hanging<P>(cm, j, z)) {
+      const int h = cm & 1u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T l[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + P * t];
+        interp_line_t<T, P>(tb.I[h], l);
+#pragma unroll
+        for (int m = 0; m < P; ++m) w.b(c)[m + P * t] = l[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < P; ++z) v[c][z] = w.b(c)[t + P2 * z];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- sum-factorised gradient
+// z-line nodal values -> reference gradient at the x-line's quadrature points:
+//   gx = (D x B x B) v, gy = (B x D x B) v, gz = (B x B x D) v  (x fastest in the Kronecker order).
+// Two barriers; buffers 0..4.  All threads call.
+template <typename T, int P>
+__device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws<T, P> w, const Tab<T, P> &tb,
+                         int t, bool act) {
+  constexpr int P2 = P * P;
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      T a = 0, d = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        a += tb.B[q][m] * v[m];
+        d += tb.D[q][m] * v[m];
+      }
+      w.b(0)[t + P2 * q] = a;
+      w.b(1)[t + P2 * q] = d;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int i = t % P, z = t / P;
+    T a[P], b[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      a[m] = w.b(0)[i + P * m + P2 * z];
+      b[m] = w.b(1)[i + P * m + P2 * z];
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        s0 += tb.B[q][m] * a[m];
+        s1 += tb.D[q][m] * a[m];
+        s2 += tb.B[q][m] * b[m];
+      }
+      w.b(2)[i + P * q + P2 * z] = s0;
+      w.b(3)[i + P * q + P2 * z] = s1;
+      w.b(4)[i + P * q + P2 * z] = s2;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    T a[P], b[P], c[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      a[m] = w.b(2)[m + P * t];
+      b[m] = w.b(3)[m + P * t];
+      c[m] = w.b(4)[m + P * t];
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      T x0 = 0, x1 = 0, x2 = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        x0 += tb.D[q][m] * a[m];
+        x1 += tb.B[q][m] * b[m];
+        x2 += tb.B[q][m] * c[m];
+      }
+      gx[q] = x0;
+      gy[q] = x1;
+      gz[q] = x2;
+    }
+  }
+}
+
+// Transpose: x-line quadrature values (fx, fy, fz tested against d/dxi, d/deta, d/dzeta of
+// the basis, f0 against the basis itself) -> z-line nodal values.  Two barriers; buffers 0..4.
+template <typename T, int P, bool VALUE>
+__device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], const T (&f0)[P], T (&out)[P],
+                         Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
+  constexpr int P2 = P * P;
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      T h0 = 0, h1 = 0, h2 = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        h0 += tb.D[q][i] * fx[q];
+        if (VALUE) h0 += tb.B[q][i] * f0[q];
+        h1 += tb.B[q][i] * fy[q];
+        h2 += tb.B[q][i] * fz[q];
+      }
+      w.b(0)[i + P * t] = h0;
+      w.b(1)[i + P * t] = h1;
+      w.b(2)[i + P * t] = h2;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int i = t % P, z = t / P;
+    T a[P], b[P], c[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      a[q] = w.b(0)[i + P * q + P2 * z];
+      b[q] = w.b(1)[i + P * q + P2 * z];
+      c[q] = w.b(2)[i + P * q + P2 * z];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      T k0 = 0, k1 = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        k0 += tb.B[q][j] * a[q] + tb.D[q][j] * b[q];
+        k1 += tb.B[q][j] * c[q];
+      }
+      w.b(3)[i + P * j + P2 * z] = k0;
+      w.b(4)[i + P * j + P2 * z] = k1;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    T a[P], b[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      a[q] = w.b(3)[t + P2 * q];
+      b[q] = w.b(4)[t + P2 * q];
+    }
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      T o = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) o += tb.B[q][z] * a[q] + tb.D[q][z] * b[q];
+      out[z] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- geometry access
+template <typename T, int P, int GEO> struct QpGeo {
+  T jx, jy, jz;          // d xi/dx, d eta/dy, (affine) d zeta/dz
+  T detJ;                // affine only
+  T a[P], b[P], c[P], wd[P];   // column: d zeta/dx, d zeta/dy, d zeta/dz, w detJ (x-line)
+};
+
+template <typename T, int P, int GEO, int NT>
+__device__ __forceinline__ void load_geo(QpGeo<T, P, GEO> &g, const GeoView<T> &gv, int64_t e, int lb, int tid,
+                                         const Tab<T, P> &tb, int t) {
+  if (GEO == GEO_AFFINE) {
+    const T *p = gv.el + 4 * e;
+    g.jx = p[0]; g.jy = p[1]; g.jz = p[2]; g.detJ = p[3];
+    const int j = t % P, z = t / P;
+    const T wjz = tb.w[j] * tb.w[z] * g.detJ;
+#pragma unroll
+    for (int i = 0; i < P; ++i) g.wd[i] = tb.w[i] * wjz;
+  } else {
+    const T *p = gv.el + 2 * e;
+    g.jx = p[0]; g.jy = p[1];
+    const T *q = gv.qp + (size_t)lb * 4 * P * NT;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      g.a[i] = q[(0 * P + i) * NT + tid];
+      g.b[i] = q[(1 * P + i) * NT + tid];
+      g.c[i] = q[(2 * P + i) * NT + tid];
+      g.wd[i] = q[(3 * P + i) * NT + tid];
+    }
+  }
+}
+
+// physical gradient G[c][s] = sum_r Gref[c][r] Jinv[r][s] at x-line point i
+template <typename T, int P, int GEO>
+__device__ __forceinline__ void to_phys(const QpGeo<T, P, GEO> &g, int i, const T (&gr)[3][3], T (&G)[3][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (GEO == GEO_AFFINE) {
+      G[c][0] = gr[c][0] * g.jx;
+      G[c][1] = gr[c][1] * g.jy;
+      G[c][2] = gr[c][2] * g.jz;
+    } else {
+      G[c][0] = gr[c][0] * g.jx + gr[c][2] * g.a[i];
+      G[c][1] = gr[c][1] * g.jy + gr[c][2] * g.b[i];
+      G[c][2] = gr[c][2] * g.c[i];
+    }
+  }
+}
+// reference flux f[c][r] = sum_s tau[c][s] Jinv[r][s]
+template <typename T, int P, int GEO>
+__device__ __forceinline__ void to_ref(const QpGeo<T, P, GEO> &g, int i, const T (&tau)[3][3], T (&f)[3][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (GEO == GEO_AFFINE) {
+      f[c][0] = tau[c][0] * g.jx;
+      f[c][1] = tau[c][1] * g.jy;
+      f[c][2] = tau[c][2] * g.jz;
+    } else {
+      f[c][0] = tau[c][0] * g.jx;
+      f[c][1] = tau[c][1] * g.jy;
+      f[c][2] = tau[c][0] * g.a[i] + tau[c][1] * g.b[i] + tau[c][2] * g.c[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pressure basis
+// x-line thread (j, z): p(i) = sum_m xp[m] L_{e0}(g_i) L_{e1}(g_j) L_{e2}(g_z)
+template <typename T, int P>
+__device__ __forceinline__ void pressure_interp(const T *xp, const Tab<T, P> &tb, int t, T (&pq)[P]) {
+  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  const int j = t % P, z = t / P;
+  T pa[P - 1];
+#pragma unroll
+  for (int a = 0; a < P - 1; ++a) pa[a] = 0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) pa[tb.pe[m][0]] += xp[m] * tb.L[tb.pe[m][1]][j] * tb.L[tb.pe[m][2]][z];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int a = 0; a < P - 1; ++a) s += pa[a] * tb.L[a][i];
+    pq[i] = s;
+  }
+}
+// partial test sums: part[m] = sum_i d[i] psi_m(i, j, z) on the thread's x-line
+template <typename T, int P>
+__device__ __forceinline__ void pressure_test(const T (&d)[P], const Tab<T, P> &tb, int t,
+                                              T (&part)[(P - 1) * P * (P + 1) / 6]) {
+  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  const int j = t % P, z = t / P;
+  T qa[P - 1];
+#pragma unroll
+  for (int a = 0; a < P - 1; ++a) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) s += tb.L[a][i] * d[i];
+    qa[a] = s;
+  }
+#pragma unroll
+  for (int m = 0; m < NP; ++m) part[m] = qa[tb.pe[m][0]] * tb.L[tb.pe[m][1]][j] * tb.L[tb.pe[m][2]][z];
+}
+
+// Sum the NP partials over the P*P threads of each element and store -sum into y_p[e].
+// Uses buffers 0..4 of the element workspace; all threads call; two barriers.
+template <typename T, int P>
+__device__ void pressure_reduce(const T (&part)[(P - 1) * P * (P + 1) / 6], Ws<T, P> w, int t, bool act,
+                                T *yp_e) {
+  constexpr int NP = (P - 1) * P * (P + 1) / 6, P2 = P * P;
+  if (act)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) w.s[m * P2 + t] = part[m];
+  __syncthreads();
+  if (act && yp_e != nullptr) {
+    for (int m = t; m < NP; m += P2) {
+      T s = 0;
+      for (int r = 0; r < P2; ++r) s += w.s[m * P2 + r];
+      yp_e[m] = -s;
+    }
+  }
+  __syncthreads();
+}
+
+// double-precision sum over the P*P threads of an element (for parameter gradients)
+template <int P>
+__device__ double elem_sum64(double v, double *red, int t, bool act) {
+  constexpr int P2 = P * P;
+  if (act) red[t] = v;
+  __syncthreads();
+  double s = 0;
+  if (act && t == 0)
+    for (int r = 0; r < P2; ++r) s += red[r];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------- basal face (zeta = -1)
+// Face Gauss point (g_i, g_j) <-> thread t = i + P j (the z-line owner of nodes (i, j, .)).
+// Interpolates the bottom-node values xb[c] to the face point (B x B).
+template <typename T, int P>
+__device__ void face_interp(const T (&xb)[3], T (&uq)[3], Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
+  constexpr int P2 = P * P;
+  const int i = t % P, j = t / P;
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w.b(0)[c * P2 + t] = xb[c];
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) s += tb.B[i][a] * w.b(0)[c * P2 + a + P * j];
+      w.b(1)[c * P2 + t] = s;
+    }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < P; ++b) s += tb.B[j][b] * w.b(1)[c * P2 + i + P * b];
+      uq[c] = s;
+    }
+}
+// Transposed: face-point values tq[c] -> bottom-node contributions out[c] (B^T x B^T).
+template <typename T, int P>
+__device__ void face_test(const T (&tq)[3], T (&out)[3], Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
+  constexpr int P2 = P * P;
+  const int i = t % P, j = t / P;
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w.b(2)[c * P2 + t] = tq[c];
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int jj = 0; jj < P; ++jj) s += tb.B[jj][j] * w.b(2)[c * P2 + i + P * jj];
+      w.b(3)[c * P2 + t] = s;
+    }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int ii = 0; ii < P; ++ii) s += tb.B[ii][i] * w.b(3)[c * P2 + ii + P * j];
+      out[c] = s;
+    }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- gather / scatter
+template <typename T, int P>
+__device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t N, int t, bool act, bool use_mask,
+                                       T (&v)[3][P], uint32_t (&nw)[P]) {
+  constexpr int P2 = P * P;
+#pragma unroll
+  for (int z = 0; z < P; ++z) nw[z] = act ? en_e[t + P2 * z] : 0u;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      const uint32_t wd = nw[z];
+      const bool masked = use_mask && ((wd >> (MASK_SHIFT + c)) & 1u);
+      v[c][z] = (act && !masked) ? x[c * N + (wd & NODE_MASK)] : T(0);
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void scatter_add(const uint32_t (&nw)[P], T *y, int64_t N, bool act, const T (&v)[3][P]) {
+  if (!act || y == nullptr) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      const uint32_t wd = nw[z];
+      if (!((wd >> (MASK_SHIFT + c)) & 1u)) unsafeAtomicAdd(&y[c * N + (wd & NODE_MASK)], v[c][z]);
+    }
+}
+
+// ================================================================= kernels
+// Jacobian apply (and VJP): y = J_c x at the stored linearisation point.
+template <typename T, int P, int GEO, bool VJP>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const T *__restrict__ fst,
+        const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
+        T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  __shared__ T smem[E * 5 * P3];
+  __shared__ double red[E * P2];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = (int64_t)lb * E + el;
+  const bool act = el < E && e < m.n_el;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * 5 * P3};
+  double *redl = red + els * P2;
+  const int64_t N = m.n_nodes;
+
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  T v[3][P];
+  uint32_t nw[P];
+  gather<T, P>(m.en + e * P3, xu, N, t, act, true, v, nw);
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  const T xb[3] = {v[0][0], v[1][0], v[2][0]};
+
+  T gr[3][3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad_fwd<T, P>(v[c], gr[c][0], gr[c][1], gr[c][2], w, tb, t, act);
+  __syncthreads();
+
+  QpGeo<T, P, GEO> g;
+  T pq[P];
+  if (act) {
+    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+    T xpl[NP];
+#pragma unroll
+    for (int mm = 0; mm < NP; ++mm) xpl[mm] = xp[e * NP + mm];
+    pressure_interp<T, P>(xpl, tb, t, pq);
+  }
+  T dw[P];
+  double gA = 0.0;
+  const T *stb = st + (size_t)lb * NSTATE * P * NT;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (!act) { dw[i] = 0; continue; }
+    T grr[3][3], G[3][3], tau[3][3], f[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) grr[c][r] = gr[c][r][i];
+    to_phys<T, P, GEO>(g, i, grr, G);
+    const T mu = stb[(0 * P + i) * NT + tid];
+    const T ka = stb[(1 * P + i) * NT + tid];
+    const T sxx = stb[(2 * P + i) * NT + tid], syy = stb[(3 * P + i) * NT + tid];
+    const T szz = stb[(4 * P + i) * NT + tid], sxy = stb[(5 * P + i) * NT + tid];
+    const T sxz = stb[(6 * P + i) * NT + tid], syz = stb[(7 * P + i) * NT + tid];
+    const T dxx = G[0][0], dyy = G[1][1], dzz = G[2][2];
+    const T dxy = T(0.5) * (G[0][1] + G[1][0]), dxz = T(0.5) * (G[0][2] + G[2][0]);
+    const T dyz = T(0.5) * (G[1][2] + G[2][1]);
+    const T s = sxx * dxx + syy * dyy + szz * dzz + T(2) * (sxy * dxy + sxz * dxz + syz * dyz);
+    if (VJP) gA += (double)s;
+    const T ks = ka * s;
+    const T pw = pq[i] * g.wd[i];
+    tau[0][0] = mu * dxx - ks * sxx - pw;
+    tau[1][1] = mu * dyy - ks * syy - pw;
+    tau[2][2] = mu * dzz - ks * szz - pw;
+    tau[0][1] = tau[1][0] = mu * dxy - ks * sxy;
+    tau[0][2] = tau[2][0] = mu * dxz - ks * sxz;
+    tau[1][2] = tau[2][1] = mu * dyz - ks * syz;
+    dw[i] = (dxx + dyy + dzz) * g.wd[i];
+    to_ref<T, P, GEO>(g, i, tau, f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) gr[c][r][i] = f[c][r];
+  }
+  // pressure rows: y_p[e][m] = -sum_q w detJ psi_m div x
+  {
+    T part[NP];
+    if (act) pressure_test<T, P>(dw, tb, t, part);
+    pressure_reduce<T, P>(part, w, t, act, (act && yp != nullptr) ? yp + e * NP : nullptr);
+  }
+  if (VJP) {
+    const double sA = elem_sum64<P>(gA, redl, t, act);
+    if (act && t == 0 && g_logA != nullptr) g_logA[e] = -inv_n * sA;
+  }
+  T y[3][P];
+  const T zero[P] = {};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad_bwd<T, P, false>(gr[c][0], gr[c][1], gr[c][2], zero, y[c], w, tb, t, act);
+  // basal Robin term on the zeta = -1 face: y += int beta (T x).(T v)
+  const int fid = act ? m.bface_of[e] : -1;
+  if (__syncthreads_or(fid >= 0)) {
+    T uq[3], tq[3], out[3];
+    face_interp<T, P>(xb, uq, w, tb, t, act);
+    double gb = 0.0;
+    if (fid >= 0) {
+      const T *fg = gv.face + (size_t)fid * NFACEGEO * P2;
+      const T ws = fg[t], n0 = fg[P2 + t], n1 = fg[2 * P2 + t], n2 = fg[3 * P2 + t];
+      const T bw = beta[fid] * ws;
+      const T nu = n0 * uq[0] + n1 * uq[1] + n2 * uq[2];
+      tq[0] = bw * (uq[0] - n0 * nu);
+      tq[1] = bw * (uq[1] - n1 * nu);
+      tq[2] = bw * (uq[2] - n2 * nu);
+      if (VJP) {
+        const T *fs = fst + (size_t)fid * NFACEST * P2;
+        gb = (double)fs[t] * uq[0] + (double)fs[P2 + t] * uq[1] + (double)fs[2 * P2 + t] * uq[2];
+      }
+    } else {
+      tq[0] = tq[1] = tq[2] = 0;
+    }
+    face_test<T, P>(tq, out, w, tb, t, act);
+    if (fid >= 0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c][0] += out[c];
+    if (VJP) {
+      const double sb = elem_sum64<P>(gb, redl, t, act);
+      if (fid >= 0 && t == 0 && g_beta != nullptr) g_beta[fid] = sb;
+    }
+  }
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  scatter_add<T, P>(nw, yu, N, act, y);
+}
+
+// Linearisation point: per quadrature point mu' = w detJ mu, kappa, Sigma0 = mu' D(u)
+// (FP64, eq. (glen) and eq. (rank4)); per basal face point w|S| T u.
+template <int P, int GEO>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_state(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restrict__ u,
+        const double *__restrict__ logA, double n, double eps, double B0, double *__restrict__ st64,
+        float *__restrict__ st32, double *__restrict__ fst64, float *__restrict__ fst32) {
+  using T = double;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  __shared__ T smem[E * 5 * P3];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = (int64_t)lb * E + el;
+  const bool act = el < E && e < m.n_el;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * 5 * P3};
+  const int64_t N = m.n_nodes;
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  T v[3][P];
+  uint32_t nw[P];
+  gather<T, P>(m.en + e * P3, u, N, t, act, true, v, nw);
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  const T xb[3] = {v[0][0], v[1][0], v[2][0]};
+  T gr[3][3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad_fwd<T, P>(v[c], gr[c][0], gr[c][1], gr[c][2], w, tb, t, act);
+  __syncthreads();
+  if (act) {
+    QpGeo<T, P, GEO> g;
+    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+    const double Be = B0 * exp(-logA[e] / n);
+    const double expo = (1.0 - n) / (2.0 * n), cf = (n - 1.0) / (2.0 * n);
+    double *s64 = st64 + (size_t)lb * NSTATE * P * NT;
+    float *s32 = st32 + (size_t)lb * NSTATE * P * NT;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      T grr[3][3], G[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) grr[c][r] = gr[c][r][i];
+      to_phys<T, P, GEO>(g, i, grr, G);
+      const T dxx = G[0][0], dyy = G[1][1], dzz = G[2][2];
+      const T dxy = 0.5 * (G[0][1] + G[1][0]), dxz = 0.5 * (G[0][2] + G[2][0]), dyz = 0.5 * (G[1][2] + G[2][1]);
+      const T II = 0.5 * (dxx * dxx + dyy * dyy + dzz * dzz) + dxy * dxy + dxz * dxz + dyz * dyz;
+      const T mu = Be * pow(II + eps, expo);
+      const T mup = g.wd[i] * mu;
+      const T ka = cf / ((II + eps) * mup);
+      const T vals[NSTATE] = {mup, ka, mup * dxx, mup * dyy, mup * dzz, mup * dxy, mup * dxz, mup * dyz};
+#pragma unroll
+      for (int f = 0; f < NSTATE; ++f) {
+        s64[(f * P + i) * NT + tid] = vals[f];
+        s32[(f * P + i) * NT + tid] = (float)vals[f];
+      }
+    }
+  }
+  const int fid = act ? m.bface_of[e] : -1;
+  if (__syncthreads_or(fid >= 0)) {
+    T uq[3];
+    face_interp<T, P>(xb, uq, w, tb, t, act);
+    if (fid >= 0) {
+      const T *fg = gv.face + (size_t)fid * NFACEGEO * P2;
+      const T ws = fg[t], n0 = fg[P2 + t], n1 = fg[2 * P2 + t], n2 = fg[3 * P2 + t];
+      const T nu = n0 * uq[0] + n1 * uq[1] + n2 * uq[2];
+      const T b[3] = {ws * (uq[0] - n0 * nu), ws * (uq[1] - n1 * nu), ws * (uq[2] - n2 * nu)};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fst64[(size_t)fid * NFACEST * P2 + c * P2 + t] = b[c];
+        fst32[(size_t)fid * NFACEST * P2 + c * P2 + t] = (float)b[c];
+      }
+    }
+  }
+}
+
+// Residual at the linearisation point (FP64): tau = Sigma0 - p w detJ I, body force,
+// basal term beta w|S| T u, pressure rows -int psi div u.
+template <int P, int GEO>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restrict__ st,
+           const double *__restrict__ fst, const double *__restrict__ beta, const double *__restrict__ p, double bx,
+           double by, double bz, double *__restrict__ ru, double *__restrict__ rp) {
+  using T = double;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  __shared__ T smem[E * 5 * P3];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = (int64_t)lb * E + el;
+  const bool act = el < E && e < m.n_el;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * 5 * P3};
+  const int64_t N = m.n_nodes;
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  uint32_t nw[P];
+#pragma unroll
+  for (int z = 0; z < P; ++z) nw[z] = act ? m.en[e * P3 + t + P2 * z] : 0u;
+
+  T fr[3][3][P], f0[3][P], dw[P];
+  if (act) {
+    QpGeo<T, P, GEO> g;
+    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+    T pq[P], xpl[NP];
+#pragma unroll
+    for (int mm = 0; mm < NP; ++mm) xpl[mm] = p[e * NP + mm];
+    pressure_interp<T, P>(xpl, tb, t, pq);
+    const T *stb = st + (size_t)lb * NSTATE * P * NT;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const T mu = stb[(0 * P + i) * NT + tid];
+      const T sxx = stb[(2 * P + i) * NT + tid], syy = stb[(3 * P + i) * NT + tid];
+      const T szz = stb[(4 * P + i) * NT + tid], sxy = stb[(5 * P + i) * NT + tid];
+      const T sxz = stb[(6 * P + i) * NT + tid], syz = stb[(7 * P + i) * NT + tid];
+      const T pw = pq[i] * g.wd[i];
+      T tau[3][3] = {{sxx - pw, sxy, sxz}, {sxy, syy - pw, syz}, {sxz, syz, szz - pw}};
+      T f[3][3];
+      to_ref<T, P, GEO>(g, i, tau, f);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fr[c][r][i] = f[c][r];
+      f0[0][i] = -bx * g.wd[i];
+      f0[1][i] = -by * g.wd[i];
+      f0[2][i] = -bz * g.wd[i];
+      dw[i] = (sxx + syy + szz) / mu * g.wd[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      dw[i] = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        f0[c][i] = 0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fr[c][r][i] = 0;
+      }
+    }
+  }
+  {
+    T part[NP];
+    if (act) pressure_test<T, P>(dw, tb, t, part);
+    pressure_reduce<T, P>(part, w, t, act, act ? rp + e * NP : nullptr);
+  }
+  T y[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad_bwd<T, P, true>(fr[c][0], fr[c][1], fr[c][2], f0[c], y[c], w, tb, t, act);
+  const int fid = act ? m.bface_of[e] : -1;
+  if (__syncthreads_or(fid >= 0)) {
+    T tq[3] = {0, 0, 0}, out[3];
+    if (fid >= 0) {
+      const T *fs = fst + (size_t)fid * NFACEST * P2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tq[c] = beta[fid] * fs[c * P2 + t];
+    }
+    face_test<T, P>(tq, out, w, tb, t, act);
+    if (fid >= 0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c][0] += out[c];
+  }
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  scatter_add<T, P>(nw, ru, N, act, y);
+}
+
+// Geometry at upload (FP64).  mode 0: classify (flags bit0 not column-mapped, bit1 not
+// affine, bit2 det J <= 0 or not finite, bit3 degenerate basal face).  mode 1: store
+// affine data.  mode 2: store column data.  Face data are stored in modes 1 and 2.
+template <int P>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode, double *__restrict__ el_out,
+           double *__restrict__ qp_out, double *__restrict__ face_out, unsigned *__restrict__ flags) {
+  using T = double;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  __shared__ T smem[E * 5 * P3];
+  __shared__ T ref0[E][3];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = (int64_t)lb * E + el;
+  const bool act = el < E && e < m.n_el;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * 5 * P3};
+  const int64_t N = m.n_nodes;
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  T v[3][P];
+  uint32_t nw[P];
+  gather<T, P>(m.en + e * P3, X, N, t, act, false, v, nw);
+  // work with coordinates relative to the first gathered node: derivatives are unchanged,
+  // and neither the hanging interpolation nor the differentiation sees large absolute
+  // coordinates (whose rounding would otherwise dominate the Jacobian of distant elements)
+  if (act && t == 0)
+    for (int c = 0; c < 3; ++c) ref0[els][c] = v[c][0];
+  __syncthreads();
+  if (act)
+    for (int c = 0; c < 3; ++c)
+      for (int z = 0; z < P; ++z) v[c][z] -= ref0[els][c];
+  __syncthreads();
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  const T xb[3] = {v[0][0], v[1][0], v[2][0]};
+  T J[3][3][P];   // J[i][r] = d x_i / d xi_r
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad_fwd<T, P>(v[c], J[c][0], J[c][1], J[c][2], w, tb, t, act);
+  if (act && t == 0) {
+    ref0[els][0] = J[0][0][0];
+    ref0[els][1] = J[1][1][0];
+    ref0[els][2] = J[2][2][0];
+  }
+  __syncthreads();
+  unsigned fl = 0;
+  if (act) {
+    const T r00 = ref0[els][0], r11 = ref0[els][1], r22 = ref0[els][2];
+    const int j = t % P, z = t / P;
+    for (int i = 0; i < P; ++i) {
+      T a[3][3];
+      for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) a[c][r] = J[c][r][i];
+      const T det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                    a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                    a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+      const T sc = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]);
+      const T tol = 1e-13 * sc;
+      if (!(det > 0) || !isfinite(det)) fl |= 4u;
+      if (fabs(a[0][1]) > tol || fabs(a[0][2]) > tol || fabs(a[1][0]) > tol || fabs(a[1][2]) > tol ||
+          fabs(a[0][0] - r00) > tol || fabs(a[1][1] - r11) > tol)
+        fl |= 1u;
+      if (fabs(a[2][0]) > tol || fabs(a[2][1]) > tol || fabs(a[2][2] - r22) > tol) fl |= 2u;
+      if (mode == 2) {
+        T *q = qp_out + (size_t)lb * 4 * P * NT;
+        const T j00 = a[0][0], j11 = a[1][1], j22 = a[2][2];
+        q[(0 * P + i) * NT + tid] = -a[2][0] / (j00 * j22);
+        q[(1 * P + i) * NT + tid] = -a[2][1] / (j11 * j22);
+        q[(2 * P + i) * NT + tid] = 1.0 / j22;
+        q[(3 * P + i) * NT + tid] = tb.w[i] * tb.w[j] * tb.w[z] * j00 * j11 * j22;
+      }
+    }
+    if (t == 0 && mode == 1) {
+      el_out[4 * e + 0] = 1.0 / r00;
+      el_out[4 * e + 1] = 1.0 / r11;
+      el_out[4 * e + 2] = 1.0 / r22;
+      el_out[4 * e + 3] = r00 * r11 * r22;
+    }
+    if (t == 0 && mode == 2) {
+      el_out[2 * e + 0] = 1.0 / r00;
+      el_out[2 * e + 1] = 1.0 / r11;
+    }
+  }
+  const int fid = act ? m.bface_of[e] : -1;
+  if (__syncthreads_or(fid >= 0)) {
+    // tangents at face Gauss points: x_xi = (D x B) X, x_eta = (B x D) X over the bottom nodes
+    const int i = t % P, j = t / P;
+    if (act)
+      for (int c = 0; c < 3; ++c) w.b(0)[c * P2 + t] = xb[c];
+    __syncthreads();
+    if (act)
+      for (int c = 0; c < 3; ++c) {
+        T sd = 0, sb = 0;
+        for (int a = 0; a < P; ++a) {
+          sd += tb.D[i][a] * w.b(0)[c * P2 + a + P * j];
+          sb += tb.B[i][a] * w.b(0)[c * P2 + a + P * j];
+        }
+        w.b(1)[c * P2 + t] = sd;
+        w.b(2)[c * P2 + t] = sb;
+      }
+    __syncthreads();
+    if (fid >= 0) {
+      T xa[3], xe[3];
+      for (int c = 0; c < 3; ++c) {
+        T s1 = 0, s2 = 0;
+        for (int b = 0; b < P; ++b) {
+          s1 += tb.B[j][b] * w.b(1)[c * P2 + i + P * b];
+          s2 += tb.D[j][b] * w.b(2)[c * P2 + i + P * b];
+        }
+        xa[c] = s1;
+        xe[c] = s2;
+      }
+      const T cr[3] = {xa[1] * xe[2] - xa[2] * xe[1], xa[2] * xe[0] - xa[0] * xe[2], xa[0] * xe[1] - xa[1] * xe[0]};
+      const T area = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      if (!(area > 0) || !isfinite(area)) fl |= 8u;
+      if (mode > 0) {
+        T *fo = face_out + (size_t)fid * NFACEGEO * P2;
+        fo[t] = tb.w[i] * tb.w[j] * area;
+        fo[P2 + t] = cr[0] / area;
+        fo[2 * P2 + t] = cr[1] / area;
+        fo[3 * P2 + t] = cr[2] / area;
+      }
+    }
+  }
+  if (mode == 0 && fl) atomicOr(flags, fl);
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_fill(uint32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+template <typename T>
+__global__ void k_copy_masked(const int32_t *list, int64_t n, const T *x, T *y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[list[i]] = x[list[i]];
+}
+__global__ void k_residual_fixup(const uint8_t *dm, int64_t n, const double *u, const double *f, double *r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = dm[i] ? u[i] : (f ? r[i] - f[i] : r[i]);
+}
+__global__ void k_d2f(const double *in, float *out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+static inline int grid1(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
+
+hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  int nb = grid1(n, 256);
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, (uint32_t *)ptr, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy_masked(hipStream_t s, int prec, const int32_t *list, int64_t n, const void *x, void *y) {
+  if (n <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_copy_masked<double>, dim3(grid1(n, 256)), dim3(256), 0, s, list, n, (const double *)x,
+                       (double *)y);
+  else
+    hipLaunchKernelGGL(k_copy_masked<float>, dim3(grid1(n, 256)), dim3(256), 0, s, list, n, (const float *)x,
+                       (float *)y);
+  return hipGetLastError();
+}
+hipError_t launch_residual_fixup(hipStream_t s, const uint8_t *dm, int64_t n, const double *u, const double *f,
+                                 double *r) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual_fixup, dim3(grid1(n, 256)), dim3(256), 0, s, dm, n, u, f, r);
+  return hipGetLastError();
+}
+hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_d2f, dim3(grid1(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dispatch
+template <int P>
+static hipError_t geometry_p(int mode, hipStream_t s, const MeshView &m, const HostTables &h, const double *X,
+                             double *el, double *qp, double *face, unsigned *flags) {
+  auto tb = make_tab<double, P>(h, false);
+  hipLaunchKernelGGL((k_geometry<P>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, tb, X, mode, el, qp, face,
+                     flags);
+  return hipGetLastError();
+}
+hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const HostTables &h,
+                                const double *X, double *el, double *qp, double *face, unsigned *flags) {
+  switch (P) {
+    case 3: return geometry_p<3>(mode, s, m, h, X, el, qp, face, flags);
+    case 4: return geometry_p<4>(mode, s, m, h, X, el, qp, face, flags);
+    case 5: return geometry_p<5>(mode, s, m, h, X, el, qp, face, flags);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P, int GEO>
+static hipError_t state_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+                           const double *u, const double *logA, double n, double eps, double B0, double *st64,
+                           float *st32, double *fst64, float *fst32) {
+  auto tb = make_tab<double, P>(h, false);
+  hipLaunchKernelGGL((k_state<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, tb, u, logA, n, eps, B0,
+                     st64, st32, fst64, fst32);
+  return hipGetLastError();
+}
+hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
+                        const HostTables &h, const double *u, const double *logA, double n, double eps, double B0,
+                        double *st64, float *st32, double *fst64, float *fst32) {
+#define NSMF_ST(PP, GG) \
+  if (P == PP && geo == GG) return state_pg<PP, GG>(s, m, g, h, u, logA, n, eps, B0, st64, st32, fst64, fst32);
+  NSMF_ST(3, GEO_AFFINE) NSMF_ST(3, GEO_COLUMN) NSMF_ST(4, GEO_AFFINE) NSMF_ST(4, GEO_COLUMN)
+  NSMF_ST(5, GEO_AFFINE) NSMF_ST(5, GEO_COLUMN)
+#undef NSMF_ST
+  return hipErrorInvalidValue;
+}
+
+template <int P, int GEO>
+static hipError_t residual_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+                              const double *st, const double *fst, const double *beta, const double *p,
+                              const double *body, double *ru, double *rp) {
+  auto tb = make_tab<double, P>(h, false);
+  hipLaunchKernelGGL((k_residual<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, tb, st, fst, beta, p,
+                     body[0], body[1], body[2], ru, rp);
+  return hipGetLastError();
+}
+hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
+                           const HostTables &h, const double *st, const double *fst, const double *beta,
+                           const double *p, const double *body, double *ru, double *rp) {
+#define NSMF_RS(PP, GG) \
+  if (P == PP && geo == GG) return residual_pg<PP, GG>(s, m, g, h, st, fst, beta, p, body, ru, rp);
+  NSMF_RS(3, GEO_AFFINE) NSMF_RS(3, GEO_COLUMN) NSMF_RS(4, GEO_AFFINE) NSMF_RS(4, GEO_COLUMN)
+  NSMF_RS(5, GEO_AFFINE) NSMF_RS(5, GEO_COLUMN)
+#undef NSMF_RS
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P, int GEO, bool VJP>
+static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, const HostTables &h, bool bf16,
+                          const void *st, const void *fst, const void *beta, const void *xu, const void *xp, void *yu,
+                          void *yp, double inv_n, double *gA, double *gB) {
+  auto tb = make_tab<T, P>(h, bf16);
+  hipLaunchKernelGGL((k_apply<T, P, GEO, VJP>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m,
+                     *(const GeoView<T> *)gview, tb, (const T *)st, (const T *)fst, (const T *)beta, (const T *)xu,
+                     (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
+  return hipGetLastError();
+}
+hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *gview,
+                        const HostTables &h, const void *st, const void *fst, const void *beta, const void *xu,
+                        const void *xp, void *yu, void *yp, double inv_n, double *gA, double *gB) {
+  const bool bf = prec == 2;
+#define NSMF_AP(TT, PP, GG, VV)                                                                                   \
+  if (P == PP && geo == GG && vjp == VV && (sizeof(TT) == 8) == (prec == 0))                                     \
+    return apply_t<TT, PP, GG, VV>(s, m, gview, h, bf, st, fst, beta, xu, xp, yu, yp, inv_n, gA, gB);
+#define NSMF_AP2(TT, PP) \
+  NSMF_AP(TT, PP, GEO_AFFINE, false) NSMF_AP(TT, PP, GEO_COLUMN, false) NSMF_AP(TT, PP, GEO_AFFINE, true) \
+  NSMF_AP(TT, PP, GEO_COLUMN, true)
+  NSMF_AP2(double, 3) NSMF_AP2(double, 4) NSMF_AP2(double, 5) NSMF_AP2(float, 3) NSMF_AP2(float, 4)
+  NSMF_AP2(float, 5)
+#undef NSMF_AP2
+#undef NSMF_AP
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nsmf

@@ -1,0 +1,218 @@
+"""ctypes binding of the C ABI in include/nsmf.h.
+
+Argument marshalling only: every step of the operator runs in the HIP library.
+Device vectors are torch tensors on the engine's GPU; the engine enqueues its
+work on torch's current stream of that device.  If the shared library has not
+been built, loading fails loudly (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libnsmf.so")
+
+FP64, FP32, FP32_BF16OPS = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16ops": FP32_BF16OPS}
+
+STATUS = {0: "NSMF_OK", -1: "NSMF_EINVAL", -2: "NSMF_EHIP", -3: "NSMF_EMESH", -4: "NSMF_ESTATE",
+          -5: "NSMF_EUNSUP", -6: "NSMF_ENOMEM"}
+
+EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh", "nsmf_set_params",
+            "nsmf_set_state", "nsmf_residual", "nsmf_jacobian_apply", "nsmf_residual_vjp", "nsmf_query",
+            "nsmf_geometry_kind", "nsmf_set_kernel_timing", "nsmf_kernel_time", "nsmf_last_error",
+            "nsmf_version"]
+
+
+class NsmfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n_el", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("n_bface", ctypes.c_int64), ("elem_nodes", ctypes.c_void_p), ("cmask", ctypes.c_void_p),
+                ("coords", ctypes.c_void_p), ("bface_elem", ctypes.c_void_p), ("dmask", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_double), ("eps", ctypes.c_double), ("B0", ctypes.c_double),
+                ("body", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP engine library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    lib.nsmf_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.nsmf_destroy.argtypes = [vp]
+    lib.nsmf_destroy.restype = None
+    lib.nsmf_set_stream.argtypes = [vp, vp]
+    lib.nsmf_upload_mesh.argtypes = [vp, ctypes.POINTER(_Mesh)]
+    lib.nsmf_set_params.argtypes = [vp, ctypes.POINTER(_Params), vp, vp]
+    lib.nsmf_set_state.argtypes = [vp, vp, vp]
+    lib.nsmf_residual.argtypes = [vp, vp, vp, vp]
+    lib.nsmf_jacobian_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.nsmf_residual_vjp.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    lib.nsmf_query.argtypes = [vp, i64p, i64p, i64p, i64p, i64p]
+    lib.nsmf_geometry_kind.argtypes = [vp]
+    lib.nsmf_set_kernel_timing.argtypes = [vp, ctypes.c_int]
+    lib.nsmf_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
+    lib.nsmf_last_error.argtypes = [vp]
+    lib.nsmf_last_error.restype = ctypes.c_char_p
+    lib.nsmf_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Engine:
+    """One engine context on one GPU (default: torch's current device)."""
+
+    def __init__(self, device: Optional[int] = None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.nsmf_create(ctypes.byref(h), self.device), None)
+        self.h = h
+        self.dev = torch.device("cuda", self.device)
+        self.sync_stream()
+        self.k = None
+
+    # -------------------------------------------------------------- plumbing
+    def _check(self, rc: int, h=-1):
+        if rc != 0:
+            msg = self.lib.nsmf_last_error(self.h if h == -1 else h)
+            raise NsmfError(rc, msg.decode() if msg else "")
+
+    def sync_stream(self):
+        """Enqueue subsequent work on torch's current stream of the engine's device."""
+        s = self.torch.cuda.current_stream(self.dev).cuda_stream
+        self._check(self.lib.nsmf_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.nsmf_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t, shape, dtype, name):
+        if not (t.is_cuda and t.device.index == self.device):
+            raise ValueError(f"{name} must be a CUDA tensor on device {self.device}")
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous {dtype} of shape {tuple(shape)}")
+        return t
+
+    # -------------------------------------------------------------- API
+    def upload_mesh(self, mesh):
+        """Copy a mesh (any object with k, elem_nodes, cmask, coords, bface_elem, dmask arrays)."""
+        en = np.ascontiguousarray(mesh.elem_nodes, dtype=np.int32)
+        cm = np.ascontiguousarray(mesh.cmask, dtype=np.uint32)
+        X = np.ascontiguousarray(mesh.coords, dtype=np.float64)
+        bf = np.ascontiguousarray(mesh.bface_elem, dtype=np.int32)
+        dm = None if mesh.dmask is None else np.ascontiguousarray(mesh.dmask, dtype=np.uint8)
+        s = _Mesh(int(mesh.k), en.shape[0], X.shape[1], bf.shape[0], en.ctypes.data, cm.ctypes.data,
+                  X.ctypes.data, bf.ctypes.data if bf.size else None, None if dm is None else dm.ctypes.data)
+        self._check(self.lib.nsmf_upload_mesh(self.h, ctypes.byref(s)))
+        self.k = int(mesh.k)
+        self.sizes = self.query()
+
+    def query(self):
+        vals = [ctypes.c_int64() for _ in range(5)]
+        self._check(self.lib.nsmf_query(self.h, *[ctypes.byref(v) for v in vals]))
+        n_nodes, n_el, n_p, n_dof, n_bface = (v.value for v in vals)
+        return dict(n_nodes=n_nodes, n_el=n_el, n_p=n_p, n_dof=n_dof, n_bface=n_bface)
+
+    def geometry_kind(self) -> str:
+        kind = self.lib.nsmf_geometry_kind(self.h)
+        if kind < 0:
+            self._check(kind)
+        return {0: "affine", 1: "column"}[kind]
+
+    def set_params(self, n=3.0, eps=1e-10, B0=0.5, body=(0.0, 0.0, 0.0), logA=None, beta=None):
+        torch = self.torch
+        sz = self.sizes
+        if logA is not None:
+            logA = self._vec(logA, (sz["n_el"],), torch.float64, "logA")
+        if beta is not None:
+            beta = self._vec(beta, (sz["n_bface"],), torch.float64, "beta")
+        prm = _Params(float(n), float(eps), float(B0), (ctypes.c_double * 3)(*[float(b) for b in body]))
+        self._check(self.lib.nsmf_set_params(self.h, ctypes.byref(prm), _ptr(logA), _ptr(beta)))
+
+    def set_state(self, u, p):
+        torch = self.torch
+        sz = self.sizes
+        u = self._vec(u, (3, sz["n_nodes"]), torch.float64, "u")
+        p = self._vec(p, (sz["n_el"], sz["n_p"]), torch.float64, "p")
+        self._check(self.lib.nsmf_set_state(self.h, _ptr(u), _ptr(p)))
+
+    def residual(self, f_u=None, out=None):
+        torch = self.torch
+        sz = self.sizes
+        if f_u is not None:
+            f_u = self._vec(f_u, (3, sz["n_nodes"]), torch.float64, "f_u")
+        if out is None:
+            out = (torch.empty((3, sz["n_nodes"]), dtype=torch.float64, device=self.dev),
+                   torch.empty((sz["n_el"], sz["n_p"]), dtype=torch.float64, device=self.dev))
+        self._check(self.lib.nsmf_residual(self.h, _ptr(f_u), _ptr(out[0]), _ptr(out[1])))
+        return out
+
+    def _dtype(self, prec):
+        return self.torch.float64 if prec == FP64 else self.torch.float32
+
+    def jacobian_apply(self, x_u, x_p, prec="fp64", out=None):
+        prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        dt = self._dtype(prec)
+        sz = self.sizes
+        x_u = self._vec(x_u, (3, sz["n_nodes"]), dt, "x_u")
+        x_p = self._vec(x_p, (sz["n_el"], sz["n_p"]), dt, "x_p")
+        if out is None:
+            out = (self.torch.empty_like(x_u), self.torch.empty_like(x_p))
+        self._check(self.lib.nsmf_jacobian_apply(self.h, prec, _ptr(x_u), _ptr(x_p), _ptr(out[0]), _ptr(out[1])))
+        return out
+
+    def residual_vjp(self, w_u, w_p, prec="fp64", want=("u", "p", "logA", "beta")):
+        torch = self.torch
+        prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        dt = self._dtype(prec)
+        sz = self.sizes
+        w_u = self._vec(w_u, (3, sz["n_nodes"]), dt, "w_u")
+        w_p = self._vec(w_p, (sz["n_el"], sz["n_p"]), dt, "w_p")
+        g_u = torch.empty_like(w_u) if "u" in want else None
+        g_p = torch.empty_like(w_p) if "p" in want else None
+        g_A = torch.empty(sz["n_el"], dtype=torch.float64, device=self.dev) if "logA" in want else None
+        g_b = torch.empty(sz["n_bface"], dtype=torch.float64, device=self.dev) if "beta" in want else None
+        self._check(self.lib.nsmf_residual_vjp(self.h, prec, _ptr(w_u), _ptr(w_p), _ptr(g_u), _ptr(g_p),
+                                               _ptr(g_A), _ptr(g_b)))
+        return g_u, g_p, g_A, g_b
+
+    def set_kernel_timing(self, enable: bool):
+        self._check(self.lib.nsmf_set_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.nsmf_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

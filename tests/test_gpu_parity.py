@@ -1,0 +1,168 @@
+"""GPU parity of the HIP engine (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances:
+* FP64 path: relative 2-norm error <= 1e-12 (the stated target) and, per entry,
+  |y - y_ref| <= 1e-12 (|K||x|)_i.  Both sides generate their 1D tables independently
+  (nodes within 1 ulp, derivative tables within ~10 ulp); the sum-factorised chain
+  multiplies up to six such factors whose magnitudes (|D| up to ~k^2) exceed the
+  assembled |K| entries, so table differences alone reach ~1e-13 per entry at k = 4.
+* FP32 path: per entry |y - y_ref| <= 64 u32 (|K||x|)_i with u32 = 2^-24: rounding of
+  x, the state and the geometry (one rounding each) plus the arithmetic depth of the
+  sum-factorised chain (3 sweeps, the quadrature-point step, 3 transposed sweeps, hanging
+  interpolation both ways, atomic accumulation over <= 8 elements: fewer than 64 roundings).
+* BF16-operator trial: the 1D operators carry a relative rounding of 2^-9 each, six of
+  them in a chain: per entry <= 16 * 2^-9 (|K||x|)_i.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import rel_err, scaled_err, small_case
+from oracle import StokesOracle
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+TOL64_REL, TOL64_SC = 1e-12, 1e-12
+TOL32_SC = 64 * U32
+TOLBF_SC = 16 * 2.0 ** -9
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def engine_for(torch, case):
+    from paper_1406_6573_amd import Engine
+    m = case["mesh"]
+    eng = Engine()
+    eng.upload_mesh(m)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    eng.set_params(case["n"], case["eps"], case["B0"], case.get("body", (0, 0, 0)), t(case["logA"]), t(case["beta"]))
+    eng.set_state(t(case["u"]), t(case["p"]))
+    return eng, t
+
+
+def oracle_for(case):
+    m = case["mesh"]
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=case.get("body", (0, 0, 0)))
+    o.set_state(case["u"], case["p"])
+    return o
+
+
+def flat(yu, yp):
+    return np.concatenate([np.ravel(yu), np.ravel(yp)])
+
+
+def check_case(torch, case, label):
+    print(f"[gpu] {label}: n_el={case['mesh'].n_el} n_dof={case['mesh'].n_dof}", flush=True)
+    eng, t = engine_for(torch, case)
+    o = oracle_for(case)
+    K = o.jacobian()
+    absK = abs(K)
+    # residual
+    ru, rp = eng.residual()
+    oru, orp = o.residual()
+    e = rel_err(flat(ru.cpu().numpy(), rp.cpu().numpy()), flat(oru, orp))
+    print(f"  residual rel {e:.2e}", flush=True)
+    assert e < TOL64_REL
+    # Jacobian apply, all precisions
+    for (xu, xp) in case["dirs"]:
+        x = flat(xu, xp)
+        yref = K @ x
+        scale = absK @ np.abs(x)
+        yu, yp = eng.jacobian_apply(t(xu), t(xp), "fp64")
+        y = flat(yu.cpu().numpy(), yp.cpu().numpy())
+        e_rel, e_sc = rel_err(y, yref), scaled_err(y, yref, scale)
+        print(f"  J fp64 rel {e_rel:.2e} scaled {e_sc:.2e}", flush=True)
+        assert e_rel < TOL64_REL and e_sc < TOL64_SC
+        x32u, x32p = t(xu).float(), t(xp).float()
+        for prec, tol in (("fp32", TOL32_SC), ("bf16ops", TOLBF_SC)):
+            yu, yp = eng.jacobian_apply(x32u, x32p, prec)
+            y = flat(yu.double().cpu().numpy(), yp.double().cpu().numpy())
+            e_sc = scaled_err(y, yref, scale)
+            print(f"  J {prec} rel {rel_err(y, yref):.2e} scaled {e_sc:.2e}", flush=True)
+            assert e_sc < tol
+    # VJP
+    wu, wp = case["dirs"][0]
+    g_u, g_p, g_A, g_b = eng.residual_vjp(t(wu), t(wp), "fp64")
+    og_u, og_p, og_A, og_b = o.vjp(wu, wp)
+    e1 = rel_err(flat(g_u.cpu().numpy(), g_p.cpu().numpy()), flat(og_u, og_p))
+    e2 = rel_err(g_A.cpu().numpy(), og_A)
+    e3 = rel_err(g_b.cpu().numpy(), og_b) if case["mesh"].n_bface else 0.0
+    print(f"  VJP rel u,p {e1:.2e} logA {e2:.2e} beta {e3:.2e}", flush=True)
+    assert e1 < TOL64_REL and e2 < TOL64_REL and e3 < TOL64_REL
+    g_u32, g_p32, g_A32, g_b32 = eng.residual_vjp(t(wu).float(), t(wp).float(), "fp32")
+    e4 = rel_err(g_A32.cpu().numpy(), og_A)
+    print(f"  VJP fp32 logA rel {e4:.2e}", flush=True)
+    assert e4 < 1e-4
+    eng.close()
+
+
+def test_config1(torch_cuda):
+    from meshgen import make_config
+    w = make_config(1)
+    case = dict(mesh=w.mesh, n=w.n, eps=w.eps, B0=w.B0, logA=w.logA, beta=w.beta, u=w.u, p=w.p, dirs=w.directions)
+    check_case(torch_cuda, case, "config1 8x8x2 Q2xP1")
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("mapped", [False, True])
+def test_hanging_small(torch_cuda, k, mapped):
+    case = small_case(k, mapped=mapped, body=(0.0, 0.1, -1.0) if mapped else (0.0, 0.0, 0.0))
+    check_case(torch_cuda, case, f"hanging k={k} mapped={mapped}")
+
+
+def test_rigid_modes_gpu(torch_cuda):
+    torch = torch_cuda
+    case = small_case(3, mapped=True, mask=False)
+    case["beta"] = np.zeros_like(case["beta"])
+    eng, t = engine_for(torch, case)
+    m = case["mesh"]
+    xr = np.array([0.3, -0.2, 0.5])[:, None] + np.cross(np.array([0.7, 0.1, -0.4]), m.coords.T).T
+    o = oracle_for(case)
+    K = o.jacobian()
+    x = flat(xr, np.zeros((m.n_el, m.n_p)))
+    scale = abs(K) @ np.abs(x)
+    yu, yp = eng.jacobian_apply(t(xr), torch.zeros((m.n_el, m.n_p), dtype=torch.float64, device="cuda"))
+    y = flat(yu.cpu().numpy(), yp.cpu().numpy())
+    assert np.max(np.abs(y) / scale) < 1e-12
+    eng.close()
+
+
+def test_dense_transpose_4x4x2(torch_cuda):
+    """VJP equals the assembled Jacobian transpose applied to w on the 4x4x2 Q3 sub-mesh."""
+    from meshgen import make_config
+    torch = torch_cuda
+    w = make_config(4, nx=4, ny=4, nz=2, frac_refined=0.0)
+    case = dict(mesh=w.mesh, n=w.n, eps=w.eps, B0=w.B0, logA=w.logA, beta=w.beta, u=w.u, p=w.p)
+    eng, t = engine_for(torch, case)
+    o = oracle_for(case)
+    Kd = o.jacobian().toarray()
+    assert Kd.shape == (3869, 3869)
+    wu, wp = w.adjoint
+    g_u, g_p, _, _ = eng.residual_vjp(t(wu), t(wp), "fp64")
+    ref = Kd.T @ flat(wu, wp)
+    assert rel_err(flat(g_u.cpu().numpy(), g_p.cpu().numpy()), ref) < TOL64_REL
+    eng.close()
+
+
+def test_symmetry_full_config2(torch_cuda):
+    """<v, J w> = <w, J v> on the full 64x64x8 workload (any-size property)."""
+    from meshgen import make_config
+    torch = torch_cuda
+    w = make_config(2, n_dirs=2)
+    case = dict(mesh=w.mesh, n=w.n, eps=w.eps, B0=w.B0, logA=w.logA, beta=w.beta, u=w.u, p=w.p)
+    eng, t = engine_for(torch, case)
+    (vu, vp), (wu, wp) = w.directions
+    Jvu, Jvp = eng.jacobian_apply(t(vu), t(vp))
+    Jwu, Jwp = eng.jacobian_apply(t(wu), t(wp))
+    a = float((t(wu) * Jvu).sum() + (t(wp) * Jvp).sum())
+    b = float((t(vu) * Jwu).sum() + (t(vp) * Jwp).sum())
+    mag = float((t(wu).abs() * Jvu.abs()).sum() + (t(wp).abs() * Jvp.abs()).sum())
+    print(f"[gpu] symmetry config2: {a:.6e} {b:.6e} rel {abs(a - b) / mag:.2e}", flush=True)
+    assert abs(a - b) < 1e-12 * mag
+    eng.close()
