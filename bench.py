@@ -40,6 +40,23 @@ def algorithmic_bytes(sz, geo_kind, word):
     return word * (8 * nq + 2 * nvec + geo + face)
 
 
+def measured_traffic(config_id):
+    """HBM bytes per apply from the committed counter summary, if it was taken with the current
+    kernel sources (otherwise None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "apply_slab64x64x8_q3_traffic.json")
+    if config_id != 2 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    f = rec["fp32_apply"]
+    return 1e6 * (f["k_apply_read_MB"] + f["k_apply_write_MB"] + f["k_assemble_read_MB"] + f["k_assemble_write_MB"])
+
+
 def cpu_baseline(seed=0):
     """The FP64 oracle as it stands: assemble the Jacobian and apply it once, on a reduced
     sample of the same workload (12x12x2 columns, same element shape, 20% refined)."""
@@ -73,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB on the device (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is "
@@ -83,6 +102,12 @@ def main():
     from meshgen import make_config
     from paper_1406_6573_amd import Engine
 
+    if args.calibration_copy_mib > 0:
+        src = torch.ones(args.calibration_copy_mib * 2 ** 18, dtype=torch.float32, device="cuda:0")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done ({float(dst[0])})", file=sys.stderr)
+        del src, dst
     print(f"[bench] building workload config{args.config}", file=sys.stderr, flush=True)
     w = make_config(args.config, n_dirs=1) if args.config != 5 else make_config(5, n_dirs=1)
     m = w.mesh
@@ -131,7 +156,7 @@ def main():
         kms, nk = eng.kernel_time()
         eng.set_kernel_timing(False)
         out[prec] = dict(ms=ms, kernel_ms=kms / max(nk, 1))
-        print(f"[bench] {prec}: {ms:.4f} ms/apply, element kernel {kms / max(nk, 1):.4f} ms", file=sys.stderr,
+        print(f"[bench] {prec}: {ms:.4f} ms/apply, device time {kms / max(nk, 1):.4f} ms", file=sys.stderr,
               flush=True)
     # accuracy of the mixed paths against the FP64 apply (which matches the FP64 oracle to ~1e-14)
     r64u, r64p = eng.jacobian_apply(x64u, x64p, "fp64")
@@ -164,8 +189,8 @@ def main():
         "bf16ops_trial": {"value": gdofs["bf16ops"], "rel_err_vs_fp64": errs["bf16ops"]},
         "set_state_ms": ms_state, "residual_ms": ms_res, "vjp_fp64_ms": ms_vjp,
         "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach32 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_apply<float,4,affine>", "kernel_ms": out["fp32"]["kernel_ms"],
+                     "frac": ach32 / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
+                     "kernel": "apply = k_apply<float,4,affine> + k_assemble<float>", "kernel_ms": out["fp32"]["kernel_ms"],
                      "algorithmic_bytes": b32},
     }
     if not args.no_cpu_baseline:

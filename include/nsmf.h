@@ -147,10 +147,10 @@ int nsmf_query(nsmf_ctx *ctx, int64_t *n_nodes, int64_t *n_el, int64_t *n_p, int
 /* Geometry kind chosen at upload: 0 affine axis-aligned boxes, 1 column-mapped. */
 int nsmf_geometry_kind(nsmf_ctx *ctx);
 
-/* Event timing of the element kernel of jacobian_apply / residual_vjp.  While enabled,
- * each such call records a HIP event pair around its element kernel on the context's
- * stream; nsmf_kernel_time synchronises and returns the summed milliseconds and the
- * number of launches since enabling, then resets. */
+/* Event timing of jacobian_apply / residual_vjp.  While enabled, each such call records a
+ * HIP event pair on the context's stream around its device work (the element kernel and
+ * the node assembly kernel); nsmf_kernel_time synchronises and returns the summed
+ * milliseconds and the number of timed calls since enabling, then resets. */
 int nsmf_set_kernel_timing(nsmf_ctx *ctx, int enable);
 int nsmf_kernel_time(nsmf_ctx *ctx, double *ms_total, int64_t *launches);
 

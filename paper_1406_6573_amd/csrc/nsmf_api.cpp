@@ -42,10 +42,11 @@ struct nsmf_ctx {
   // mesh
   bool have_mesh = false;
   int k = 0, P = 0, n_p = 0, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0;
-  int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_masked = 0;
+  int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_inc = 0;
   HostTables tab;
   DevBuf<uint32_t> en, cmask;
-  DevBuf<int32_t> bface_of, mask_list;
+  DevBuf<int32_t> bface_of, inc_ptr;   // node -> first entry of its segment of the element vector
+  DevBuf<uint8_t> rank;               // slot -> position within its node's segment
   DevBuf<uint8_t> dmask;
   DevBuf<double> geo_el64, geo_qp64, face64;
   DevBuf<float> geo_el32, geo_qp32, face32;
@@ -56,7 +57,7 @@ struct nsmf_ctx {
   DevBuf<float> beta32;
   // state
   bool have_state = false;
-  DevBuf<double> st64, fst64, u, p;
+  DevBuf<double> st64, fst64, u, p, ev;   // ev: element vector (double or float)
   DevBuf<float> st32, fst32;
   // timing
   bool timing = false;
@@ -76,6 +77,9 @@ struct nsmf_ctx {
     m.en = en.p;
     m.cmask = cmask.p;
     m.bface_of = bface_of.p;
+    m.inc_ptr = inc_ptr.p;
+    m.rank = rank.p;
+    m.n_inc = n_inc;
     m.n_el = n_el;
     m.n_nodes = n_nodes;
     m.nblocks = nblocks;
@@ -84,7 +88,7 @@ struct nsmf_ctx {
   GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p}; }
   GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p}; }
   void free_mesh() {
-    en.free(); cmask.free(); bface_of.free(); mask_list.free(); dmask.free();
+    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); rank.free(); dmask.free(); ev.free();
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free();
@@ -165,16 +169,25 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
     if (bof[e] >= 0) return ctx->fail(NSMF_EMESH, "element listed twice in bface_elem");
     bof[e] = (int32_t)f;
   }
-  std::vector<int32_t> mlist;
   std::vector<uint8_t> dm((size_t)3 * N, 0);
   if (m->dmask)
-    for (int64_t i = 0; i < 3 * N; ++i)
-      if (m->dmask[i]) {
-        mlist.push_back((int32_t)i);
-        dm[i] = 1;
-      }
+    for (int64_t i = 0; i < 3 * N; ++i) dm[i] = m->dmask[i] ? 1 : 0;
   if (3 * N >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EINVAL, "3*n_nodes must fit in int32");
-
+  // node-ordered element vector: node n owns entries [iptr[n], iptr[n+1]); slot (e, a) takes
+  // entry iptr[node] + rank[e][a], ranks in element order
+  const int64_t n_inc = n_el * P3;
+  if (n_inc >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EUNSUP, "mesh too large for int32 entries");
+  std::vector<int32_t> iptr((size_t)N + 1, 0);
+  std::vector<uint8_t> irank((size_t)n_inc);
+  for (int64_t i = 0; i < n_inc; ++i) iptr[(words[i] & NODE_MASK) + 1]++;
+  for (int64_t n = 0; n < N; ++n) {
+    if (iptr[n + 1] > 255) return ctx->fail(NSMF_EMESH, "a node is shared by more than 255 element slots");
+    iptr[n + 1] += iptr[n];
+  }
+  {
+    std::vector<uint8_t> cnt((size_t)N, 0);
+    for (int64_t i = 0; i < n_inc; ++i) irank[i] = cnt[words[i] & NODE_MASK]++;
+  }
   ctx->k = m->k;
   ctx->P = P;
   build_tables(m->k, &ctx->tab);
@@ -182,7 +195,6 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   ctx->n_el = n_el;
   ctx->n_nodes = N;
   ctx->n_bface = NB;
-  ctx->n_masked = (int64_t)mlist.size();
   ctx->nt = launch_threads(P);
   ctx->epb = launch_elems(P);
   ctx->nblocks = (int)((n_el + ctx->epb - 1) / ctx->epb);
@@ -192,13 +204,16 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->cmask.alloc(n_el), "hipMalloc");
   NSMF_TRY(ctx, ctx->bface_of.alloc(n_el), "hipMalloc");
   NSMF_TRY(ctx, ctx->dmask.alloc(3 * N), "hipMalloc");
-  NSMF_TRY(ctx, ctx->mask_list.alloc(mlist.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->inc_ptr.alloc(iptr.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->rank.alloc(irank.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->ev.alloc((size_t)3 * n_inc), "hipMalloc");
+  ctx->n_inc = n_inc;
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->en.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->cmask.p, m->cmask, n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->bface_of.p, bof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->dmask.p, dm.data(), 3 * N, hipMemcpyHostToDevice, s), "copy");
-  if (!mlist.empty())
-    NSMF_TRY(ctx, hipMemcpyAsync(ctx->mask_list.p, mlist.data(), mlist.size() * 4, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->inc_ptr.p, iptr.data(), iptr.size() * 4, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->rank.p, irank.data(), irank.size(), hipMemcpyHostToDevice, s), "copy");
 
   DevBuf<double> X;
   DevBuf<unsigned> flags;
@@ -302,12 +317,13 @@ int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p) {
   if (!ctx || !r_u || !r_p) return NSMF_EINVAL;
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "residual needs a state");
   hipStream_t s = ctx->stream;
-  NSMF_TRY(ctx, launch_fill(s, r_u, 6 * ctx->n_nodes), "fill");
   NSMF_TRY(ctx,
            launch_residual(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->st64.p, ctx->fst64.p,
-                           ctx->beta64.p, ctx->p.p, ctx->prm.body, r_u, r_p),
+                           ctx->beta64.p, ctx->p.p, ctx->prm.body, ctx->ev.p, r_p),
            "residual kernel");
-  NSMF_TRY(ctx, launch_residual_fixup(s, ctx->dmask.p, 3 * ctx->n_nodes, ctx->u.p, f_u, r_u), "fixup");
+  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p,
+                                ctx->u.p, f_u, r_u),
+           "assembly");
   return NSMF_OK;
 }
 
@@ -318,8 +334,6 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
   if (prec < 0 || prec > 2) return ctx->fail(NSMF_EINVAL, "precision must be 0, 1 or 2");
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "Jacobian apply needs a state");
   hipStream_t s = ctx->stream;
-  const size_t esz = prec == 0 ? 8 : 4;
-  if (y_u) NSMF_TRY(ctx, launch_fill(s, y_u, 3 * ctx->n_nodes * esz / 4), "fill");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     NSMF_TRY(ctx, hipEventCreate(&e0), "event");
@@ -333,14 +347,17 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
   const void *fst = prec == 0 ? (const void *)ctx->fst64.p : (const void *)ctx->fst32.p;
   const void *beta = prec == 0 ? (const void *)ctx->beta64.p : (const void *)ctx->beta32.p;
   NSMF_TRY(ctx,
-           launch_apply(ctx->P, ctx->geo, prec, vjp, s, ctx->mesh_view(), gv, ctx->tab, st, fst, beta, x_u, x_p, y_u,
-                        y_p, 1.0 / ctx->prm.n, g_logA, g_beta),
+           launch_apply(ctx->P, ctx->geo, prec, vjp, s, ctx->mesh_view(), gv, ctx->tab, st, fst, beta, x_u, x_p,
+                        y_u ? (void *)ctx->ev.p : nullptr, y_p, 1.0 / ctx->prm.n, g_logA, g_beta),
            "apply kernel");
+  if (y_u)
+    NSMF_TRY(ctx, launch_assemble(s, prec, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p,
+                                  x_u, nullptr, y_u),
+             "assembly");
   if (ctx->timing) {
     NSMF_TRY(ctx, hipEventRecord(e1, s), "event");
     ctx->events.emplace_back(e0, e1);
   }
-  if (y_u) NSMF_TRY(ctx, launch_copy_masked(s, prec, ctx->mask_list.p, ctx->n_masked, x_u, y_u), "mask");
   return NSMF_OK;
 }
 

@@ -16,10 +16,20 @@ constexpr int MASK_SHIFT = 28;
 
 // Threads per block and elements per block for P = k+1 nodes per direction.  One
 // thread owns one line of P values of an element, so an element occupies P*P threads.
+// E elements per block; NT rounds E*P*P up to whole wavefronts.
+#ifndef NSMF_E3
+#define NSMF_E3 7
+#endif
+#ifndef NSMF_E4
+#define NSMF_E4 4
+#endif
+#ifndef NSMF_E5
+#define NSMF_E5 5
+#endif
 template <int P> struct Launch;
-template <> struct Launch<3> { static constexpr int NT = 64;  static constexpr int E = 7; };
-template <> struct Launch<4> { static constexpr int NT = 64;  static constexpr int E = 4; };
-template <> struct Launch<5> { static constexpr int NT = 128; static constexpr int E = 5; };
+template <> struct Launch<3> { static constexpr int E = NSMF_E3; static constexpr int NT = (E * 9 + 63) / 64 * 64; };
+template <> struct Launch<4> { static constexpr int E = NSMF_E4; static constexpr int NT = (E * 16 + 63) / 64 * 64; };
+template <> struct Launch<5> { static constexpr int E = NSMF_E5; static constexpr int NT = (E * 25 + 63) / 64 * 64; };
 
 // Reference-element tables (passed by value as kernel arguments, read through the
 // scalar cache).  Indices: q = Gauss point, a = Gauss-Lobatto node.
@@ -49,7 +59,9 @@ struct MeshView {
   const uint32_t *en;        // [n_el][P^3] node word (id | mask bits)
   const uint32_t *cmask;     // [n_el]
   const int32_t *bface_of;   // [n_el] basal face id or -1
-  int64_t n_el, n_nodes;
+  const int32_t *inc_ptr;    // [n_nodes + 1] first incidence of each node in the node-ordered element vector
+  const uint8_t *rank;       // [n_el][P^3] position of the slot among its node's incidences
+  int64_t n_el, n_nodes, n_inc;
   int nblocks;
 };
 
@@ -74,9 +86,8 @@ hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, con
                            const HostTables &tab, const double *st64, const double *fst64, const double *beta,
                            const double *p, const double *body, double *r_u, double *r_p);
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
-hipError_t launch_copy_masked(hipStream_t s, int prec, const int32_t *list, int64_t n, const void *x, void *y);
-hipError_t launch_residual_fixup(hipStream_t s, const uint8_t *dmask, int64_t n, const double *u, const double *f,
-                                 double *r);
+hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
+                           const uint8_t *dm, const void *xm, const void *f, void *y);
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);
 
 }  // namespace nsmf

@@ -14,8 +14,8 @@
 // with point (x, y, z) stored at LDS offset x + P*y + P*P*z.
 //
 // Per-quadrature-point data are stored in the x-line layout of the kernel itself:
-// index ((block * F + field) * P + i) * NT + thread, so that each load of a field is one
-// contiguous NT-wide access.
+// index ((block * F + field) * NT + thread) * P + i, so that each thread loads one field of
+// its P points with one wide load and a wavefront's load is one contiguous access.
 #include <hip/hip_runtime.h>
 
 #include "nsmf_internal.h"
@@ -84,11 +84,24 @@ template <typename T, int P> __device__ __forceinline__ void interp_line_t(const
   for (int i = 0; i < P; ++i) v[i] = o[i];
 }
 
-// Element workspace: NB buffers of P^3 values.
+// LDS strides chosen against bank conflicts (32 banks of 4 bytes): the z-plane stride SZ
+// spreads the P lines of a y-line access over distinct banks, and the element stride puts the
+// elements sharing a half-wavefront on disjoint banks.
+template <typename T, int P> struct LdsShape { static constexpr int SZ = P * P, PADE = 0; };
+template <typename T> struct LdsShape<T, 4> { static constexpr int SZ = 20, PADE = sizeof(T) == 8 ? 8 : 0; };
+template <typename T> struct LdsShape<T, 5> { static constexpr int SZ = 26, PADE = 0; };
+
+// Element workspace: NB buffers of P planes each; point (x, y, z) at x + P*y + SZ*z.
 template <typename T, int P> struct Ws {
-  static constexpr int P2 = P * P, P3 = P * P * P, NB = 5;
+  static constexpr int P2 = P * P, NB = 5;
+  static constexpr int SZ = LdsShape<T, P>::SZ;          // z-plane stride
+  static constexpr int BS = SZ * P;                      // buffer size
+  static constexpr int ES = NB * BS + LdsShape<T, P>::PADE;   // element stride
   T *s;
-  __device__ T *b(int k) const { return s + k * P3; }
+  __device__ T *b(int k) const { return s + k * BS; }
+  // start of the z-line of thread t = x + P*y, and of the x-line of thread t = y + P*z
+  __device__ static int zl(int t, int z) { return t + SZ * z; }
+  __device__ static int xl(int t) { return P * (t % P) + SZ * (t / P); }
 };
 
 // ---------------------------------------------------------------- hanging restriction R_e
@@ -102,7 +115,7 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int z = 0; z < P; ++z) w.b(c)[t + P2 * z] = v[c][z];
+      for (int z = 0; z < P; ++z) w.b(c)[w.zl(t, z)] = v[c][z];
   __syncthreads();
   if (act) {
     const int j = t % P, z = t / P;
@@ -112,10 +125,10 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
       for (int c = 0; c < 3; ++c) {
         T l[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + P * t];
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + w.xl(t)];
         interp_line<T, P>(tb.I[h], l);
 #pragma unroll
-        for (int m = 0; m < P; ++m) w.b(c)[m + P * t] = l[m];
+        for (int m = 0; m < P; ++m) w.b(c)[m + w.xl(t)] = l[m];
       }
     }
   }
@@ -128,10 +141,10 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
       for (int c = 0; c < 3; ++c) {
         T l[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + P2 * z];
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + w.SZ * z];
         interp_line<T, P>(tb.I[h], l);
 #pragma unroll
-        for (int m = 0; m < P; ++m) w.b(c)[i + P * m + P2 * z] = l[m];
+        for (int m = 0; m < P; ++m) w.b(c)[i + P * m + w.SZ * z] = l[m];
       }
     }
   }
@@ -140,7 +153,7 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int z = 0; z < P; ++z) v[c][z] = w.b(c)[t + P2 * z];
+      for (int z = 0; z < P; ++z) v[c][z] = w.b(c)[w.zl(t, z)];
     const int i = t % P, j = t / P;
     if (zline_hanging<P>(cm, i, j)) {
       const int h = (cm >> 2) & 1u;
@@ -165,7 +178,7 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int z = 0; z < P; ++z) w.b(c)[t + P2 * z] = v[c][z];
+      for (int z = 0; z < P; ++z) w.b(c)[w.zl(t, z)] = v[c][z];
   }
   __syncthreads();
   if (act) {
@@ -176,10 +189,10 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
       for (int c = 0; c < 3; ++c) {
         T l[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + P2 * z];
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + w.SZ * z];
         interp_line_t<T, P>(tb.I[h], l);
 #pragma unroll
-        for (int m = 0; m < P; ++m) w.b(c)[i + P * m + P2 * z] = l[m];
+        for (int m = 0; m < P; ++m) w.b(c)[i + P * m + w.SZ * z] = l[m];
       }
     }
   }
@@ -192,10 +205,10 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
       for (int c = 0; c < 3; ++c) {
         T l[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + P * t];
+        for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + w.xl(t)];
         interp_line_t<T, P>(tb.I[h], l);
 #pragma unroll
-        for (int m = 0; m < P; ++m) w.b(c)[m + P * t] = l[m];
+        for (int m = 0; m < P; ++m) w.b(c)[m + w.xl(t)] = l[m];
       }
     }
   }
@@ -204,7 +217,7 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int z = 0; z < P; ++z) v[c][z] = w.b(c)[t + P2 * z];
+      for (int z = 0; z < P; ++z) v[c][z] = w.b(c)[w.zl(t, z)];
   __syncthreads();
 }
 
@@ -225,8 +238,8 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
         a += tb.B[q][m] * v[m];
         d += tb.D[q][m] * v[m];
       }
-      w.b(0)[t + P2 * q] = a;
-      w.b(1)[t + P2 * q] = d;
+      w.b(0)[w.zl(t, q)] = a;
+      w.b(1)[w.zl(t, q)] = d;
     }
   }
   __syncthreads();
@@ -235,8 +248,8 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
     T a[P], b[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-      a[m] = w.b(0)[i + P * m + P2 * z];
-      b[m] = w.b(1)[i + P * m + P2 * z];
+      a[m] = w.b(0)[i + P * m + w.SZ * z];
+      b[m] = w.b(1)[i + P * m + w.SZ * z];
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -247,9 +260,9 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
         s1 += tb.D[q][m] * a[m];
         s2 += tb.B[q][m] * b[m];
       }
-      w.b(2)[i + P * q + P2 * z] = s0;
-      w.b(3)[i + P * q + P2 * z] = s1;
-      w.b(4)[i + P * q + P2 * z] = s2;
+      w.b(2)[i + P * q + w.SZ * z] = s0;
+      w.b(3)[i + P * q + w.SZ * z] = s1;
+      w.b(4)[i + P * q + w.SZ * z] = s2;
     }
   }
   __syncthreads();
@@ -257,9 +270,9 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
     T a[P], b[P], c[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-      a[m] = w.b(2)[m + P * t];
-      b[m] = w.b(3)[m + P * t];
-      c[m] = w.b(4)[m + P * t];
+      a[m] = w.b(2)[m + w.xl(t)];
+      b[m] = w.b(3)[m + w.xl(t)];
+      c[m] = w.b(4)[m + w.xl(t)];
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -294,9 +307,9 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
         h1 += tb.B[q][i] * fy[q];
         h2 += tb.B[q][i] * fz[q];
       }
-      w.b(0)[i + P * t] = h0;
-      w.b(1)[i + P * t] = h1;
-      w.b(2)[i + P * t] = h2;
+      w.b(0)[i + w.xl(t)] = h0;
+      w.b(1)[i + w.xl(t)] = h1;
+      w.b(2)[i + w.xl(t)] = h2;
     }
   }
   __syncthreads();
@@ -305,9 +318,9 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
     T a[P], b[P], c[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      a[q] = w.b(0)[i + P * q + P2 * z];
-      b[q] = w.b(1)[i + P * q + P2 * z];
-      c[q] = w.b(2)[i + P * q + P2 * z];
+      a[q] = w.b(0)[i + P * q + w.SZ * z];
+      b[q] = w.b(1)[i + P * q + w.SZ * z];
+      c[q] = w.b(2)[i + P * q + w.SZ * z];
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -317,8 +330,8 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
         k0 += tb.B[q][j] * a[q] + tb.D[q][j] * b[q];
         k1 += tb.B[q][j] * c[q];
       }
-      w.b(3)[i + P * j + P2 * z] = k0;
-      w.b(4)[i + P * j + P2 * z] = k1;
+      w.b(3)[i + P * j + w.SZ * z] = k0;
+      w.b(4)[i + P * j + w.SZ * z] = k1;
     }
   }
   __syncthreads();
@@ -326,8 +339,8 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
     T a[P], b[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      a[q] = w.b(3)[t + P2 * q];
-      b[q] = w.b(4)[t + P2 * q];
+      a[q] = w.b(3)[w.zl(t, q)];
+      b[q] = w.b(4)[w.zl(t, q)];
     }
 #pragma unroll
     for (int z = 0; z < P; ++z) {
@@ -336,6 +349,26 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
       for (int q = 0; q < P; ++q) o += tb.B[q][z] * a[q] + tb.D[q][z] * b[q];
       out[z] = o;
     }
+  }
+}
+
+// Per-quadrature-point field f of thread tid in block lb: the thread's P points along its
+// x-line are contiguous, index ((lb * F + f) * NT + tid) * P + i.
+template <int P, int NT, int F>
+__device__ __forceinline__ size_t qp_index(int lb, int f, int tid) {
+  return (((size_t)lb * F + f) * NT + tid) * P;
+}
+template <typename T, int P>
+__device__ __forceinline__ void load_line(const T *__restrict__ p, T (&o)[P]) {
+  if constexpr (P == 4 && sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else if constexpr (P == 4 && sizeof(T) == 8) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < P; ++i) o[i] = p[i];
   }
 }
 
@@ -359,14 +392,10 @@ __device__ __forceinline__ void load_geo(QpGeo<T, P, GEO> &g, const GeoView<T> &
   } else {
     const T *p = gv.el + 2 * e;
     g.jx = p[0]; g.jy = p[1];
-    const T *q = gv.qp + (size_t)lb * 4 * P * NT;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      g.a[i] = q[(0 * P + i) * NT + tid];
-      g.b[i] = q[(1 * P + i) * NT + tid];
-      g.c[i] = q[(2 * P + i) * NT + tid];
-      g.wd[i] = q[(3 * P + i) * NT + tid];
-    }
+    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 0, tid), g.a);
+    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 1, tid), g.b);
+    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 2, tid), g.c);
+    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 3, tid), g.wd);
   }
 }
 
@@ -448,12 +477,12 @@ __device__ void pressure_reduce(const T (&part)[(P - 1) * P * (P + 1) / 6], Ws<T
   constexpr int NP = (P - 1) * P * (P + 1) / 6, P2 = P * P;
   if (act)
 #pragma unroll
-    for (int m = 0; m < NP; ++m) w.s[m * P2 + t] = part[m];
+    for (int m = 0; m < NP; ++m) w.s[m * (P2 + 1) + t] = part[m];
   __syncthreads();
   if (act && yp_e != nullptr) {
     for (int m = t; m < NP; m += P2) {
       T s = 0;
-      for (int r = 0; r < P2; ++r) s += w.s[m * P2 + r];
+      for (int r = 0; r < P2; ++r) s += w.s[m * (P2 + 1) + r];
       yp_e[m] = -s;
     }
   }
@@ -548,16 +577,22 @@ __device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t
     }
 }
 
+// Element-vector store in node order: the result of element slot (e, a) for component c goes to
+// ev[c * n_inc + ptr[node] + rank], where ptr is the node's first incidence and rank the slot's
+// position among the node's incidences (both built at upload).  The assembly kernel then sums
+// contiguous segments.
 template <typename T, int P>
-__device__ __forceinline__ void scatter_add(const uint32_t (&nw)[P], T *y, int64_t N, bool act, const T (&v)[3][P]) {
-  if (!act || y == nullptr) return;
+__device__ __forceinline__ void evec_store(T *ev, int64_t n_inc, const int32_t *__restrict__ ptr,
+                                           const uint8_t *__restrict__ rank_e, const uint32_t (&nw)[P], int t,
+                                           bool act, const T (&v)[3][P]) {
+  if (!act || ev == nullptr) return;
+  constexpr int P2 = P * P;
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int z = 0; z < P; ++z) {
+    const int64_t k = (int64_t)ptr[nw[z] & NODE_MASK] + rank_e[t + P2 * z];
 #pragma unroll
-    for (int z = 0; z < P; ++z) {
-      const uint32_t wd = nw[z];
-      if (!((wd >> (MASK_SHIFT + c)) & 1u)) unsafeAtomicAdd(&y[c * N + (wd & NODE_MASK)], v[c][z]);
-    }
+    for (int c = 0; c < 3; ++c) ev[c * n_inc + k] = v[c][z];
+  }
 }
 
 // ================================================================= kernels
@@ -569,16 +604,21 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
         T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   constexpr int NP = (P - 1) * P * (P + 1) / 6;
-  __shared__ T smem[E * 5 * P3];
+  __shared__ T smem[E * Ws<T, P>::ES];
   __shared__ double red[E * P2];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = (int64_t)lb * E + el;
   const bool act = el < E && e < m.n_el;
   const int els = el < E ? el : E - 1;
-  Ws<T, P> w{smem + els * 5 * P3};
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
   double *redl = red + els * P2;
   const int64_t N = m.n_nodes;
+  // linearisation data of the thread's P points, requested first so that its latency
+  // overlaps the gather and the forward sweeps (the block's slice is always allocated)
+  T stv[NSTATE][P];
+#pragma unroll
+  for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
 
   const uint32_t cm = act ? m.cmask[e] : 0u;
   T v[3][P];
@@ -603,7 +643,6 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
   }
   T dw[P];
   double gA = 0.0;
-  const T *stb = st + (size_t)lb * NSTATE * P * NT;
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     if (!act) { dw[i] = 0; continue; }
@@ -613,11 +652,9 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
 #pragma unroll
       for (int r = 0; r < 3; ++r) grr[c][r] = gr[c][r][i];
     to_phys<T, P, GEO>(g, i, grr, G);
-    const T mu = stb[(0 * P + i) * NT + tid];
-    const T ka = stb[(1 * P + i) * NT + tid];
-    const T sxx = stb[(2 * P + i) * NT + tid], syy = stb[(3 * P + i) * NT + tid];
-    const T szz = stb[(4 * P + i) * NT + tid], sxy = stb[(5 * P + i) * NT + tid];
-    const T sxz = stb[(6 * P + i) * NT + tid], syz = stb[(7 * P + i) * NT + tid];
+    const T mu = stv[0][i], ka = stv[1][i];
+    const T sxx = stv[2][i], syy = stv[3][i], szz = stv[4][i];
+    const T sxy = stv[5][i], sxz = stv[6][i], syz = stv[7][i];
     const T dxx = G[0][0], dyy = G[1][1], dzz = G[2][2];
     const T dxy = T(0.5) * (G[0][1] + G[1][0]), dxz = T(0.5) * (G[0][2] + G[2][0]);
     const T dyz = T(0.5) * (G[1][2] + G[2][1]);
@@ -683,7 +720,7 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
     }
   }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
-  scatter_add<T, P>(nw, yu, N, act, y);
+  evec_store<T, P>(yu, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
 }
 
 // Linearisation point: per quadrature point mu' = w detJ mu, kappa, Sigma0 = mu' D(u)
@@ -695,13 +732,13 @@ k_state(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restr
         float *__restrict__ st32, double *__restrict__ fst64, float *__restrict__ fst32) {
   using T = double;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
-  __shared__ T smem[E * 5 * P3];
+  __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = (int64_t)lb * E + el;
   const bool act = el < E && e < m.n_el;
   const int els = el < E ? el : E - 1;
-  Ws<T, P> w{smem + els * 5 * P3};
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
   const uint32_t cm = act ? m.cmask[e] : 0u;
   T v[3][P];
@@ -718,8 +755,8 @@ k_state(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restr
     load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
     const double Be = B0 * exp(-logA[e] / n);
     const double expo = (1.0 - n) / (2.0 * n), cf = (n - 1.0) / (2.0 * n);
-    double *s64 = st64 + (size_t)lb * NSTATE * P * NT;
-    float *s32 = st32 + (size_t)lb * NSTATE * P * NT;
+    double *s64 = st64;
+    float *s32 = st32;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       T grr[3][3], G[3][3];
@@ -737,8 +774,8 @@ k_state(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restr
       const T vals[NSTATE] = {mup, ka, mup * dxx, mup * dyy, mup * dzz, mup * dxy, mup * dxz, mup * dyz};
 #pragma unroll
       for (int f = 0; f < NSTATE; ++f) {
-        s64[(f * P + i) * NT + tid] = vals[f];
-        s32[(f * P + i) * NT + tid] = (float)vals[f];
+        s64[qp_index<P, NT, NSTATE>(lb, f, tid) + i] = vals[f];
+        s32[qp_index<P, NT, NSTATE>(lb, f, tid) + i] = (float)vals[f];
       }
     }
   }
@@ -770,13 +807,13 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
   using T = double;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   constexpr int NP = (P - 1) * P * (P + 1) / 6;
-  __shared__ T smem[E * 5 * P3];
+  __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = (int64_t)lb * E + el;
   const bool act = el < E && e < m.n_el;
   const int els = el < E ? el : E - 1;
-  Ws<T, P> w{smem + els * 5 * P3};
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
   const uint32_t cm = act ? m.cmask[e] : 0u;
   uint32_t nw[P];
@@ -791,13 +828,14 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
 #pragma unroll
     for (int mm = 0; mm < NP; ++mm) xpl[mm] = p[e * NP + mm];
     pressure_interp<T, P>(xpl, tb, t, pq);
-    const T *stb = st + (size_t)lb * NSTATE * P * NT;
+    T stv[NSTATE][P];
+#pragma unroll
+    for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const T mu = stb[(0 * P + i) * NT + tid];
-      const T sxx = stb[(2 * P + i) * NT + tid], syy = stb[(3 * P + i) * NT + tid];
-      const T szz = stb[(4 * P + i) * NT + tid], sxy = stb[(5 * P + i) * NT + tid];
-      const T sxz = stb[(6 * P + i) * NT + tid], syz = stb[(7 * P + i) * NT + tid];
+      const T mu = stv[0][i];
+      const T sxx = stv[2][i], syy = stv[3][i], szz = stv[4][i];
+      const T sxy = stv[5][i], sxz = stv[6][i], syz = stv[7][i];
       const T pw = pq[i] * g.wd[i];
       T tau[3][3] = {{sxx - pw, sxy, sxz}, {sxy, syy - pw, syz}, {sxz, syz, szz - pw}};
       T f[3][3];
@@ -845,7 +883,7 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
       for (int c = 0; c < 3; ++c) y[c][0] += out[c];
   }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
-  scatter_add<T, P>(nw, ru, N, act, y);
+  evec_store<T, P>(ru, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
 }
 
 // Geometry at upload (FP64).  mode 0: classify (flags bit0 not column-mapped, bit1 not
@@ -857,14 +895,14 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
            double *__restrict__ qp_out, double *__restrict__ face_out, unsigned *__restrict__ flags) {
   using T = double;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
-  __shared__ T smem[E * 5 * P3];
+  __shared__ T smem[E * Ws<T, P>::ES];
   __shared__ T ref0[E][3];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = (int64_t)lb * E + el;
   const bool act = el < E && e < m.n_el;
   const int els = el < E ? el : E - 1;
-  Ws<T, P> w{smem + els * 5 * P3};
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
   const uint32_t cm = act ? m.cmask[e] : 0u;
   T v[3][P];
@@ -910,12 +948,11 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
         fl |= 1u;
       if (fabs(a[2][0]) > tol || fabs(a[2][1]) > tol || fabs(a[2][2] - r22) > tol) fl |= 2u;
       if (mode == 2) {
-        T *q = qp_out + (size_t)lb * 4 * P * NT;
         const T j00 = a[0][0], j11 = a[1][1], j22 = a[2][2];
-        q[(0 * P + i) * NT + tid] = -a[2][0] / (j00 * j22);
-        q[(1 * P + i) * NT + tid] = -a[2][1] / (j11 * j22);
-        q[(2 * P + i) * NT + tid] = 1.0 / j22;
-        q[(3 * P + i) * NT + tid] = tb.w[i] * tb.w[j] * tb.w[z] * j00 * j11 * j22;
+        qp_out[qp_index<P, NT, 4>(lb, 0, tid) + i] = -a[2][0] / (j00 * j22);
+        qp_out[qp_index<P, NT, 4>(lb, 1, tid) + i] = -a[2][1] / (j11 * j22);
+        qp_out[qp_index<P, NT, 4>(lb, 2, tid) + i] = 1.0 / j22;
+        qp_out[qp_index<P, NT, 4>(lb, 3, tid) + i] = tb.w[i] * tb.w[j] * tb.w[z] * j00 * j11 * j22;
       }
     }
     if (t == 0 && mode == 1) {
@@ -973,19 +1010,35 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
   if (mode == 0 && fl) atomicOr(flags, fl);
 }
 
+// ---------------------------------------------------------------- assembly  y = sum_e R_e^T y_e
+// One thread per node: sums the node's contiguous segment of the node-ordered element vector
+// (fixed order, so the result is deterministic).  Rows of Dirichlet-flagged components take the
+// value xm (x for the Jacobian, u for the residual); other rows subtract f when given.
+template <typename T>
+__global__ void k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_inc,
+                           const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f,
+                           T *__restrict__ y) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  T s0 = 0, s1 = 0, s2 = 0;
+  const int32_t k1 = ptr[n + 1];
+  for (int32_t k = ptr[n]; k < k1; ++k) {
+    s0 += ev[k];
+    s1 += ev[n_inc + k];
+    s2 += ev[2 * n_inc + k];
+  }
+  const T sv[3] = {s0, s1, s2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t i = c * N + n;
+    y[i] = dm[i] ? xm[i] : (f ? sv[c] - f[i] : sv[c]);
+  }
+}
+
 // ---------------------------------------------------------------- small kernels
 __global__ void k_fill(uint32_t *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
-}
-template <typename T>
-__global__ void k_copy_masked(const int32_t *list, int64_t n, const T *x, T *y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[list[i]] = x[list[i]];
-}
-__global__ void k_residual_fixup(const uint8_t *dm, int64_t n, const double *u, const double *f, double *r) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) r[i] = dm[i] ? u[i] : (f ? r[i] - f[i] : r[i]);
 }
 __global__ void k_d2f(const double *in, float *out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -994,27 +1047,22 @@ __global__ void k_d2f(const double *in, float *out, int64_t n) {
 
 static inline int grid1(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 
+hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
+                           const uint8_t *dm, const void *xm, const void *f, void *y) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, 256)), dim3(256), 0, s, N, ptr, (const double *)ev, n_inc,
+                       dm, (const double *)xm, (const double *)f, (double *)y);
+  else
+    hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, 256)), dim3(256), 0, s, N, ptr, (const float *)ev, n_inc, dm,
+                       (const float *)xm, (const float *)f, (float *)y);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n) {
   if (n <= 0) return hipSuccess;
   int nb = grid1(n, 256);
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, (uint32_t *)ptr, n);
-  return hipGetLastError();
-}
-hipError_t launch_copy_masked(hipStream_t s, int prec, const int32_t *list, int64_t n, const void *x, void *y) {
-  if (n <= 0) return hipSuccess;
-  if (prec == 0)
-    hipLaunchKernelGGL(k_copy_masked<double>, dim3(grid1(n, 256)), dim3(256), 0, s, list, n, (const double *)x,
-                       (double *)y);
-  else
-    hipLaunchKernelGGL(k_copy_masked<float>, dim3(grid1(n, 256)), dim3(256), 0, s, list, n, (const float *)x,
-                       (float *)y);
-  return hipGetLastError();
-}
-hipError_t launch_residual_fixup(hipStream_t s, const uint8_t *dm, int64_t n, const double *u, const double *f,
-                                 double *r) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual_fixup, dim3(grid1(n, 256)), dim3(256), 0, s, dm, n, u, f, r);
   return hipGetLastError();
 }
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n) {

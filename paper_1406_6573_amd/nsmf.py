@@ -95,6 +95,7 @@ class Engine:
         self.dev = torch.device("cuda", self.device)
         self.sync_stream()
         self.k = None
+        self.state_version = 0
 
     # -------------------------------------------------------------- plumbing
     def _check(self, rc: int, h=-1):
@@ -160,6 +161,7 @@ class Engine:
             beta = self._vec(beta, (sz["n_bface"],), torch.float64, "beta")
         prm = _Params(float(n), float(eps), float(B0), (ctypes.c_double * 3)(*[float(b) for b in body]))
         self._check(self.lib.nsmf_set_params(self.h, ctypes.byref(prm), _ptr(logA), _ptr(beta)))
+        self.state_version += 1
 
     def set_state(self, u, p):
         torch = self.torch
@@ -167,6 +169,7 @@ class Engine:
         u = self._vec(u, (3, sz["n_nodes"]), torch.float64, "u")
         p = self._vec(p, (sz["n_el"], sz["n_p"]), torch.float64, "p")
         self._check(self.lib.nsmf_set_state(self.h, _ptr(u), _ptr(p)))
+        self.state_version += 1
 
     def residual(self, f_u=None, out=None):
         torch = self.torch
