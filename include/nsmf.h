@@ -141,6 +141,30 @@ int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_
 int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
                       double *g_logA, double *g_beta);
 
+/* Block-Jacobi preconditioner data at the state (FP64, DEVICE outputs), used by the Newton-Krylov
+ * driver (Sec. 4.2).  d_u [3][n_nodes]: the diagonal of the velocity block F per component
+ * (eq. (rank4) tested with each basis function, plus the basal Robin term), hanging nodes
+ * collecting their children's diagonals with squared interpolation weights; 1 on Dirichlet rows.
+ * d_p [n_el][n_p]: minus the lumped 1/mu-weighted pressure mass, the Schur-complement
+ * approximation of Sec. 6.  With invert != 0 both outputs hold the reciprocals (the
+ * preconditioner's action).  Requires a state. */
+int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p);
+
+/* Vector kernels of the Krylov driver (classical Gram-Schmidt FGMRES, Sec. 4.2) on DEVICE
+ * vectors of length n; prec 0: double vectors, 1: float vectors.  Inner products always
+ * accumulate in FP64 with a fixed reduction order (deterministic).
+ *   nsmf_vec_dots:  h[i] = sum_r V[i*ldv + r] w[r], i < k <= 64 (h: DEVICE doubles [k])
+ *   nsmf_vec_gemv:  w[r] += alpha sum_i V[i*ldv + r] h[i] (h: DEVICE doubles [k])
+ *   nsmf_vec_axpby: y = a x + b y
+ *   nsmf_vec_mul:   z = d .* x (d: DEVICE doubles [n])
+ *   nsmf_vec_convert: out = in, double -> float (to_fp32 != 0) or float -> double */
+int nsmf_vec_dots(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w, double *h);
+int nsmf_vec_gemv(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
+                  double alpha, void *w);
+int nsmf_vec_axpby(nsmf_ctx *ctx, int prec, int64_t n, double a, const void *x, double b, void *y);
+int nsmf_vec_mul(nsmf_ctx *ctx, int prec, int64_t n, const double *d, const void *x, void *z);
+int nsmf_vec_convert(nsmf_ctx *ctx, int64_t n, int to_fp32, const void *in, void *out);
+
 /* Sizes of the uploaded mesh; any pointer may be NULL. */
 int nsmf_query(nsmf_ctx *ctx, int64_t *n_nodes, int64_t *n_el, int64_t *n_p, int64_t *n_dof, int64_t *n_bface);
 

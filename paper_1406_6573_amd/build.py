@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libnsmf.so")
 
-SOURCES = ["nsmf_tables.cpp", "nsmf_api.cpp", "nsmf_kernels.hip"]
+SOURCES = ["nsmf_tables.cpp", "nsmf_api.cpp", "nsmf_kernels.hip", "nsmf_blas.hip"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -59,6 +59,8 @@ struct nsmf_ctx {
   bool have_state = false;
   DevBuf<double> st64, fst64, u, p, ev;   // ev: element vector (double or float)
   DevBuf<float> st32, fst32;
+  // Krylov vector kernels: partial sums of the multi-dot products
+  DevBuf<double> dot_partial;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -91,7 +93,7 @@ struct nsmf_ctx {
     en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); rank.free(); dmask.free(); ev.free();
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
     logA.free(); beta64.free(); beta32.free();
-    st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free();
+    st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
     have_mesh = have_params = have_state = false;
   }
 };
@@ -368,6 +370,76 @@ int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_
 int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
                       double *g_logA, double *g_beta) {
   return apply_common(ctx, prec, true, w_u, w_p, g_u, g_p, g_logA, g_beta);
+}
+
+int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p) {
+  if (!ctx || !d_u || !d_p) return NSMF_EINVAL;
+  if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "jacobi_diag needs a state");
+  hipStream_t s = ctx->stream;
+  NSMF_TRY(ctx,
+           launch_diag(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->st64.p, ctx->beta64.p,
+                       ctx->ev.p, d_p),
+           "diagonal kernel");
+  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p, nullptr,
+                                nullptr, d_u),
+           "assembly");
+  if (invert) {
+    NSMF_TRY(ctx, launch_recip(s, 3 * ctx->n_nodes, d_u), "reciprocal");
+    NSMF_TRY(ctx, launch_recip(s, ctx->n_el * ctx->n_p, d_p), "reciprocal");
+  }
+  return NSMF_OK;
+}
+
+static int vec_check(nsmf_ctx *ctx, int prec, int64_t n) {
+  if (!ctx) return NSMF_EINVAL;
+  if (prec != 0 && prec != 1) return ctx->fail(NSMF_EINVAL, "vector precision must be 0 (double) or 1 (float)");
+  if (n <= 0) return ctx->fail(NSMF_EINVAL, "vector length must be positive");
+  return NSMF_OK;
+}
+
+int nsmf_vec_dots(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w, double *h) {
+  int rc = vec_check(ctx, prec, n);
+  if (rc) return rc;
+  if (!V || !w || !h || k < 1 || k > MAX_DOTS || ldv < n) return ctx->fail(NSMF_EINVAL, "bad nsmf_vec_dots arguments");
+  if (!ctx->dot_partial.p) NSMF_TRY(ctx, ctx->dot_partial.alloc((size_t)1024 * MAX_DOTS), "hipMalloc");
+  NSMF_TRY(ctx, launch_dots(ctx->stream, prec, n, k, V, ldv, w, ctx->dot_partial.p, h), "dots");
+  return NSMF_OK;
+}
+
+int nsmf_vec_gemv(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
+                  double alpha, void *w) {
+  int rc = vec_check(ctx, prec, n);
+  if (rc) return rc;
+  if (!V || !w || !h || k < 1 || k > MAX_DOTS || ldv < n) return ctx->fail(NSMF_EINVAL, "bad nsmf_vec_gemv arguments");
+  NSMF_TRY(ctx, launch_gemv(ctx->stream, prec, n, k, V, ldv, h, alpha, w), "gemv");
+  return NSMF_OK;
+}
+
+int nsmf_vec_axpby(nsmf_ctx *ctx, int prec, int64_t n, double a, const void *x, double b, void *y) {
+  int rc = vec_check(ctx, prec, n);
+  if (rc) return rc;
+  if (!x || !y) return ctx->fail(NSMF_EINVAL, "NULL vector");
+  NSMF_TRY(ctx, launch_axpby(ctx->stream, prec, n, a, x, b, y), "axpby");
+  return NSMF_OK;
+}
+
+int nsmf_vec_mul(nsmf_ctx *ctx, int prec, int64_t n, const double *d, const void *x, void *z) {
+  int rc = vec_check(ctx, prec, n);
+  if (rc) return rc;
+  if (!d || !x || !z) return ctx->fail(NSMF_EINVAL, "NULL vector");
+  NSMF_TRY(ctx, launch_mul(ctx->stream, prec, n, d, x, z), "mul");
+  return NSMF_OK;
+}
+
+int nsmf_vec_convert(nsmf_ctx *ctx, int64_t n, int to_fp32, const void *in, void *out) {
+  int rc = vec_check(ctx, 0, n);
+  if (rc) return rc;
+  if (!in || !out) return ctx->fail(NSMF_EINVAL, "NULL vector");
+  if (to_fp32)
+    NSMF_TRY(ctx, launch_d2f(ctx->stream, (const double *)in, (float *)out, n), "convert");
+  else
+    NSMF_TRY(ctx, launch_f2d(ctx->stream, (const float *)in, (double *)out, n), "convert");
+  return NSMF_OK;
 }
 
 int nsmf_query(nsmf_ctx *ctx, int64_t *n_nodes, int64_t *n_el, int64_t *n_p, int64_t *n_dof, int64_t *n_bface) {

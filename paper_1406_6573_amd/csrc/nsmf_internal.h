@@ -14,6 +14,9 @@ enum GeoKind { GEO_AFFINE = 0, GEO_COLUMN = 1 };
 constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;
 constexpr int MASK_SHIFT = 28;
 
+// Largest number of simultaneous dot products of nsmf_vec_dots (Krylov basis size + 1).
+constexpr int MAX_DOTS = 64;
+
 // Threads per block and elements per block for P = k+1 nodes per direction.  One
 // thread owns one line of P values of an element, so an element occupies P*P threads.
 // E elements per block; NT rounds E*P*P up to whole wavefronts.
@@ -85,9 +88,19 @@ hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const
 hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                            const HostTables &tab, const double *st64, const double *fst64, const double *beta,
                            const double *p, const double *body, double *r_u, double *r_p);
+hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+                       const double *st, const double *beta, double *ev, double *dp);
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
                            const uint8_t *dm, const void *xm, const void *f, void *y);
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);
+hipError_t launch_f2d(hipStream_t s, const float *in, double *out, int64_t n);
+hipError_t launch_recip(hipStream_t s, int64_t n, double *x);
+hipError_t launch_dots(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w,
+                       double *partial, double *h);
+hipError_t launch_gemv(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
+                       double alpha, void *w);
+hipError_t launch_axpby(hipStream_t s, int prec, int64_t n, double a, const void *x, double b, void *y);
+hipError_t launch_mul(hipStream_t s, int prec, int64_t n, const double *d, const void *x, void *z);
 
 }  // namespace nsmf

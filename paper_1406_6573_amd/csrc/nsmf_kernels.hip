@@ -886,6 +886,108 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
   evec_store<T, P>(ru, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
 }
 
+// Block-Jacobi data at the linearisation point (FP64).  Velocity: the diagonal of F per
+// component, sum over quadrature points of mu'/2 (|grad phi_a|^2 + (d_c phi_a)^2) - kappa
+// ((Sigma0 grad phi_a)_c)^2 (eq. (rank4) tested with phi_a e_c), plus the basal term
+// beta w|S| phi_a^2 (1 - n_c^2); hanging slots reach their parent nodes through squared
+// interpolation weights (tb2), i.e. sum_e sum_a R_e[a,n]^2 F_e[a,a].  Pressure: the lumped
+// mass weighted by 1/mu with a minus sign, the Schur-complement approximation of Sec. 6.
+template <int P, int GEO>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_diag(MeshView m, GeoView<double> gv, Tab<double, P> tb, Tab<double, P> tb2, const double *__restrict__ st,
+       const double *__restrict__ beta, double *__restrict__ ev, double *__restrict__ dp) {
+  using T = double;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  __shared__ T smem[E * Ws<T, P>::ES];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = (int64_t)lb * E + el;
+  const bool act = el < E && e < m.n_el;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  uint32_t nw[P];
+#pragma unroll
+  for (int z = 0; z < P; ++z) nw[z] = act ? m.en[e * P3 + t + P2 * z] : 0u;
+  T y[3][P];
+  T part[NP];
+#pragma unroll
+  for (int mm = 0; mm < NP; ++mm) part[mm] = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < P; ++z) y[c][z] = 0;
+  if (act) {
+    const int i = t % P, j = t / P;          // slot (i, j, z) of the z-line
+    double jx = 0, jy = 0, jz = 0, detJ = 0;
+    if (GEO == GEO_AFFINE) {
+      jx = gv.el[4 * e]; jy = gv.el[4 * e + 1]; jz = gv.el[4 * e + 2]; detJ = gv.el[4 * e + 3];
+    } else {
+      jx = gv.el[2 * e]; jy = gv.el[2 * e + 1];
+    }
+    for (int tq = 0; tq < P2; ++tq) {          // quadrature points (qx, qy, qz), qy + P qz = tq
+      const int qy = tq % P, qz = tq / P;
+      const int tidq = el * P2 + tq;
+      for (int qx = 0; qx < P; ++qx) {
+        const double mu = st[qp_index<P, NT, NSTATE>(lb, 0, tidq) + qx];
+        const double ka = st[qp_index<P, NT, NSTATE>(lb, 1, tidq) + qx];
+        double S[6];
+        for (int f = 0; f < 6; ++f) S[f] = st[qp_index<P, NT, NSTATE>(lb, 2 + f, tidq) + qx];
+        double a = 0, b = 0, cc = jz, wd;
+        if (GEO == GEO_AFFINE) {
+          wd = tb.w[qx] * tb.w[qy] * tb.w[qz] * detJ;
+        } else {
+          a = gv.qp[qp_index<P, NT, 4>(lb, 0, tidq) + qx];
+          b = gv.qp[qp_index<P, NT, 4>(lb, 1, tidq) + qx];
+          cc = gv.qp[qp_index<P, NT, 4>(lb, 2, tidq) + qx];
+          wd = gv.qp[qp_index<P, NT, 4>(lb, 3, tidq) + qx];
+        }
+        // pressure: thread (j, z) of the x-line layout owns points (., j, z); here every
+        // thread accumulates the points of its own tq = t for the lumped 1/mu mass
+        if (tq == t) {
+          const double g = wd * wd / mu;
+          for (int mm = 0; mm < NP; ++mm) {
+            const double psi = tb.L[tb.pe[mm][0]][qx] * tb.L[tb.pe[mm][1]][qy] * tb.L[tb.pe[mm][2]][qz];
+            part[mm] += g * psi * psi;
+          }
+        }
+        for (int z = 0; z < P; ++z) {
+          const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
+          const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
+          const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
+          double G[3];
+          if (GEO == GEO_AFFINE) {
+            G[0] = gr0 * jx; G[1] = gr1 * jy; G[2] = gr2 * jz;
+          } else {
+            G[0] = gr0 * jx + gr2 * a; G[1] = gr1 * jy + gr2 * b; G[2] = gr2 * cc;
+          }
+          const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+          const double SG[3] = {S[0] * G[0] + S[3] * G[1] + S[4] * G[2], S[3] * G[0] + S[1] * G[1] + S[5] * G[2],
+                                S[4] * G[0] + S[5] * G[1] + S[2] * G[2]};
+          for (int c = 0; c < 3; ++c) y[c][z] += 0.5 * mu * (g2 + G[c] * G[c]) - ka * SG[c] * SG[c];
+        }
+      }
+    }
+    const int fid = m.bface_of[e];
+    if (fid >= 0) {
+      const double *fg = gv.face + (size_t)fid * NFACEGEO * P2;
+      for (int fq = 0; fq < P2; ++fq) {
+        const double phi = tb.B[fq % P][i] * tb.B[fq / P][j];
+        const double bw = beta[fid] * fg[fq] * phi * phi;
+        for (int c = 0; c < 3; ++c) {
+          const double nc = fg[(1 + c) * P2 + fq];
+          y[c][0] += bw * (1.0 - nc * nc);
+        }
+      }
+    }
+  }
+  // lumped -M(1/mu): thread t holds the points of x-line t, reduce over the element's threads
+  pressure_reduce<T, P>(part, w, t, act, act ? dp + e * NP : nullptr);
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb2, t, act);
+  evec_store<T, P>(ev, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
+}
+
 // Geometry at upload (FP64).  mode 0: classify (flags bit0 not column-mapped, bit1 not
 // affine, bit2 det J <= 0 or not finite, bit3 degenerate basal face).  mode 1: store
 // affine data.  mode 2: store column data.  Face data are stored in modes 1 and 2.
@@ -1031,7 +1133,7 @@ __global__ void k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int64_t i = c * N + n;
-    y[i] = dm[i] ? xm[i] : (f ? sv[c] - f[i] : sv[c]);
+    y[i] = dm[i] ? (xm ? xm[i] : T(1)) : (f ? sv[c] - f[i] : sv[c]);
   }
 }
 
@@ -1127,6 +1229,27 @@ hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, con
   NSMF_RS(3, GEO_AFFINE) NSMF_RS(3, GEO_COLUMN) NSMF_RS(4, GEO_AFFINE) NSMF_RS(4, GEO_COLUMN)
   NSMF_RS(5, GEO_AFFINE) NSMF_RS(5, GEO_COLUMN)
 #undef NSMF_RS
+  return hipErrorInvalidValue;
+}
+
+template <int P, int GEO>
+static hipError_t diag_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+                          const double *st, const double *beta, double *ev, double *dp) {
+  auto tb = make_tab<double, P>(h, false);
+  auto tb2 = tb;
+  for (int hh = 0; hh < 2; ++hh)
+    for (int i = 0; i < P; ++i)
+      for (int k = 0; k < P; ++k) tb2.I[hh][i][k] = tb.I[hh][i][k] * tb.I[hh][i][k];
+  hipLaunchKernelGGL((k_diag<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, tb, tb2, st, beta, ev, dp);
+  return hipGetLastError();
+}
+hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+                       const double *st, const double *beta, double *ev, double *dp) {
+#define NSMF_DG(PP, GG) \
+  if (P == PP && geo == GG) return diag_pg<PP, GG>(s, m, g, h, st, beta, ev, dp);
+  NSMF_DG(3, GEO_AFFINE) NSMF_DG(3, GEO_COLUMN) NSMF_DG(4, GEO_AFFINE) NSMF_DG(4, GEO_COLUMN)
+  NSMF_DG(5, GEO_AFFINE) NSMF_DG(5, GEO_COLUMN)
+#undef NSMF_DG
   return hipErrorInvalidValue;
 }
 

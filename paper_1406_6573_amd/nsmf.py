@@ -25,7 +25,8 @@ STATUS = {0: "NSMF_OK", -1: "NSMF_EINVAL", -2: "NSMF_EHIP", -3: "NSMF_EMESH", -4
 EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh", "nsmf_set_params",
             "nsmf_set_state", "nsmf_residual", "nsmf_jacobian_apply", "nsmf_residual_vjp", "nsmf_query",
             "nsmf_geometry_kind", "nsmf_set_kernel_timing", "nsmf_kernel_time", "nsmf_last_error",
-            "nsmf_version"]
+            "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
+            "nsmf_vec_convert"]
 
 
 class NsmfError(RuntimeError):
@@ -73,6 +74,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_last_error.argtypes = [vp]
     lib.nsmf_last_error.restype = ctypes.c_char_p
     lib.nsmf_version.restype = ctypes.c_char_p
+    i64, dbl, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.nsmf_jacobi_diag.argtypes = [vp, ci, vp, vp]
+    lib.nsmf_vec_dots.argtypes = [vp, ci, i64, ci, vp, i64, vp, vp]
+    lib.nsmf_vec_gemv.argtypes = [vp, ci, i64, ci, vp, i64, vp, dbl, vp]
+    lib.nsmf_vec_axpby.argtypes = [vp, ci, i64, dbl, vp, dbl, vp]
+    lib.nsmf_vec_mul.argtypes = [vp, ci, i64, vp, vp, vp]
+    lib.nsmf_vec_convert.argtypes = [vp, i64, ci, vp, vp]
     _lib = lib
     return lib
 
@@ -210,6 +218,54 @@ class Engine:
         self._check(self.lib.nsmf_residual_vjp(self.h, prec, _ptr(w_u), _ptr(w_p), _ptr(g_u), _ptr(g_p),
                                                _ptr(g_A), _ptr(g_b)))
         return g_u, g_p, g_A, g_b
+
+    def jacobi_diag(self, invert=False, out=None):
+        """Block-Jacobi data at the state: (d_u [3, n_nodes], d_p [n_el, n_p]) in FP64, or their
+        reciprocals with invert=True."""
+        torch = self.torch
+        sz = self.sizes
+        if out is None:
+            out = (torch.empty((3, sz["n_nodes"]), dtype=torch.float64, device=self.dev),
+                   torch.empty((sz["n_el"], sz["n_p"]), dtype=torch.float64, device=self.dev))
+        d_u, d_p = out
+        self._check(self.lib.nsmf_jacobi_diag(self.h, 1 if invert else 0, _ptr(d_u), _ptr(d_p)))
+        return d_u, d_p
+
+    # Krylov vector kernels: 1D device tensors (float64 or float32), FP64 accumulation
+    @staticmethod
+    def _prec_of(t):
+        import torch
+        if t.dtype == torch.float64:
+            return 0
+        if t.dtype == torch.float32:
+            return 1
+        raise ValueError("vectors must be float64 or float32")
+
+    def vec_dots(self, V, k, w, h):
+        """h[:k] = V[:k] @ w  (V: [rows, n] contiguous, h: float64 device [>= k])."""
+        prec = self._prec_of(w)
+        self._check(self.lib.nsmf_vec_dots(self.h, prec, w.numel(), int(k), _ptr(V), V.stride(0), _ptr(w), _ptr(h)))
+
+    def vec_gemv(self, V, k, h, alpha, w):
+        """w += alpha * V[:k].T @ h[:k]."""
+        prec = self._prec_of(w)
+        self._check(self.lib.nsmf_vec_gemv(self.h, prec, w.numel(), int(k), _ptr(V), V.stride(0), _ptr(h),
+                                           float(alpha), _ptr(w)))
+
+    def vec_axpby(self, a, x, b, y):
+        """y = a x + b y."""
+        self._check(self.lib.nsmf_vec_axpby(self.h, self._prec_of(y), y.numel(), float(a), _ptr(x), float(b),
+                                            _ptr(y)))
+
+    def vec_mul(self, d, x, z):
+        """z = d * x (d float64)."""
+        self._check(self.lib.nsmf_vec_mul(self.h, self._prec_of(z), z.numel(), _ptr(d), _ptr(x), _ptr(z)))
+
+    def vec_convert(self, x, out):
+        """out = x converted between float64 and float32."""
+        import torch
+        to32 = 1 if out.dtype == torch.float32 else 0
+        self._check(self.lib.nsmf_vec_convert(self.h, x.numel(), to32, _ptr(x), _ptr(out)))
 
     def set_kernel_timing(self, enable: bool):
         self._check(self.lib.nsmf_set_kernel_timing(self.h, 1 if enable else 0))

@@ -1,0 +1,195 @@
+"""Newton-Krylov driver on the engine (Sec. 4.1-4.2 of the paper).
+
+Each Newton step linearises at (u, p), evaluates the FP64 residual, builds the
+block-Jacobi preconditioner (diagonal of F, lumped -M(1/mu) for the Schur block)
+and solves J_c d = -r with right-preconditioned FGMRES(m) using classical
+Gram-Schmidt with a second pass.  A backtracking line search on ||r|| accepts
+the step.  Every vector operation runs in the engine's kernels (multi-dots with
+FP64 accumulation, basis combinations, scaling); the host holds only the small
+Hessenberg least-squares problem.
+
+Precision modes:
+* "fp64": FP64 Krylov basis and FP64 Jacobian applies;
+* "mixed": FP32 Krylov basis and FP32 Jacobian applies, inner products
+  accumulated in FP64, FP64 right-hand side and FP64 outer refinement of the
+  correction (d += FGMRES_32(b - J_64 d) for ``refine`` cycles).
+
+The preconditioner is a plain fallback (the paper's AMG is not part of this
+engine); block Jacobi is not h-robust, so convergence per Krylov iteration
+degrades with mesh size and aspect ratio.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+
+@dataclass
+class SolveStats:
+    newton_residuals: list = field(default_factory=list)
+    linear_reductions: list = field(default_factory=list)
+    krylov_iterations: list = field(default_factory=list)
+    step_lengths: list = field(default_factory=list)
+    seconds: float = 0.0
+
+
+class NewtonKrylov:
+    def __init__(self, engine, restart: int = 50, precision: str = "fp64", refine: int = 1):
+        if restart + 1 > 64:
+            raise ValueError("restart must be at most 63")
+        self.eng, self.m, self.precision, self.refine = engine, restart, precision, refine
+        sz = engine.sizes
+        self.N, self.n_el, self.n_p = sz["n_nodes"], sz["n_el"], sz["n_p"]
+        self.n = 3 * self.N + self.n_el * self.n_p
+        dev = engine.dev
+        kt = torch.float64 if precision == "fp64" else torch.float32
+        self.kt = kt
+        self.V = torch.empty((restart + 1, self.n), dtype=kt, device=dev)
+        self.Z = torch.empty((restart, self.n), dtype=kt, device=dev)
+        self.h = torch.empty(64, dtype=torch.float64, device=dev)
+        self.minv = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.w64 = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.r64 = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.d64 = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.tmp = torch.empty(self.n, dtype=kt, device=dev)
+
+    # ------------------------------------------------------------ views
+    def split(self, x):
+        return x[:3 * self.N].view(3, self.N), x[3 * self.N:].view(self.n_el, self.n_p)
+
+    def apply(self, x, y):
+        """y = J_c x in the precision of x."""
+        prec = "fp64" if x.dtype == torch.float64 else "fp32"
+        self.eng.jacobian_apply(*self.split(x), prec, out=self.split(y))
+
+    def norm(self, x):
+        self.eng.vec_dots(x.view(1, -1), 1, x, self.h)
+        return math.sqrt(max(float(self.h[0]), 0.0))
+
+    # ------------------------------------------------------------ FGMRES
+    def fgmres(self, b, x, tol):
+        """Approximately solve J x = b (vectors of the Krylov precision), x += correction.
+        Returns (iterations, residual estimate / ||b||)."""
+        eng, V, Z, m = self.eng, self.V, self.Z, self.m
+        w = V[0]
+        self.apply(x, w)
+        eng.vec_axpby(1.0, b, -1.0, w)                   # r = b - J x, stored in V[0]
+        beta = self.norm(w)
+        bnorm = self.norm(b)
+        if beta == 0.0 or bnorm == 0.0:
+            return 0, 0.0
+        eng.vec_axpby(0.0, w, 1.0 / beta, w)
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            eng.vec_mul(self.minv, V[j], Z[j])             # z_j = M^-1 v_j
+            wj = V[j + 1]
+            self.apply(Z[j], wj)
+            hcol = np.zeros(j + 2)
+            for _ in range(2):                             # classical Gram-Schmidt, twice
+                eng.vec_dots(V, j + 1, wj, self.h)
+                eng.vec_gemv(V, j + 1, self.h, -1.0, wj)
+                hcol[:j + 1] += self.h[:j + 1].cpu().numpy()
+            hn = self.norm(wj)
+            hcol[j + 1] = hn
+            if hn > 0.0:
+                eng.vec_axpby(0.0, wj, 1.0 / hn, wj)
+            for i in range(j):                             # apply previous Givens rotations
+                t = cs[i] * hcol[i] + sn[i] * hcol[i + 1]
+                hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1]
+                hcol[i] = t
+            rho = math.hypot(hcol[j], hcol[j + 1])
+            cs[j], sn[j] = (hcol[j] / rho, hcol[j + 1] / rho) if rho > 0 else (1.0, 0.0)
+            hcol[j], hcol[j + 1] = rho, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            H[:j + 2, j] = hcol
+            k = j + 1
+            if abs(g[j + 1]) <= tol * bnorm or hn == 0.0:
+                break
+        y = np.linalg.solve(np.triu(H[:k, :k]), g[:k]) if k else np.zeros(0)
+        if k:
+            self.h[:k].copy_(torch.from_numpy(y))
+            eng.vec_gemv(Z, k, self.h, 1.0, x)            # x += Z y
+        return k, abs(g[k]) / bnorm
+
+    def linear_solve(self, rhs64, tol):
+        """d64 = approx J^-1 rhs64 (FP64 in and out)."""
+        eng = self.eng
+        self.d64.zero_()
+        if self.precision == "fp64":
+            its, red = self.fgmres(rhs64, self.d64, tol)
+            return its, red
+        its = 0
+        for _ in range(self.refine):                       # FP64 outer refinement of the correction
+            self.apply(self.d64, self.w64)
+            eng.vec_axpby(1.0, rhs64, 0.0, self.r64)
+            eng.vec_axpby(-1.0, self.w64, 1.0, self.r64)  # r = rhs - J_64 d
+            b32 = self.V[0].new_empty(self.n)
+            eng.vec_convert(self.r64, b32)
+            x32 = self.tmp
+            x32.zero_()
+            k, _ = self.fgmres(b32, x32, tol)
+            its += k
+            eng.vec_convert(x32, self.w64)
+            eng.vec_axpby(1.0, self.w64, 1.0, self.d64)
+        self.apply(self.d64, self.w64)
+        eng.vec_axpby(1.0, rhs64, 0.0, self.r64)
+        eng.vec_axpby(-1.0, self.w64, 1.0, self.r64)
+        return its, self.norm(self.r64) / max(self.norm(rhs64), 1e-300)
+
+    # ------------------------------------------------------------ Newton
+    def residual_vec(self, out):
+        ru, rp = self.split(out)
+        self.eng.residual(out=(ru, rp))
+        return out
+
+    def solve(self, u, p, n_newton=5, lin_tol=1e-8, max_backtrack=6, verbose=False):
+        """Newton iterations from (u, p) (FP64 tensors, updated in place)."""
+        eng, st = self.eng, SolveStats()
+        t0 = time.perf_counter()
+        x = torch.cat([u.reshape(-1), p.reshape(-1)])
+        r = torch.empty_like(x)
+        trial = torch.empty_like(x)
+        xu, xp = self.split(x)
+        eng.set_state(xu, xp)
+        self.residual_vec(r)
+        rn = self.norm(r)
+        st.newton_residuals.append(rn)
+        for it in range(n_newton):
+            mu, mp = self.split(self.minv)
+            eng.jacobi_diag(invert=True, out=(mu, mp))
+            eng.vec_axpby(0.0, r, -1.0, r)                  # rhs = -r
+            its, red = self.linear_solve(r, lin_tol)
+            st.krylov_iterations.append(its)
+            st.linear_reductions.append(red)
+            alpha = 1.0
+            for _ in range(max_backtrack + 1):               # backtracking on ||r||
+                eng.vec_axpby(1.0, x, 0.0, trial)
+                eng.vec_axpby(alpha, self.d64, 1.0, trial)
+                tu, tp = self.split(trial)
+                eng.set_state(tu, tp)
+                self.residual_vec(r)
+                rt = self.norm(r)
+                if rt <= (1.0 - 1e-4 * alpha) * rn:
+                    break
+                alpha *= 0.5
+            eng.vec_axpby(1.0, trial, 0.0, x)
+            rn = rt
+            st.newton_residuals.append(rn)
+            st.step_lengths.append(alpha)
+            if verbose:
+                print(f"[newton {self.precision}] step {it + 1}: |r| = {rn:.6e}, krylov {its}, "
+                      f"linear reduction {red:.2e}, alpha {alpha}", flush=True)
+        u.copy_(self.split(x)[0])
+        p.copy_(self.split(x)[1])
+        torch.cuda.synchronize()
+        st.seconds = time.perf_counter() - t0
+        return st

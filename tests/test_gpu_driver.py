@@ -1,0 +1,176 @@
+"""Block-Jacobi data, Krylov vector kernels and the Newton/FGMRES driver on the GPU."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from gpu_common import small_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def setup(torch, case):
+    from paper_1406_6573_amd import Engine
+    eng = Engine()
+    eng.upload_mesh(case["mesh"])
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    eng.set_params(case["n"], case["eps"], case["B0"], case.get("body", (0, 0, 0)), t(case["logA"]), t(case["beta"]))
+    eng.set_state(t(case["u"]), t(case["p"]))
+    return eng, t
+
+
+@pytest.mark.parametrize("k,mapped", [(2, False), (3, True), (4, False)])
+def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped):
+    """d_u = sum_e sum_a R_e[a, n]^2 F_e[aa] (exact diagonal of F on conforming parts), 1 on masked
+    rows; d_p = -sum_q w detJ psi_m^2 / mu."""
+    from oracle import StokesOracle
+    torch = torch_cuda
+    case = small_case(k, mapped=mapped)
+    m = case["mesh"]
+    eng, t = setup(torch, case)
+    d_u, d_p = eng.jacobi_diag()
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"])
+    o.set_state(case["u"], case["p"])
+    A, _ = o.element_matrices()
+    S = o.S
+    dA = np.stack([np.diagonal(A, axis1=1, axis2=2)[:, c * S:(c + 1) * S].reshape(-1) for c in range(3)])
+    R2 = o.R.multiply(o.R)
+    ref_u = np.stack([R2.T @ dA[c] for c in range(3)])
+    msk = m.dmask.astype(bool)
+    ref_u[msk] = 1.0
+    ref_p = -np.einsum("eq,qm->em", o.W / o.mu, o.ref.Psi ** 2)
+    eu = np.max(np.abs(d_u.cpu().numpy() - ref_u) / np.abs(ref_u))
+    ep = np.max(np.abs(d_p.cpu().numpy() - ref_p) / np.abs(ref_p))
+    print(f"[gpu] jacobi diag k={k} mapped={mapped}: rel err u {eu:.2e} p {ep:.2e}", flush=True)
+    assert eu < 1e-12 and ep < 1e-12
+    # conforming slots: equals the assembled diagonal of J_c
+    if not (m.cmask >> 3).any():
+        assert np.allclose(ref_u.ravel(), o.jacobian().diagonal()[:3 * m.n_nodes], rtol=1e-13)
+    inv_u, inv_p = eng.jacobi_diag(invert=True)
+    assert torch.allclose(inv_u * d_u, torch.ones_like(d_u), rtol=1e-15, atol=0)
+    eng.close()
+
+
+def test_vector_kernels(torch_cuda):
+    torch = torch_cuda
+    from paper_1406_6573_amd import Engine
+    eng = Engine()
+    eng.upload_mesh(small_case(2)["mesh"])
+    g = torch.Generator(device="cuda").manual_seed(0)
+    n, k = 100003, 7
+    for dt in (torch.float64, torch.float32):
+        V = torch.rand((k, n), dtype=dt, device="cuda", generator=g) - 0.5
+        w = torch.rand(n, dtype=dt, device="cuda", generator=g) - 0.5
+        h = torch.empty(64, dtype=torch.float64, device="cuda")
+        eng.vec_dots(V, k, w, h)
+        ref = (V.double() @ w.double())
+        assert torch.allclose(h[:k], ref, rtol=1e-12, atol=1e-12)
+        w2 = w.clone()
+        eng.vec_gemv(V, k, h, -0.5, w2)
+        ref2 = (w.double() - 0.5 * (V.double().T @ h[:k]))
+        assert torch.allclose(w2.double(), ref2, rtol=1e-6 if dt == torch.float32 else 1e-13, atol=1e-6)
+        y = w.clone()
+        eng.vec_axpby(2.0, V[0], -1.0, y)
+        assert torch.allclose(y, 2.0 * V[0] - w)
+        d = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
+        z = torch.empty_like(w)
+        eng.vec_mul(d, w, z)
+        assert torch.allclose(z.double(), d * w.double(), rtol=1e-6)
+    x = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
+    x32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    eng.vec_convert(x, x32)
+    assert torch.equal(x32, x.float())
+    eng.close()
+
+
+def test_newton_fgmres_against_oracle(torch_cuda):
+    """One Newton step on a small dome-like case: the driver's reported linear reduction is the
+    true one (oracle Jacobian), and its next residual equals the oracle residual there."""
+    torch = torch_cuda
+    from oracle import StokesOracle
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    case = small_case(2, mapped=True, nx=3, ny=3, nz=2, body=(0.0, 0.0, -1.0))
+    m = case["mesh"]
+    eng, t = setup(torch, case)
+    u, p = t(case["u"]), t(case["p"])
+    u0, p0 = u.clone(), p.clone()
+    nk = NewtonKrylov(eng, restart=40, precision="fp64")
+    st = nk.solve(u, p, n_newton=1, lin_tol=1e-12)
+    d = nk.d64.cpu().numpy()
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=(0.0, 0.0, -1.0))
+    o.set_state(case["u"], case["p"])
+    K = o.jacobian()
+    r0 = np.concatenate([a.ravel() for a in o.residual()])
+    true_red = np.linalg.norm(K @ d + r0) / np.linalg.norm(r0)
+    print(f"[gpu] newton step: |r0| {st.newton_residuals[0]:.6e} (oracle {np.linalg.norm(r0):.6e}), "
+          f"krylov {st.krylov_iterations[0]}, reported reduction {st.linear_reductions[0]:.3e}, true {true_red:.3e}",
+          flush=True)
+    assert abs(st.newton_residuals[0] - np.linalg.norm(r0)) < 1e-12 * np.linalg.norm(r0)
+    assert abs(st.linear_reductions[0] - true_red) < 1e-6 * max(true_red, 1e-8) + 1e-10
+    o.set_state(u.cpu().numpy(), p.cpu().numpy())
+    r1 = np.linalg.norm(np.concatenate([a.ravel() for a in o.residual()]))
+    assert abs(st.newton_residuals[1] - r1) < 1e-10 * r1
+    assert st.newton_residuals[1] < st.newton_residuals[0]
+    eng.close()
+
+
+def test_newton_mixed_matches_fp64(torch_cuda):
+    """Equal Krylov budgets (one FGMRES(50) cycle per Newton step): the mixed path (FP32 Krylov,
+    FP64 dots and right-hand side) follows the FP64 Newton trajectory."""
+    torch = torch_cuda
+    from meshgen import make_config
+    from paper_1406_6573_amd import Engine
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    w = make_config(5, nx=32, ny=32, nz=2)
+    m = w.mesh
+    res = {}
+    for prec in ("fp64", "mixed"):
+        eng = Engine()
+        eng.upload_mesh(m)
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+        eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
+        u, p = t(w.u), t(w.p)
+        nk = NewtonKrylov(eng, restart=50, precision=prec, refine=1)
+        st = nk.solve(u, p, n_newton=3, lin_tol=1e-10, verbose=True)
+        res[prec] = st.newton_residuals
+        eng.close()
+    a, b = np.array(res["fp64"]), np.array(res["mixed"])
+    print("[gpu] newton residuals fp64", a, "mixed", b, flush=True)
+    assert np.all(np.diff(a) < 0) and np.all(np.diff(b) < 0)
+    assert np.max(np.abs(a - b) / a) < 1e-3
+
+
+def test_mixed_refinement_reaches_fp64_accuracy(torch_cuda):
+    """FP32 inner FGMRES + FP64 outer refinement solves J d = b to FP64-level accuracy (beyond what
+    FP32 arithmetic alone can give), checked against a direct solve with the oracle's Jacobian."""
+    torch = torch_cuda
+    import scipy.sparse.linalg as spla
+    from oracle import StokesOracle
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    case = small_case(2, mapped=True, nx=2, ny=2, nz=1, frac=0.5, L=20.0)
+    m = case["mesh"]
+    eng, t = setup(torch, case)
+    nk = NewtonKrylov(eng, restart=60, precision="mixed", refine=40)
+    mu, mp = nk.split(nk.minv)
+    eng.jacobi_diag(invert=True, out=(mu, mp))
+    rng = np.random.default_rng(3)
+    b = rng.uniform(-1, 1, m.n_dof)
+    b[:3 * m.n_nodes][m.dmask.ravel().astype(bool)] = 0.0
+    its, red = nk.linear_solve(t(b), 1e-7)
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"])
+    o.set_state(case["u"], case["p"])
+    K = o.jacobian().tocsc()
+    d_ref = spla.spsolve(K, b)
+    d = nk.d64.cpu().numpy()
+    err = np.linalg.norm(d - d_ref) / np.linalg.norm(d_ref)
+    true_res = np.linalg.norm(K @ d - b) / np.linalg.norm(b)
+    print(f"[gpu] mixed refinement: {its} FP32 Krylov iterations, residual {red:.2e} (oracle {true_res:.2e}), "
+          f"solution error vs direct solve {err:.2e}", flush=True)
+    assert true_res < 1e-9 and err < 1e-6
