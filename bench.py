@@ -83,6 +83,38 @@ def cpu_baseline(seed=0):
                        f"({m.n_dof / ((t2 - t1) / reps) / 1e9:.4f} GDoF/s)")}
 
 
+def run_newton(args, w, dev, n_newton=5, restart=50):
+    """Newton driver on the workload: FP64 and mixed precision with equal Krylov budgets."""
+    import torch
+    from paper_1406_6573_amd import Engine
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    m = w.mesh
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        eng = Engine(0)
+        eng.upload_mesh(m)
+        eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
+        u, p = t(w.u), t(w.p)
+        nk = NewtonKrylov(eng, restart=restart, precision=prec, refine=1)
+        st = nk.solve(u, p, n_newton=n_newton, lin_tol=1e-8, verbose=True)
+        out[prec] = dict(seconds=st.seconds, newton_residuals=st.newton_residuals,
+                         linear_reductions=st.linear_reductions, krylov_iterations=st.krylov_iterations,
+                         step_lengths=st.step_lengths)
+        eng.close()
+        del nk
+        torch.cuda.empty_cache()
+    a, b = np.array(out["fp64"]["newton_residuals"]), np.array(out["mixed"]["newton_residuals"])
+    rec = {"metric": "Newton-Krylov solve: 5 Newton steps x FGMRES(50), block Jacobi, FP64 vs mixed",
+           "value": out["fp64"]["seconds"] / out["mixed"]["seconds"], "unit": "speedup mixed vs fp64",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"config{args.config}", "n_dof": m.n_dof, "n_el": m.n_el, "k": m.k},
+           "residual_reduction_fp64": float(a[-1] / a[0]), "residual_reduction_mixed": float(b[-1] / b[0]),
+           "max_rel_diff_newton_residuals": float(np.max(np.abs(a - b) / a)), "fp64": out["fp64"],
+           "mixed": out["mixed"]}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +122,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--newton", action="store_true",
+                    help="instead of the apply benchmark, run the Newton/FGMRES driver (5 steps x FGMRES(50)) "
+                         "in FP64 and in mixed precision and print one JSON line")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (reference for HBM counters)")
     args = ap.parse_args()
@@ -125,6 +160,10 @@ def main():
     sz = dict(eng.sizes)
     sz["k"] = m.k
     geo = eng.geometry_kind()
+    if args.newton:
+        eng.close()
+        run_newton(args, w, dev)
+        return
     print(f"[bench] n_el={sz['n_el']} n_dof={sz['n_dof']} geometry={geo}", file=sys.stderr, flush=True)
 
     def timed(fn, steps, warm):

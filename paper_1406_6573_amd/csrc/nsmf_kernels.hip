@@ -433,16 +433,34 @@ __device__ __forceinline__ void to_ref(const QpGeo<T, P, GEO> &g, int i, const T
 }
 
 // ---------------------------------------------------------------- pressure basis
+// Exponents (i, j, l) of the pressure basis, i+j+l <= k-1 ordered by (i+j+l, l, j, i), as
+// compile-time constants so that register arrays indexed by them stay in registers.
+template <int P> struct PExp {
+  static constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  int e[NP][3];
+  constexpr PExp() : e{} {
+    int m = 0;
+    for (int d = 0; d < P - 1; ++d)
+      for (int l = 0; l <= d; ++l)
+        for (int j = 0; j <= d - l; ++j) {
+          e[m][0] = d - l - j;
+          e[m][1] = j;
+          e[m][2] = l;
+          ++m;
+        }
+  }
+};
 // x-line thread (j, z): p(i) = sum_m xp[m] L_{e0}(g_i) L_{e1}(g_j) L_{e2}(g_z)
 template <typename T, int P>
 __device__ __forceinline__ void pressure_interp(const T *xp, const Tab<T, P> &tb, int t, T (&pq)[P]) {
   constexpr int NP = (P - 1) * P * (P + 1) / 6;
   const int j = t % P, z = t / P;
+  constexpr PExp<P> pe{};
   T pa[P - 1];
 #pragma unroll
   for (int a = 0; a < P - 1; ++a) pa[a] = 0;
 #pragma unroll
-  for (int m = 0; m < NP; ++m) pa[tb.pe[m][0]] += xp[m] * tb.L[tb.pe[m][1]][j] * tb.L[tb.pe[m][2]][z];
+  for (int m = 0; m < NP; ++m) pa[pe.e[m][0]] += xp[m] * tb.L[pe.e[m][1]][j] * tb.L[pe.e[m][2]][z];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     T s = 0;
@@ -465,8 +483,9 @@ __device__ __forceinline__ void pressure_test(const T (&d)[P], const Tab<T, P> &
     for (int i = 0; i < P; ++i) s += tb.L[a][i] * d[i];
     qa[a] = s;
   }
+  constexpr PExp<P> pe{};
 #pragma unroll
-  for (int m = 0; m < NP; ++m) part[m] = qa[tb.pe[m][0]] * tb.L[tb.pe[m][1]][j] * tb.L[tb.pe[m][2]][z];
+  for (int m = 0; m < NP; ++m) part[m] = qa[pe.e[m][0]] * tb.L[pe.e[m][1]][j] * tb.L[pe.e[m][2]][z];
 }
 
 // Sum the NP partials over the P*P threads of each element and store -sum into y_p[e].
@@ -614,11 +633,16 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   double *redl = red + els * P2;
   const int64_t N = m.n_nodes;
-  // linearisation data of the thread's P points, requested first so that its latency
-  // overlaps the gather and the forward sweeps (the block's slice is always allocated)
+  // linearisation data of the thread's P points; in FP32 requested first so that its latency
+  // overlaps the gather and the forward sweeps (in FP64 the extra live registers would cost
+  // occupancy, so it is loaded just before the quadrature-point step).  The block's slice is
+  // always allocated, also for threads without an element.
+  constexpr bool kEarlyState = sizeof(T) == 4;
   T stv[NSTATE][P];
+  if constexpr (kEarlyState) {
 #pragma unroll
-  for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
+    for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
+  }
 
   const uint32_t cm = act ? m.cmask[e] : 0u;
   T v[3][P];
@@ -643,6 +667,10 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
   }
   T dw[P];
   double gA = 0.0;
+  if constexpr (!kEarlyState) {
+#pragma unroll
+    for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
+  }
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     if (!act) { dw[i] = 0; continue; }
@@ -947,8 +975,10 @@ k_diag(MeshView m, GeoView<double> gv, Tab<double, P> tb, Tab<double, P> tb2, co
         // thread accumulates the points of its own tq = t for the lumped 1/mu mass
         if (tq == t) {
           const double g = wd * wd / mu;
+          constexpr PExp<P> pe{};
+#pragma unroll
           for (int mm = 0; mm < NP; ++mm) {
-            const double psi = tb.L[tb.pe[mm][0]][qx] * tb.L[tb.pe[mm][1]][qy] * tb.L[tb.pe[mm][2]][qz];
+            const double psi = tb.L[pe.e[mm][0]][qx] * tb.L[pe.e[mm][1]][qy] * tb.L[pe.e[mm][2]][qz];
             part[mm] += g * psi * psi;
           }
         }
@@ -999,6 +1029,7 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   __shared__ T smem[E * Ws<T, P>::ES];
   __shared__ T ref0[E][3];
+  __shared__ T xmag[E];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = (int64_t)lb * E + el;
@@ -1013,8 +1044,10 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
   // work with coordinates relative to the first gathered node: derivatives are unchanged,
   // and neither the hanging interpolation nor the differentiation sees large absolute
   // coordinates (whose rounding would otherwise dominate the Jacobian of distant elements)
-  if (act && t == 0)
+  if (act && t == 0) {
+    xmag[els] = fabs(v[0][0]) + fabs(v[1][0]) + fabs(v[2][0]);
     for (int c = 0; c < 3; ++c) ref0[els][c] = v[c][0];
+  }
   __syncthreads();
   if (act)
     for (int c = 0; c < 3; ++c)
@@ -1042,8 +1075,10 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
       const T det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+      // the input coordinates carry rounding relative to their absolute size (xmag), which
+      // the derivatives see amplified by the 1D derivative weights
       const T sc = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]);
-      const T tol = 1e-13 * sc;
+      const T tol = 1e-13 * sc + 1e-14 * xmag[els];
       if (!(det > 0) || !isfinite(det)) fl |= 4u;
       if (fabs(a[0][1]) > tol || fabs(a[0][2]) > tol || fabs(a[1][0]) > tol || fabs(a[1][2]) > tol ||
           fabs(a[0][0] - r00) > tol || fabs(a[1][1] - r11) > tol)

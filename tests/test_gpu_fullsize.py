@@ -1,0 +1,126 @@
+"""Parity at the workloads' full sizes, on sampled outputs.
+
+The oracle assembles only the elements incident to a random sample of velocity rows and pressure
+elements (the rows are then exact), at the full mesh sizes and in the engine's production launch
+configuration; properties that hold at any size (FP32 vs FP64 over all rows, symmetry) cover the
+rest.  For the VJP workload, parameter gradients are also checked by central finite differences
+(h = 1e-6) of the engine's own residual.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROWS = {2: (150, 40), 3: (40, 12), 4: (120, 40), 5: (200, 60)}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def sampled(mesh, rng, n_vel, n_pres):
+    nodes = rng.choice(mesh.n_nodes, n_vel, replace=False)
+    comps = rng.integers(0, 3, n_vel)
+    pel = rng.choice(mesh.n_el, n_pres, replace=False)
+    touch = np.isin(mesh.elem_nodes, nodes).any(axis=1)
+    elems = np.union1d(np.nonzero(touch)[0], pel)
+    return nodes, comps, pel, elems
+
+
+@pytest.mark.parametrize("cfg", [2, 3, 4, 5])
+def test_fullsize_sampled_parity(torch_cuda, cfg):
+    torch = torch_cuda
+    from meshgen import make_config
+    from oracle import StokesOracle
+    from paper_1406_6573_amd import Engine
+    w = make_config(cfg, n_dirs=1)
+    m = w.mesh
+    print(f"[gpu] full-size config{cfg}: n_el={m.n_el} n_dof={m.n_dof}", flush=True)
+    eng = Engine()
+    eng.upload_mesh(m)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
+    eng.set_state(t(w.u), t(w.p))
+    xu, xp = w.directions[0]
+    ru, rp = eng.residual()
+    yu, yp = eng.jacobian_apply(t(xu), t(xp))
+    y32u, y32p = eng.jacobian_apply(t(xu).float(), t(xp).float(), "fp32")
+    wu, wp = (w.adjoint if w.adjoint is not None else w.directions[0])
+    g_u, g_p, g_A, g_b = eng.residual_vjp(t(wu), t(wp))
+    torch.cuda.synchronize()
+    # FP32 vs FP64 over all rows
+    full64 = torch.cat([yu.reshape(-1), yp.reshape(-1)])
+    full32 = torch.cat([y32u.reshape(-1), y32p.reshape(-1)]).double()
+    e32 = float((full32 - full64).norm() / full64.norm())
+    print(f"  fp32 vs fp64 over all {full64.numel()} rows: rel {e32:.2e}", flush=True)
+    assert e32 < 1e-5
+    # sampled rows against the oracle
+    rng = np.random.default_rng(100 + cfg)
+    nodes, comps, pel, elems = sampled(m, rng, *ROWS[cfg])
+    o = StokesOracle(m, w.n, w.eps, w.B0, w.logA, w.beta, body=w.body, elems=elems)
+    o.set_state(w.u, w.p)
+    print(f"  oracle on {len(elems)} incident elements", flush=True)
+    N = m.n_nodes
+    vrows = comps * N + nodes
+    prow = (pel[:, None] * m.n_p + np.arange(m.n_p)[None, :]).ravel()
+    oru, orp = o.residual()
+    K = o.jacobian()
+    x = np.concatenate([xu.ravel(), xp.ravel()])
+    oy = K @ x
+    sc = abs(K) @ np.abs(x)
+    gy = np.concatenate([yu.cpu().numpy().ravel(), yp.cpu().numpy().ravel()])
+    rows = np.concatenate([vrows, 3 * N + prow])
+    e_j = np.max(np.abs(gy[rows] - oy[rows]) / sc[rows])
+    gr = np.concatenate([ru.cpu().numpy().ravel(), rp.cpu().numpy().ravel()])
+    orr = np.concatenate([oru.ravel(), orp.ravel()])
+    rmag = np.max(np.abs(orr[rows]))
+    e_r = np.max(np.abs(gr[rows] - orr[rows])) / rmag
+    og_u, og_p, og_A, og_b = o.vjp(wu, wp)
+    gg = np.concatenate([g_u.cpu().numpy().ravel(), g_p.cpu().numpy().ravel()])
+    ogg = np.concatenate([og_u.ravel(), og_p.ravel()])
+    wv = np.concatenate([np.asarray(wu).ravel(), np.asarray(wp).ravel()])
+    e_v = np.max(np.abs(gg[rows] - ogg[rows]) / (abs(K) @ np.abs(wv))[rows])
+    # logA gradient per element: a sum with cancellation over quadrature points; scale the error by the
+    # sum of the magnitudes of its terms, (1/n) sum_q |w detJ mu D0 : D(w)|
+    pos = np.searchsorted(o.elems, pel)
+    we = o.gather(wu)
+    Gw = np.einsum("esc,eqsi->eqci", we[pos], o.Gp[pos])
+    Dw = 0.5 * (Gw + np.swapaxes(Gw, 2, 3))
+    scale_A = np.sum(np.abs(o.W[pos] * o.mu[pos] * np.einsum("eqij,eqij->eq", o.D0[pos], Dw)), axis=1) / w.n
+    e_a = np.max(np.abs(g_A.cpu().numpy()[pel] - og_A[pel]) / np.maximum(scale_A, 1e-300))
+    print(f"  sampled rows: J scaled {e_j:.2e}, residual {e_r:.2e}, VJP u,p scaled {e_v:.2e}, logA {e_a:.2e}",
+          flush=True)
+    assert e_j < 1e-12 and e_r < 1e-12 and e_v < 1e-12 and e_a < 1e-12
+    if m.n_bface and len(o.fid):
+        fids = o.fid
+        gb = g_b.cpu().numpy()[fids]
+        e_b = np.max(np.abs(gb - og_b[fids]) / np.maximum(np.abs(og_b[fids]), 1e-300))
+        print(f"  beta gradient on {len(fids)} faces: rel {e_b:.2e}", flush=True)
+        assert e_b < 1e-11
+    if cfg == 4:
+        # central differences of <w, r> in logA and beta with the engine's own residual
+        def wr(logA, beta):
+            eng.set_params(w.n, w.eps, w.B0, w.body, t(logA), t(beta))
+            eng.set_state(t(w.u), t(w.p))
+            a, b = eng.residual()
+            return float((a * t(wu)).sum() + (b * t(wp)).sum())
+        h = 1e-6
+        for e in rng.choice(m.n_el, 3, replace=False):
+            la1, la0 = w.logA.copy(), w.logA.copy()
+            la1[e] += h
+            la0[e] -= h
+            fd = (wr(la1, w.beta) - wr(la0, w.beta)) / (2 * h)
+            print(f"  FD logA[{e}]: {fd:.8e} vs VJP {float(g_A[e]):.8e}", flush=True)
+            assert abs(fd - float(g_A[e])) < 1e-5 * abs(float(g_A[e])) + 1e-8 * abs(wr(w.logA, w.beta))
+        for f in rng.choice(m.n_bface, 3, replace=False):
+            b1, b0 = w.beta.copy(), w.beta.copy()
+            b1[f] += h
+            b0[f] -= h
+            fd = (wr(w.logA, b1) - wr(w.logA, b0)) / (2 * h)
+            print(f"  FD beta[{f}]: {fd:.8e} vs VJP {float(g_b[f]):.8e}", flush=True)
+            assert abs(fd - float(g_b[f])) < 1e-5 * abs(float(g_b[f])) + 1e-8 * abs(wr(w.logA, w.beta))
+    eng.close()
