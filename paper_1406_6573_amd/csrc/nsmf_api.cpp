@@ -46,7 +46,7 @@ struct nsmf_ctx {
   HostTables tab;
   DevBuf<uint32_t> en, cmask;
   DevBuf<int32_t> bface_of, inc_ptr;   // node -> first entry of its segment of the element vector
-  DevBuf<uint8_t> rank;               // slot -> position within its node's segment
+  DevBuf<int32_t> pos;                // element slot -> its entry in the element vector
   DevBuf<uint8_t> dmask;
   DevBuf<double> geo_el64, geo_qp64, face64;
   DevBuf<float> geo_el32, geo_qp32, face32;
@@ -79,8 +79,7 @@ struct nsmf_ctx {
     m.en = en.p;
     m.cmask = cmask.p;
     m.bface_of = bface_of.p;
-    m.inc_ptr = inc_ptr.p;
-    m.rank = rank.p;
+    m.pos = pos.p;
     m.n_inc = n_inc;
     m.n_el = n_el;
     m.n_nodes = n_nodes;
@@ -90,7 +89,7 @@ struct nsmf_ctx {
   GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p}; }
   GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p}; }
   void free_mesh() {
-    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); rank.free(); dmask.free(); ev.free();
+    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); pos.free(); dmask.free(); ev.free();
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
@@ -176,19 +175,17 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
     for (int64_t i = 0; i < 3 * N; ++i) dm[i] = m->dmask[i] ? 1 : 0;
   if (3 * N >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EINVAL, "3*n_nodes must fit in int32");
   // node-ordered element vector: node n owns entries [iptr[n], iptr[n+1]); slot (e, a) takes
-  // entry iptr[node] + rank[e][a], ranks in element order
+  // entry pos[e][a] = iptr[node] + (number of earlier slots of the same node, in element order)
   const int64_t n_inc = n_el * P3;
   if (n_inc >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EUNSUP, "mesh too large for int32 entries");
-  std::vector<int32_t> iptr((size_t)N + 1, 0);
-  std::vector<uint8_t> irank((size_t)n_inc);
+  std::vector<int32_t> iptr((size_t)N + 1, 0), ipos((size_t)n_inc);
   for (int64_t i = 0; i < n_inc; ++i) iptr[(words[i] & NODE_MASK) + 1]++;
   for (int64_t n = 0; n < N; ++n) {
-    if (iptr[n + 1] > 255) return ctx->fail(NSMF_EMESH, "a node is shared by more than 255 element slots");
     iptr[n + 1] += iptr[n];
   }
   {
-    std::vector<uint8_t> cnt((size_t)N, 0);
-    for (int64_t i = 0; i < n_inc; ++i) irank[i] = cnt[words[i] & NODE_MASK]++;
+    std::vector<int32_t> next(iptr.begin(), iptr.end() - 1);
+    for (int64_t i = 0; i < n_inc; ++i) ipos[i] = next[words[i] & NODE_MASK]++;
   }
   ctx->k = m->k;
   ctx->P = P;
@@ -207,7 +204,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->bface_of.alloc(n_el), "hipMalloc");
   NSMF_TRY(ctx, ctx->dmask.alloc(3 * N), "hipMalloc");
   NSMF_TRY(ctx, ctx->inc_ptr.alloc(iptr.size()), "hipMalloc");
-  NSMF_TRY(ctx, ctx->rank.alloc(irank.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->pos.alloc(ipos.size()), "hipMalloc");
   NSMF_TRY(ctx, ctx->ev.alloc((size_t)3 * n_inc), "hipMalloc");
   ctx->n_inc = n_inc;
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->en.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s), "copy");
@@ -215,7 +212,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->bface_of.p, bof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->dmask.p, dm.data(), 3 * N, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->inc_ptr.p, iptr.data(), iptr.size() * 4, hipMemcpyHostToDevice, s), "copy");
-  NSMF_TRY(ctx, hipMemcpyAsync(ctx->rank.p, irank.data(), irank.size(), hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->pos.p, ipos.data(), ipos.size() * 4, hipMemcpyHostToDevice, s), "copy");
 
   DevBuf<double> X;
   DevBuf<unsigned> flags;

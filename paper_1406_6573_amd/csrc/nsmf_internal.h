@@ -62,8 +62,7 @@ struct MeshView {
   const uint32_t *en;        // [n_el][P^3] node word (id | mask bits)
   const uint32_t *cmask;     // [n_el]
   const int32_t *bface_of;   // [n_el] basal face id or -1
-  const int32_t *inc_ptr;    // [n_nodes + 1] first incidence of each node in the node-ordered element vector
-  const uint8_t *rank;       // [n_el][P^3] position of the slot among its node's incidences
+  const int32_t *pos;        // [n_el][P^3] entry of each element slot in the node-ordered element vector
   int64_t n_el, n_nodes, n_inc;
   int nblocks;
 };

@@ -597,21 +597,24 @@ __device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t
 }
 
 // Element-vector store in node order: the result of element slot (e, a) for component c goes to
-// ev[c * n_inc + ptr[node] + rank], where ptr is the node's first incidence and rank the slot's
-// position among the node's incidences (both built at upload).  The assembly kernel then sums
-// contiguous segments.
+// ev[c * n_inc + pos[e][a]], pos being the slot's entry in its node's contiguous segment (built
+// at upload).  The entry indices are loaded with the connectivity, so the stores do not wait on
+// any dependent load; the assembly kernel then sums contiguous segments.
 template <typename T, int P>
-__device__ __forceinline__ void evec_store(T *ev, int64_t n_inc, const int32_t *__restrict__ ptr,
-                                           const uint8_t *__restrict__ rank_e, const uint32_t (&nw)[P], int t,
-                                           bool act, const T (&v)[3][P]) {
+__device__ __forceinline__ void evec_store(T *ev, int64_t n_inc, const int32_t (&pos)[P], bool act,
+                                           const T (&v)[3][P]) {
   if (!act || ev == nullptr) return;
+#pragma unroll
+  for (int z = 0; z < P; ++z)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ev[c * n_inc + pos[z]] = v[c][z];
+}
+
+template <int P>
+__device__ __forceinline__ void load_pos(const int32_t *__restrict__ pos_e, int t, bool act, int32_t (&pos)[P]) {
   constexpr int P2 = P * P;
 #pragma unroll
-  for (int z = 0; z < P; ++z) {
-    const int64_t k = (int64_t)ptr[nw[z] & NODE_MASK] + rank_e[t + P2 * z];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ev[c * n_inc + k] = v[c][z];
-  }
+  for (int z = 0; z < P; ++z) pos[z] = act ? pos_e[t + P2 * z] : 0;
 }
 
 // ================================================================= kernels
@@ -748,7 +751,9 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
     }
   }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
-  evec_store<T, P>(yu, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
+  int32_t pos[P];
+  load_pos<P>(m.pos + e * P3, t, act, pos);
+  evec_store<T, P>(yu, m.n_inc, pos, act, y);
 }
 
 // Linearisation point: per quadrature point mu' = w detJ mu, kappa, Sigma0 = mu' D(u)
@@ -847,6 +852,8 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
   uint32_t nw[P];
 #pragma unroll
   for (int z = 0; z < P; ++z) nw[z] = act ? m.en[e * P3 + t + P2 * z] : 0u;
+  int32_t pos[P];
+  load_pos<P>(m.pos + e * P3, t, act, pos);
 
   T fr[3][3][P], f0[3][P], dw[P];
   if (act) {
@@ -911,7 +918,7 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
       for (int c = 0; c < 3; ++c) y[c][0] += out[c];
   }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
-  evec_store<T, P>(ru, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
+  evec_store<T, P>(ru, m.n_inc, pos, act, y);
 }
 
 // Block-Jacobi data at the linearisation point (FP64).  Velocity: the diagonal of F per
@@ -938,6 +945,8 @@ k_diag(MeshView m, GeoView<double> gv, Tab<double, P> tb, Tab<double, P> tb2, co
   uint32_t nw[P];
 #pragma unroll
   for (int z = 0; z < P; ++z) nw[z] = act ? m.en[e * P3 + t + P2 * z] : 0u;
+  int32_t pos[P];
+  load_pos<P>(m.pos + e * P3, t, act, pos);
   T y[3][P];
   T part[NP];
 #pragma unroll
@@ -1015,7 +1024,7 @@ k_diag(MeshView m, GeoView<double> gv, Tab<double, P> tb, Tab<double, P> tb2, co
   // lumped -M(1/mu): thread t holds the points of x-line t, reduce over the element's threads
   pressure_reduce<T, P>(part, w, t, act, act ? dp + e * NP : nullptr);
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb2, t, act);
-  evec_store<T, P>(ev, m.n_inc, m.inc_ptr, m.rank + e * P3, nw, t, act, y);
+  evec_store<T, P>(ev, m.n_inc, pos, act, y);
 }
 
 // Geometry at upload (FP64).  mode 0: classify (flags bit0 not column-mapped, bit1 not
@@ -1158,8 +1167,24 @@ __global__ void k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   T s0 = 0, s1 = 0, s2 = 0;
-  const int32_t k1 = ptr[n + 1];
-  for (int32_t k = ptr[n]; k < k1; ++k) {
+  const int32_t k0 = ptr[n], k1 = ptr[n + 1];
+  // up to 8 entries (a vertex of a conforming hexahedral mesh) with all loads in flight, the rest
+  // (coarse nodes collecting hanging contributions) in a tail loop; fixed order either way
+  T a[3][8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const bool in = k0 + q < k1;
+    a[0][q] = in ? ev[k0 + q] : T(0);
+    a[1][q] = in ? ev[n_inc + k0 + q] : T(0);
+    a[2][q] = in ? ev[2 * n_inc + k0 + q] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    s0 += a[0][q];
+    s1 += a[1][q];
+    s2 += a[2][q];
+  }
+  for (int32_t k = k0 + 8; k < k1; ++k) {
     s0 += ev[k];
     s1 += ev[n_inc + k];
     s2 += ev[2 * n_inc + k];
