@@ -59,11 +59,11 @@ def measured_traffic(config_id):
 
 def cpu_baseline(seed=0):
     """The FP64 oracle as it stands: assemble the Jacobian and apply it once, on a reduced
-    sample of the same workload (12x12x2 columns, same element shape, 20% refined)."""
+    sample of the same workload (20x20x2 columns, same element shape, 20% refined)."""
     import threadpoolctl
     from meshgen import make_config
     from oracle import StokesOracle
-    w = make_config(2, seed=seed, nx=12, ny=12, nz=2)
+    w = make_config(2, seed=seed, nx=20, ny=20, nz=2)
     m = w.mesh
     t0 = time.perf_counter()
     o = StokesOracle(m, w.n, w.eps, w.B0, w.logA, w.beta)
@@ -77,7 +77,7 @@ def cpu_baseline(seed=0):
     t2 = time.perf_counter()
     threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] + [1])
     return {"value": m.n_dof / (t1 - t0) / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"slab 12x12x2 Q3xP2 (aspect 125, 20% refined), {m.n_el} elements, {m.n_dof} DoF: "
+            "sample": (f"slab 20x20x2 Q3xP2 (aspect 125, 20% refined), {m.n_el} elements, {m.n_dof} DoF: "
                        f"dense-quadrature element matrices + CSR assembly + one SpMV = {t1 - t0:.2f} s; "
                        f"SpMV alone with the assembled matrix {(t2 - t1) / reps * 1e3:.2f} ms "
                        f"({m.n_dof / ((t2 - t1) / reps) / 1e9:.4f} GDoF/s)")}
@@ -229,7 +229,7 @@ def main():
         "set_state_ms": ms_state, "residual_ms": ms_res, "vjp_fp64_ms": ms_vjp,
         "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach32 / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
-                     "kernel": "apply = k_apply<float,4,affine> + k_assemble<float>", "kernel_ms": out["fp32"]["kernel_ms"],
+                     "kernel": f"apply = k_apply<float,{sz['k'] + 1},{geo}> + k_assemble<float>", "kernel_ms": out["fp32"]["kernel_ms"],
                      "algorithmic_bytes": b32},
     }
     if not args.no_cpu_baseline:
