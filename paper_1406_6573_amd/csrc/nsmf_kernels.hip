@@ -1160,35 +1160,55 @@ k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode
 // One thread per node: sums the node's contiguous segment of the node-ordered element vector
 // (fixed order, so the result is deterministic).  Rows of Dirichlet-flagged components take the
 // value xm (x for the Jacobian, u for the residual); other rows subtract f when given.
+constexpr int ASM_NT = 256;
+constexpr int ASM_TILE = 4 * ASM_NT;
+
+// The entries of the block's nodes form one contiguous range [ptr[n0], ptr[n0 + NT]) of each
+// component plane of ev: it is streamed through LDS in tiles with coalesced loads, and each
+// thread sums its own node's segment from LDS in increasing slot order.
 template <typename T>
-__global__ void k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_inc,
-                           const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f,
-                           T *__restrict__ y) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+__global__ void __launch_bounds__(ASM_NT)
+k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_inc,
+           const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f, T *__restrict__ y) {
+  __shared__ T tile[3][ASM_TILE];
+  const int64_t n0 = (int64_t)blockIdx.x * ASM_NT;
+  const int64_t n = n0 + threadIdx.x;
+  const int64_t nend = n0 + ASM_NT < N ? n0 + ASM_NT : N;
+  const int32_t r0 = ptr[n0], r1 = ptr[nend];
+  int32_t k0 = 0, k1 = 0;
+  if (n < N) {
+    k0 = ptr[n];
+    k1 = ptr[n + 1];
+  }
   T s0 = 0, s1 = 0, s2 = 0;
-  const int32_t k0 = ptr[n], k1 = ptr[n + 1];
-  // up to 8 entries (a vertex of a conforming hexahedral mesh) with all loads in flight, the rest
-  // (coarse nodes collecting hanging contributions) in a tail loop; fixed order either way
-  T a[3][8];
+  for (int32_t c0 = r0; c0 < r1; c0 += ASM_TILE) {
+    const int32_t cn = r1 - c0 < ASM_TILE ? r1 - c0 : ASM_TILE;
+    T a[3][ASM_TILE / ASM_NT];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const bool in = k0 + q < k1;
-    a[0][q] = in ? ev[k0 + q] : T(0);
-    a[1][q] = in ? ev[n_inc + k0 + q] : T(0);
-    a[2][q] = in ? ev[2 * n_inc + k0 + q] : T(0);
-  }
+    for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
+      const int j = (int)threadIdx.x + u * ASM_NT;
+      const bool in = j < cn;
+      a[0][u] = in ? ev[c0 + j] : T(0);
+      a[1][u] = in ? ev[n_inc + c0 + j] : T(0);
+      a[2][u] = in ? ev[2 * n_inc + c0 + j] : T(0);
+    }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    s0 += a[0][q];
-    s1 += a[1][q];
-    s2 += a[2][q];
+    for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
+      const int j = (int)threadIdx.x + u * ASM_NT;
+      tile[0][j] = a[0][u];
+      tile[1][j] = a[1][u];
+      tile[2][j] = a[2][u];
+    }
+    __syncthreads();
+    const int32_t kb = k0 > c0 ? k0 : c0, ke = k1 < c0 + cn ? k1 : c0 + cn;
+    for (int32_t k = kb; k < ke; ++k) {
+      s0 += tile[0][k - c0];
+      s1 += tile[1][k - c0];
+      s2 += tile[2][k - c0];
+    }
+    __syncthreads();
   }
-  for (int32_t k = k0 + 8; k < k1; ++k) {
-    s0 += ev[k];
-    s1 += ev[n_inc + k];
-    s2 += ev[2 * n_inc + k];
-  }
+  if (n >= N) return;
   const T sv[3] = {s0, s1, s2};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1212,10 +1232,10 @@ static inline int grid1(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
                            const uint8_t *dm, const void *xm, const void *f, void *y) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, 256)), dim3(256), 0, s, N, ptr, (const double *)ev, n_inc,
+    hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const double *)ev, n_inc,
                        dm, (const double *)xm, (const double *)f, (double *)y);
   else
-    hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, 256)), dim3(256), 0, s, N, ptr, (const float *)ev, n_inc, dm,
+    hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev, n_inc, dm,
                        (const float *)xm, (const float *)f, (float *)y);
   return hipGetLastError();
 }
