@@ -48,6 +48,7 @@ struct nsmf_ctx {
   DevBuf<int32_t> bface_of, inc_ptr;   // node -> first entry of its segment of the element vector
   DevBuf<int32_t> pos;                // element slot -> its entry in the element vector
   DevBuf<uint8_t> dmask;
+  DevBuf<double> tabs;                // TabSet<P> of the mesh's degree
   DevBuf<double> geo_el64, geo_qp64, face64;
   DevBuf<float> geo_el32, geo_qp32, face32;
   // params
@@ -89,7 +90,7 @@ struct nsmf_ctx {
   GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p}; }
   GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p}; }
   void free_mesh() {
-    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); pos.free(); dmask.free(); ev.free();
+    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); pos.free(); dmask.free(); ev.free(); tabs.free();
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
@@ -213,6 +214,10 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->dmask.p, dm.data(), 3 * N, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->inc_ptr.p, iptr.data(), iptr.size() * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->pos.p, ipos.data(), ipos.size() * 4, hipMemcpyHostToDevice, s), "copy");
+  std::vector<double> tabset((tabset_bytes(P) + 7) / 8);
+  fill_tabset(ctx->tab, tabset.data());
+  NSMF_TRY(ctx, ctx->tabs.alloc(tabset.size()), "hipMalloc");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->tabs.p, tabset.data(), tabset.size() * 8, hipMemcpyHostToDevice, s), "copy");
 
   DevBuf<double> X;
   DevBuf<unsigned> flags;
@@ -221,7 +226,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipMemcpyAsync(X.p, m->coords, 3 * N * 8, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, launch_fill(s, flags.p, 1), "fill");
   MeshView mv = ctx->mesh_view();
-  NSMF_TRY(ctx, launch_geometry_impl(P, 0, s, mv, ctx->tab, X.p, nullptr, nullptr, nullptr, flags.p), "geometry");
+  NSMF_TRY(ctx, launch_geometry_impl(P, 0, s, mv, ctx->tabs.p, X.p, nullptr, nullptr, nullptr, flags.p), "geometry");
   unsigned hflags = 0;
   NSMF_TRY(ctx, hipMemcpyAsync(&hflags, flags.p, 4, hipMemcpyDeviceToHost, s), "copy");
   NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry check");
@@ -250,7 +255,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   }
   NSMF_TRY(ctx, ctx->face64.alloc((size_t)NB * 4 * P2), "hipMalloc");
   NSMF_TRY(ctx, ctx->face32.alloc((size_t)NB * 4 * P2), "hipMalloc");
-  NSMF_TRY(ctx, launch_geometry_impl(P, ctx->geo == GEO_AFFINE ? 1 : 2, s, mv, ctx->tab, X.p, ctx->geo_el64.p,
+  NSMF_TRY(ctx, launch_geometry_impl(P, ctx->geo == GEO_AFFINE ? 1 : 2, s, mv, ctx->tabs.p, X.p, ctx->geo_el64.p,
                                      ctx->geo_qp64.p, ctx->face64.p, nullptr),
            "geometry");
   NSMF_TRY(ctx, launch_d2f(s, ctx->geo_el64.p, ctx->geo_el32.p, nel_geo), "convert");
@@ -305,7 +310,7 @@ int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p) {
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->u.p, u, 3 * ctx->n_nodes * 8, hipMemcpyDeviceToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->p.p, p, ctx->n_el * ctx->n_p * 8, hipMemcpyDeviceToDevice, s), "copy");
   NSMF_TRY(ctx,
-           launch_state(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->u.p, ctx->logA.p,
+           launch_state(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->u.p, ctx->logA.p,
                         ctx->prm.n, ctx->prm.eps, ctx->prm.B0, ctx->st64.p, ctx->st32.p, ctx->fst64.p, ctx->fst32.p),
            "state kernel");
   ctx->have_state = true;
@@ -317,7 +322,7 @@ int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p) {
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "residual needs a state");
   hipStream_t s = ctx->stream;
   NSMF_TRY(ctx,
-           launch_residual(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->st64.p, ctx->fst64.p,
+           launch_residual(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->fst64.p,
                            ctx->beta64.p, ctx->p.p, ctx->prm.body, ctx->ev.p, r_p),
            "residual kernel");
   NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p,
@@ -346,7 +351,7 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
   const void *fst = prec == 0 ? (const void *)ctx->fst64.p : (const void *)ctx->fst32.p;
   const void *beta = prec == 0 ? (const void *)ctx->beta64.p : (const void *)ctx->beta32.p;
   NSMF_TRY(ctx,
-           launch_apply(ctx->P, ctx->geo, prec, vjp, s, ctx->mesh_view(), gv, ctx->tab, st, fst, beta, x_u, x_p,
+           launch_apply(ctx->P, ctx->geo, prec, vjp, s, ctx->mesh_view(), gv, ctx->tabs.p, st, fst, beta, x_u, x_p,
                         y_u ? (void *)ctx->ev.p : nullptr, y_p, 1.0 / ctx->prm.n, g_logA, g_beta),
            "apply kernel");
   if (y_u)
@@ -374,7 +379,7 @@ int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p) {
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "jacobi_diag needs a state");
   hipStream_t s = ctx->stream;
   NSMF_TRY(ctx,
-           launch_diag(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tab, ctx->st64.p, ctx->beta64.p,
+           launch_diag(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->beta64.p,
                        ctx->ev.p, d_p),
            "diagonal kernel");
   NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p, nullptr,

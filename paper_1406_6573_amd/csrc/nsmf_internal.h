@@ -39,7 +39,8 @@ template <> struct Launch<5> { static constexpr int E = NSMF_E5; static constexp
 template <typename T, int P> struct Tab {
   T B[P][P];        // B[q][a]  = l_a(g_q)         Lagrange basis at Gauss points
   T D[P][P];        // D[q][a]  = l_a'(g_q)        its derivative
-  T I[2][P][P];     // I[h][i][m] = l_m(child node i of half h)  child-interval interpolation
+  T I[P][P];        // I[i][m] = l_m(child node i of the lower half [-1, 0]); the upper half is its
+                    // mirror image, I_upper[i][m] = I[P-1-i][P-1-m] (symmetric nodes)
   T L[P - 1][P];    // L[j][q]  = sqrt((2j+1)/2) P_j(g_q)  normalised Legendre at Gauss points
   T w[P];           // Gauss weights
   int8_t pe[(P - 1) * P * (P + 1) / 6][3];  // pressure basis exponents (i, j, l)
@@ -56,6 +57,18 @@ struct HostTables {
 void build_tables(int k, HostTables *t);
 
 template <typename T, int P> Tab<T, P> make_tab(const HostTables &h, bool bf16_ops);
+
+// All table variants of one degree, kept once per context in device memory and passed to the
+// kernels by pointer: uniform entries are read through the scalar cache, lane-dependent ones
+// (quadrature weights, Legendre values at a thread's own points) by ordinary vector loads.
+template <int P> struct TabSet {
+  Tab<double, P> d;     // FP64 operators
+  Tab<float, P> f;      // FP32 operators
+  Tab<float, P> fb;     // FP32 arithmetic, B and D rounded to bfloat16
+  Tab<double, P> dsq;   // FP64 with squared child-interval weights (diagonal of R^T F R)
+};
+size_t tabset_bytes(int P);
+void fill_tabset(const HostTables &h, void *host_buf);   // host_buf holds tabset_bytes(h.P) bytes
 
 // Device views used by the kernels.
 struct MeshView {
@@ -74,20 +87,20 @@ template <typename T> struct GeoView {
 };
 
 // Launchers (defined in nsmf_kernels.hip).  Return hipError_t of the launch.
-hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const HostTables &tab,
+hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const void *tabs,
                                 const double *coords, double *el_out, double *qp_out, double *face_out,
                                 unsigned *flags);
 hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
-                        const HostTables &tab, const double *u, const double *logA, double n, double eps,
+                        const void *tabs, const double *u, const double *logA, double n, double eps,
                         double B0, double *st64, float *st32, double *fst64, float *fst32);
 hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *geo_view,
-                        const HostTables &tab, const void *state, const void *fstate, const void *beta,
+                        const void *tabs, const void *state, const void *fstate, const void *beta,
                         const void *x_u, const void *x_p, void *y_u, void *y_p, double inv_n,
                         double *g_logA, double *g_beta);
 hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
-                           const HostTables &tab, const double *st64, const double *fst64, const double *beta,
+                           const void *tabs, const double *st64, const double *fst64, const double *beta,
                            const double *p, const double *body, double *r_u, double *r_p);
-hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                        const double *st, const double *beta, double *ev, double *dp);
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,

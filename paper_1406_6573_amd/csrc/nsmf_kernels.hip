@@ -59,29 +59,37 @@ template <int P> __device__ __forceinline__ bool zline_hanging(uint32_t cm, int 
          ((f >> 3) & 1u && j == P - 1) || edge_on<P>(cm, 2, i, j);
 }
 
-template <typename T, int P> __device__ __forceinline__ void interp_line(const T (&I)[P][P], T *v) {
-  T o[P];
+// Child-interval interpolation of a line (half h of the parent interval) and its transpose.
+// The upper half is the mirror image of the lower one, so h = 1 reverses the line, applies the
+// lower-half matrix and reverses the result: the table is indexed statically and stays in scalar
+// registers.
+template <typename T, int P> __device__ __forceinline__ void interp_line(const Tab<T, P> &tb, int h, T *v) {
+  T r[P], o[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) r[m] = h ? v[P - 1 - m] : v[m];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     T a = 0;
 #pragma unroll
-    for (int m = 0; m < P; ++m) a += I[i][m] * v[m];
+    for (int m = 0; m < P; ++m) a += tb.I[i][m] * r[m];
     o[i] = a;
   }
 #pragma unroll
-  for (int i = 0; i < P; ++i) v[i] = o[i];
+  for (int i = 0; i < P; ++i) v[i] = h ? o[P - 1 - i] : o[i];
 }
-template <typename T, int P> __device__ __forceinline__ void interp_line_t(const T (&I)[P][P], T *v) {
-  T o[P];
+template <typename T, int P> __device__ __forceinline__ void interp_line_t(const Tab<T, P> &tb, int h, T *v) {
+  T r[P], o[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) r[i] = h ? v[P - 1 - i] : v[i];
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     T a = 0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) a += I[i][m] * v[i];
+    for (int i = 0; i < P; ++i) a += tb.I[i][m] * r[i];
     o[m] = a;
   }
 #pragma unroll
-  for (int i = 0; i < P; ++i) v[i] = o[i];
+  for (int m = 0; m < P; ++m) v[m] = h ? o[P - 1 - m] : o[m];
 }
 
 // LDS strides chosen against bank conflicts (32 banks of 4 bytes): the z-plane stride SZ
@@ -126,7 +134,7 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
         T l[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + w.xl(t)];
-        interp_line<T, P>(tb.I[h], l);
+        interp_line<T, P>(tb, h, l);
 #pragma unroll
         for (int m = 0; m < P; ++m) w.b(c)[m + w.xl(t)] = l[m];
       }
@@ -142,7 +150,7 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
         T l[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + w.SZ * z];
-        interp_line<T, P>(tb.I[h], l);
+        interp_line<T, P>(tb, h, l);
 #pragma unroll
         for (int m = 0; m < P; ++m) w.b(c)[i + P * m + w.SZ * z] = l[m];
       }
@@ -158,7 +166,7 @@ __device__ void hang_fwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
     if (zline_hanging<P>(cm, i, j)) {
       const int h = (cm >> 2) & 1u;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) interp_line<T, P>(tb.I[h], v[c]);
+      for (int c = 0; c < 3; ++c) interp_line<T, P>(tb, h, v[c]);
     }
   }
   __syncthreads();
@@ -173,7 +181,7 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
     if (zline_hanging<P>(cm, i, j)) {
       const int h = (cm >> 2) & 1u;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) interp_line_t<T, P>(tb.I[h], v[c]);
+      for (int c = 0; c < 3; ++c) interp_line_t<T, P>(tb, h, v[c]);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -190,7 +198,7 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
         T l[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) l[m] = w.b(c)[i + P * m + w.SZ * z];
-        interp_line_t<T, P>(tb.I[h], l);
+        interp_line_t<T, P>(tb, h, l);
 #pragma unroll
         for (int m = 0; m < P; ++m) w.b(c)[i + P * m + w.SZ * z] = l[m];
       }
@@ -206,7 +214,7 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
         T l[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) l[m] = w.b(c)[m + w.xl(t)];
-        interp_line_t<T, P>(tb.I[h], l);
+        interp_line_t<T, P>(tb, h, l);
 #pragma unroll
         for (int m = 0; m < P; ++m) w.b(c)[m + w.xl(t)] = l[m];
       }
@@ -580,12 +588,17 @@ __device__ void face_test(const T (&tq)[3], T (&out)[3], Ws<T, P> w, const Tab<T
 }
 
 // ---------------------------------------------------------------- gather / scatter
-template <typename T, int P>
-__device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t N, int t, bool act, bool use_mask,
-                                       T (&v)[3][P], uint32_t (&nw)[P]) {
+// Node words of the thread's z-line (node id | Dirichlet mask bits), then the values of x they
+// name (0 in masked components).
+template <int P>
+__device__ __forceinline__ void load_words(const uint32_t *__restrict__ en_e, int t, bool act, uint32_t (&nw)[P]) {
   constexpr int P2 = P * P;
 #pragma unroll
   for (int z = 0; z < P; ++z) nw[z] = act ? en_e[t + P2 * z] : 0u;
+}
+template <typename T, int P>
+__device__ __forceinline__ void gather_words(const uint32_t (&nw)[P], const T *x, int64_t N, bool act, bool use_mask,
+                                             T (&v)[3][P]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -594,6 +607,12 @@ __device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t
       const bool masked = use_mask && ((wd >> (MASK_SHIFT + c)) & 1u);
       v[c][z] = (act && !masked) ? x[c * N + (wd & NODE_MASK)] : T(0);
     }
+}
+template <typename T, int P>
+__device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t N, int t, bool act, bool use_mask,
+                                       T (&v)[3][P], uint32_t (&nw)[P]) {
+  load_words<P>(en_e, t, act, nw);
+  gather_words<T, P>(nw, x, N, act, use_mask, v);
 }
 
 // Element-vector store in node order: the result of element slot (e, a) for component c goes to
@@ -621,9 +640,10 @@ __device__ __forceinline__ void load_pos(const int32_t *__restrict__ pos_e, int 
 // Jacobian apply (and VJP): y = J_c x at the stored linearisation point.
 template <typename T, int P, int GEO, bool VJP>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const T *__restrict__ fst,
+k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *__restrict__ st, const T *__restrict__ fst,
         const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
         T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
+  const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   constexpr int NP = (P - 1) * P * (P + 1) / 6;
   __shared__ T smem[E * Ws<T, P>::ES];
@@ -636,21 +656,22 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   double *redl = red + els * P2;
   const int64_t N = m.n_nodes;
-  // linearisation data of the thread's P points; in FP32 requested first so that its latency
-  // overlaps the gather and the forward sweeps (in FP64 the extra live registers would cost
-  // occupancy, so it is loaded just before the quadrature-point step).  The block's slice is
-  // always allocated, also for threads without an element.
+  // connectivity first (the gather of x waits on it), then the linearisation data of the thread's
+  // P points: in FP32 requested here so that its latency overlaps the gather and the forward
+  // sweeps (in FP64 the extra live registers would cost occupancy, so it is loaded just before
+  // the quadrature-point step).  The block's slice is always allocated, also for threads
+  // without an element.
+  uint32_t nw[P];
+  load_words<P>(m.en + e * P3, t, act, nw);
+  const uint32_t cm = act ? m.cmask[e] : 0u;
   constexpr bool kEarlyState = sizeof(T) == 4;
   T stv[NSTATE][P];
   if constexpr (kEarlyState) {
 #pragma unroll
     for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
   }
-
-  const uint32_t cm = act ? m.cmask[e] : 0u;
   T v[3][P];
-  uint32_t nw[P];
-  gather<T, P>(m.en + e * P3, xu, N, t, act, true, v, nw);
+  gather_words<T, P>(nw, xu, N, act, true, v);
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
 
@@ -760,10 +781,11 @@ k_apply(MeshView m, GeoView<T> gv, Tab<T, P> tb, const T *__restrict__ st, const
 // (FP64, eq. (glen) and eq. (rank4)); per basal face point w|S| T u.
 template <int P, int GEO>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_state(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restrict__ u,
+k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ u,
         const double *__restrict__ logA, double n, double eps, double B0, double *__restrict__ st64,
         float *__restrict__ st32, double *__restrict__ fst64, float *__restrict__ fst32) {
   using T = double;
+  const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
@@ -834,10 +856,11 @@ k_state(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restr
 // basal term beta w|S| T u, pressure rows -int psi div u.
 template <int P, int GEO>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__restrict__ st,
+k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ st,
            const double *__restrict__ fst, const double *__restrict__ beta, const double *__restrict__ p, double bx,
            double by, double bz, double *__restrict__ ru, double *__restrict__ rp) {
   using T = double;
+  const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   constexpr int NP = (P - 1) * P * (P + 1) / 6;
   __shared__ T smem[E * Ws<T, P>::ES];
@@ -929,9 +952,11 @@ k_residual(MeshView m, GeoView<double> gv, Tab<double, P> tb, const double *__re
 // mass weighted by 1/mu with a minus sign, the Schur-complement approximation of Sec. 6.
 template <int P, int GEO>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_diag(MeshView m, GeoView<double> gv, Tab<double, P> tb, Tab<double, P> tb2, const double *__restrict__ st,
+k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
+       const Tab<double, P> *__restrict__ tb2p, const double *__restrict__ st,
        const double *__restrict__ beta, double *__restrict__ ev, double *__restrict__ dp) {
   using T = double;
+  const Tab<T, P> &tb = *tbp, &tb2 = *tb2p;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   constexpr int NP = (P - 1) * P * (P + 1) / 6;
   __shared__ T smem[E * Ws<T, P>::ES];
@@ -1032,9 +1057,10 @@ k_diag(MeshView m, GeoView<double> gv, Tab<double, P> tb, Tab<double, P> tb2, co
 // affine data.  mode 2: store column data.  Face data are stored in modes 1 and 2.
 template <int P>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_geometry(MeshView m, Tab<double, P> tb, const double *__restrict__ X, int mode, double *__restrict__ el_out,
+k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ X, int mode, double *__restrict__ el_out,
            double *__restrict__ qp_out, double *__restrict__ face_out, unsigned *__restrict__ flags) {
   using T = double;
+  const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   __shared__ T smem[E * Ws<T, P>::ES];
   __shared__ T ref0[E][3];
@@ -1255,37 +1281,35 @@ hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n) {
 
 // ---------------------------------------------------------------- dispatch
 template <int P>
-static hipError_t geometry_p(int mode, hipStream_t s, const MeshView &m, const HostTables &h, const double *X,
+static hipError_t geometry_p(int mode, hipStream_t s, const MeshView &m, const void *tabs, const double *X,
                              double *el, double *qp, double *face, unsigned *flags) {
-  auto tb = make_tab<double, P>(h, false);
-  hipLaunchKernelGGL((k_geometry<P>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, tb, X, mode, el, qp, face,
+  hipLaunchKernelGGL((k_geometry<P>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, &((const TabSet<P> *)tabs)->d, X, mode, el, qp, face,
                      flags);
   return hipGetLastError();
 }
-hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const HostTables &h,
+hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const void *tabs,
                                 const double *X, double *el, double *qp, double *face, unsigned *flags) {
   switch (P) {
-    case 3: return geometry_p<3>(mode, s, m, h, X, el, qp, face, flags);
-    case 4: return geometry_p<4>(mode, s, m, h, X, el, qp, face, flags);
-    case 5: return geometry_p<5>(mode, s, m, h, X, el, qp, face, flags);
+    case 3: return geometry_p<3>(mode, s, m, tabs, X, el, qp, face, flags);
+    case 4: return geometry_p<4>(mode, s, m, tabs, X, el, qp, face, flags);
+    case 5: return geometry_p<5>(mode, s, m, tabs, X, el, qp, face, flags);
   }
   return hipErrorInvalidValue;
 }
 
 template <int P, int GEO>
-static hipError_t state_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+static hipError_t state_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                            const double *u, const double *logA, double n, double eps, double B0, double *st64,
                            float *st32, double *fst64, float *fst32) {
-  auto tb = make_tab<double, P>(h, false);
-  hipLaunchKernelGGL((k_state<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, tb, u, logA, n, eps, B0,
+  hipLaunchKernelGGL((k_state<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &((const TabSet<P> *)tabs)->d, u, logA, n, eps, B0,
                      st64, st32, fst64, fst32);
   return hipGetLastError();
 }
 hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
-                        const HostTables &h, const double *u, const double *logA, double n, double eps, double B0,
+                        const void *tabs, const double *u, const double *logA, double n, double eps, double B0,
                         double *st64, float *st32, double *fst64, float *fst32) {
 #define NSMF_ST(PP, GG) \
-  if (P == PP && geo == GG) return state_pg<PP, GG>(s, m, g, h, u, logA, n, eps, B0, st64, st32, fst64, fst32);
+  if (P == PP && geo == GG) return state_pg<PP, GG>(s, m, g, tabs, u, logA, n, eps, B0, st64, st32, fst64, fst32);
   NSMF_ST(3, GEO_AFFINE) NSMF_ST(3, GEO_COLUMN) NSMF_ST(4, GEO_AFFINE) NSMF_ST(4, GEO_COLUMN)
   NSMF_ST(5, GEO_AFFINE) NSMF_ST(5, GEO_COLUMN)
 #undef NSMF_ST
@@ -1293,19 +1317,18 @@ hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const 
 }
 
 template <int P, int GEO>
-static hipError_t residual_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+static hipError_t residual_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                               const double *st, const double *fst, const double *beta, const double *p,
                               const double *body, double *ru, double *rp) {
-  auto tb = make_tab<double, P>(h, false);
-  hipLaunchKernelGGL((k_residual<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, tb, st, fst, beta, p,
+  hipLaunchKernelGGL((k_residual<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &((const TabSet<P> *)tabs)->d, st, fst, beta, p,
                      body[0], body[1], body[2], ru, rp);
   return hipGetLastError();
 }
 hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
-                           const HostTables &h, const double *st, const double *fst, const double *beta,
+                           const void *tabs, const double *st, const double *fst, const double *beta,
                            const double *p, const double *body, double *ru, double *rp) {
 #define NSMF_RS(PP, GG) \
-  if (P == PP && geo == GG) return residual_pg<PP, GG>(s, m, g, h, st, fst, beta, p, body, ru, rp);
+  if (P == PP && geo == GG) return residual_pg<PP, GG>(s, m, g, tabs, st, fst, beta, p, body, ru, rp);
   NSMF_RS(3, GEO_AFFINE) NSMF_RS(3, GEO_COLUMN) NSMF_RS(4, GEO_AFFINE) NSMF_RS(4, GEO_COLUMN)
   NSMF_RS(5, GEO_AFFINE) NSMF_RS(5, GEO_COLUMN)
 #undef NSMF_RS
@@ -1313,20 +1336,17 @@ hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, con
 }
 
 template <int P, int GEO>
-static hipError_t diag_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+static hipError_t diag_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                           const double *st, const double *beta, double *ev, double *dp) {
-  auto tb = make_tab<double, P>(h, false);
-  auto tb2 = tb;
-  for (int hh = 0; hh < 2; ++hh)
-    for (int i = 0; i < P; ++i)
-      for (int k = 0; k < P; ++k) tb2.I[hh][i][k] = tb.I[hh][i][k] * tb.I[hh][i][k];
-  hipLaunchKernelGGL((k_diag<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, tb, tb2, st, beta, ev, dp);
+  const TabSet<P> *ts = (const TabSet<P> *)tabs;
+  hipLaunchKernelGGL((k_diag<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &ts->d, &ts->dsq, st, beta, ev,
+                     dp);
   return hipGetLastError();
 }
-hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const HostTables &h,
+hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                        const double *st, const double *beta, double *ev, double *dp) {
 #define NSMF_DG(PP, GG) \
-  if (P == PP && geo == GG) return diag_pg<PP, GG>(s, m, g, h, st, beta, ev, dp);
+  if (P == PP && geo == GG) return diag_pg<PP, GG>(s, m, g, tabs, st, beta, ev, dp);
   NSMF_DG(3, GEO_AFFINE) NSMF_DG(3, GEO_COLUMN) NSMF_DG(4, GEO_AFFINE) NSMF_DG(4, GEO_COLUMN)
   NSMF_DG(5, GEO_AFFINE) NSMF_DG(5, GEO_COLUMN)
 #undef NSMF_DG
@@ -1334,22 +1354,25 @@ hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const G
 }
 
 template <typename T, int P, int GEO, bool VJP>
-static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, const HostTables &h, bool bf16,
+static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, const void *tabs, bool bf16,
                           const void *st, const void *fst, const void *beta, const void *xu, const void *xp, void *yu,
                           void *yp, double inv_n, double *gA, double *gB) {
-  auto tb = make_tab<T, P>(h, bf16);
+  const TabSet<P> *ts = (const TabSet<P> *)tabs;
+  const Tab<T, P> *tb;
+  if constexpr (sizeof(T) == 8) tb = &ts->d;
+  else tb = bf16 ? &ts->fb : &ts->f;
   hipLaunchKernelGGL((k_apply<T, P, GEO, VJP>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m,
                      *(const GeoView<T> *)gview, tb, (const T *)st, (const T *)fst, (const T *)beta, (const T *)xu,
                      (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
   return hipGetLastError();
 }
 hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *gview,
-                        const HostTables &h, const void *st, const void *fst, const void *beta, const void *xu,
+                        const void *tabs, const void *st, const void *fst, const void *beta, const void *xu,
                         const void *xp, void *yu, void *yp, double inv_n, double *gA, double *gB) {
   const bool bf = prec == 2;
 #define NSMF_AP(TT, PP, GG, VV)                                                                                   \
   if (P == PP && geo == GG && vjp == VV && (sizeof(TT) == 8) == (prec == 0))                                     \
-    return apply_t<TT, PP, GG, VV>(s, m, gview, h, bf, st, fst, beta, xu, xp, yu, yp, inv_n, gA, gB);
+    return apply_t<TT, PP, GG, VV>(s, m, gview, tabs, bf, st, fst, beta, xu, xp, yu, yp, inv_n, gA, gB);
 #define NSMF_AP2(TT, PP) \
   NSMF_AP(TT, PP, GEO_AFFINE, false) NSMF_AP(TT, PP, GEO_COLUMN, false) NSMF_AP(TT, PP, GEO_AFFINE, true) \
   NSMF_AP(TT, PP, GEO_COLUMN, true)

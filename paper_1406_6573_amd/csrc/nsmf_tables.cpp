@@ -138,15 +138,32 @@ Tab<T, P> make_tab(const HostTables &h, bool bf16_ops) {
       t.B[q][a] = bf16_ops ? (T)round_bf16(h.B[q][a]) : (T)h.B[q][a];
       t.D[q][a] = bf16_ops ? (T)round_bf16(h.D[q][a]) : (T)h.D[q][a];
     }
-  for (int hh = 0; hh < 2; ++hh)
-    for (int i = 0; i < P; ++i)
-      for (int m = 0; m < P; ++m) t.I[hh][i][m] = (T)h.I[hh][i][m];
+  for (int i = 0; i < P; ++i)
+    for (int m = 0; m < P; ++m) t.I[i][m] = (T)h.I[0][i][m];
   for (int j = 0; j < P - 1; ++j)
     for (int q = 0; q < P; ++q) t.L[j][q] = (T)h.L[j][q];
   for (int q = 0; q < P; ++q) t.w[q] = (T)h.w[q];
   for (int m = 0; m < (P - 1) * P * (P + 1) / 6; ++m)
     for (int d = 0; d < 3; ++d) t.pe[m][d] = h.pe[m][d];
   return t;
+}
+
+template <int P> static void fill_set(const HostTables &h, TabSet<P> *t) {
+  t->d = make_tab<double, P>(h, false);
+  t->f = make_tab<float, P>(h, false);
+  t->fb = make_tab<float, P>(h, true);
+  t->dsq = t->d;
+  for (int i = 0; i < P; ++i)
+    for (int k = 0; k < P; ++k) t->dsq.I[i][k] = t->d.I[i][k] * t->d.I[i][k];
+}
+size_t tabset_bytes(int P) {
+  return P == 3 ? sizeof(TabSet<3>) : (P == 4 ? sizeof(TabSet<4>) : (P == 5 ? sizeof(TabSet<5>) : 0));
+}
+void fill_tabset(const HostTables &h, void *buf) {
+  std::memset(buf, 0, tabset_bytes(h.P));
+  if (h.P == 3) fill_set<3>(h, (TabSet<3> *)buf);
+  if (h.P == 4) fill_set<4>(h, (TabSet<4> *)buf);
+  if (h.P == 5) fill_set<5>(h, (TabSet<5> *)buf);
 }
 
 template Tab<double, 3> make_tab<double, 3>(const HostTables &, bool);
