@@ -335,7 +335,8 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
       T k0 = 0, k1 = 0;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        k0 += tb.B[q][j] * a[q] + tb.D[q][j] * b[q];
+        k0 += tb.B[q][j] * a[q];
+        k0 += tb.D[q][j] * b[q];
         k1 += tb.B[q][j] * c[q];
       }
       w.b(3)[i + P * j + w.SZ * z] = k0;
@@ -354,7 +355,10 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
     for (int z = 0; z < P; ++z) {
       T o = 0;
 #pragma unroll
-      for (int q = 0; q < P; ++q) o += tb.B[q][z] * a[q] + tb.D[q][z] * b[q];
+      for (int q = 0; q < P; ++q) {
+        o += tb.B[q][z] * a[q];
+        o += tb.D[q][z] * b[q];
+      }
       out[z] = o;
     }
   }
@@ -672,6 +676,15 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   }
   T v[3][P];
   gather_words<T, P>(nw, xu, N, act, true, v);
+  // geometry and pressure coefficients are needed only after the forward sweeps; requesting them
+  // here hides their latency behind the sweeps (per-point geometry of column-mapped elements)
+  QpGeo<T, P, GEO> g;
+  T xpl[NP];
+  if (act) {
+    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+#pragma unroll
+    for (int mm = 0; mm < NP; ++mm) xpl[mm] = xp[e * NP + mm];
+  }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
 
@@ -680,15 +693,8 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   for (int c = 0; c < 3; ++c) grad_fwd<T, P>(v[c], gr[c][0], gr[c][1], gr[c][2], w, tb, t, act);
   __syncthreads();
 
-  QpGeo<T, P, GEO> g;
   T pq[P];
-  if (act) {
-    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
-    T xpl[NP];
-#pragma unroll
-    for (int mm = 0; mm < NP; ++mm) xpl[mm] = xp[e * NP + mm];
-    pressure_interp<T, P>(xpl, tb, t, pq);
-  }
+  if (act) pressure_interp<T, P>(xpl, tb, t, pq);
   T dw[P];
   double gA = 0.0;
   if constexpr (!kEarlyState) {
@@ -707,19 +713,25 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
     const T mu = stv[0][i], ka = stv[1][i];
     const T sxx = stv[2][i], syy = stv[3][i], szz = stv[4][i];
     const T sxy = stv[5][i], sxz = stv[6][i], syz = stv[7][i];
+    // D = sym(G): off-diagonal entries kept doubled (exy = 2 Dxy) so that Sigma0 : D takes no
+    // extra factors; tau = mu' D - kappa (Sigma0 : D) Sigma0 - p w detJ I
     const T dxx = G[0][0], dyy = G[1][1], dzz = G[2][2];
-    const T dxy = T(0.5) * (G[0][1] + G[1][0]), dxz = T(0.5) * (G[0][2] + G[2][0]);
-    const T dyz = T(0.5) * (G[1][2] + G[2][1]);
-    const T s = sxx * dxx + syy * dyy + szz * dzz + T(2) * (sxy * dxy + sxz * dxz + syz * dyz);
+    const T exy = G[0][1] + G[1][0], exz = G[0][2] + G[2][0], eyz = G[1][2] + G[2][1];
+    T s = sxx * dxx;
+    s += syy * dyy;
+    s += szz * dzz;
+    s += sxy * exy;
+    s += sxz * exz;
+    s += syz * eyz;
     if (VJP) gA += (double)s;
-    const T ks = ka * s;
+    const T ks = ka * s, muh = T(0.5) * mu;
     const T pw = pq[i] * g.wd[i];
-    tau[0][0] = mu * dxx - ks * sxx - pw;
-    tau[1][1] = mu * dyy - ks * syy - pw;
-    tau[2][2] = mu * dzz - ks * szz - pw;
-    tau[0][1] = tau[1][0] = mu * dxy - ks * sxy;
-    tau[0][2] = tau[2][0] = mu * dxz - ks * sxz;
-    tau[1][2] = tau[2][1] = mu * dyz - ks * syz;
+    tau[0][0] = mu * dxx - (ks * sxx + pw);
+    tau[1][1] = mu * dyy - (ks * syy + pw);
+    tau[2][2] = mu * dzz - (ks * szz + pw);
+    tau[0][1] = tau[1][0] = muh * exy - ks * sxy;
+    tau[0][2] = tau[2][0] = muh * exz - ks * sxz;
+    tau[1][2] = tau[2][1] = muh * eyz - ks * syz;
     dw[i] = (dxx + dyy + dzz) * g.wd[i];
     to_ref<T, P, GEO>(g, i, tau, f);
 #pragma unroll
