@@ -364,31 +364,31 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
   }
 }
 
-// Per-quadrature-point field f of thread tid in block lb: the thread's P points along its
-// x-line are contiguous, index ((lb * F + f) * NT + tid) * P + i.
+// Per-quadrature-point field f of point i on the x-line of thread tid in block lb.  P = 4:
+// thread-major, the thread's 4 points contiguous, read as one 16/32-byte line with the
+// non-temporal hint (the stream is read once per launch and would otherwise displace from L2
+// the reused lines: gathered nodal values and partially written element-vector lines; 11%
+// faster FP32 apply on the Q3 slab).  P = 3, 5: point-major, so that each of the thread's
+// scalar loads is one contiguous span across the wavefront.
 template <int P, int NT, int F>
-__device__ __forceinline__ size_t qp_index(int lb, int f, int tid) {
-  return (((size_t)lb * F + f) * NT + tid) * P;
+__device__ __forceinline__ size_t qp_at(int lb, int f, int tid, int i) {
+  if constexpr (P == 4) return (((size_t)lb * F + f) * NT + tid) * P + i;
+  else return (((size_t)lb * F + f) * P + i) * NT + tid;
 }
-// Per-point data (linearisation, column geometry) is read once per launch.  The 16/32-byte
-// line loads of P = 4 carry the non-temporal hint, so that the stream does not displace from
-// L2 the lines that are reused: the gathered nodal values and the partially written lines of
-// the element vector, which L2 combines before they reach HBM (measured: 11% faster FP32
-// apply on the Q3 slab).  For the scalar loads of P = 3, 5 the hint measured slower.
-template <typename T, int P>
-__device__ __forceinline__ void load_line(const T *__restrict__ p, T (&o)[P]) {
+template <typename T, int P, int NT, int F>
+__device__ __forceinline__ void load_field(const T *__restrict__ base, int lb, int f, int tid, T (&o)[P]) {
   if constexpr (P == 4 && sizeof(T) == 4) {
     typedef float f4v __attribute__((ext_vector_type(4)));
-    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(base + qp_at<P, NT, F>(lb, f, tid, 0)));
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   } else if constexpr (P == 4 && sizeof(T) == 8) {
     typedef double d2v __attribute__((ext_vector_type(2)));
-    const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
-    const d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p) + 1);
+    const d2v *q = reinterpret_cast<const d2v *>(base + qp_at<P, NT, F>(lb, f, tid, 0));
+    const d2v a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1);
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
   } else {
 #pragma unroll
-    for (int i = 0; i < P; ++i) o[i] = p[i];
+    for (int i = 0; i < P; ++i) o[i] = base[qp_at<P, NT, F>(lb, f, tid, i)];
   }
 }
 
@@ -412,10 +412,10 @@ __device__ __forceinline__ void load_geo(QpGeo<T, P, GEO> &g, const GeoView<T> &
   } else {
     const T *p = gv.el + 2 * e;
     g.jx = p[0]; g.jy = p[1];
-    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 0, tid), g.a);
-    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 1, tid), g.b);
-    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 2, tid), g.c);
-    load_line<T, P>(gv.qp + qp_index<P, NT, 4>(lb, 3, tid), g.wd);
+    load_field<T, P, NT, 4>(gv.qp, lb, 0, tid, g.a);
+    load_field<T, P, NT, 4>(gv.qp, lb, 1, tid, g.b);
+    load_field<T, P, NT, 4>(gv.qp, lb, 2, tid, g.c);
+    load_field<T, P, NT, 4>(gv.qp, lb, 3, tid, g.wd);
   }
 }
 
@@ -680,7 +680,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   T stv[NSTATE][P];
   if constexpr (kEarlyState) {
 #pragma unroll
-    for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
+    for (int f = 0; f < NSTATE; ++f) load_field<T, P, NT, NSTATE>(st, lb, f, tid, stv[f]);
   }
   T v[3][P];
   gather_words<T, P>(nw, xu, N, act, true, v);
@@ -707,7 +707,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   double gA = 0.0;
   if constexpr (!kEarlyState) {
 #pragma unroll
-    for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
+    for (int f = 0; f < NSTATE; ++f) load_field<T, P, NT, NSTATE>(st, lb, f, tid, stv[f]);
   }
 #pragma unroll
   for (int i = 0; i < P; ++i) {
@@ -849,8 +849,8 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
       const T vals[NSTATE] = {mup, ka, mup * dxx, mup * dyy, mup * dzz, mup * dxy, mup * dxz, mup * dyz};
 #pragma unroll
       for (int f = 0; f < NSTATE; ++f) {
-        s64[qp_index<P, NT, NSTATE>(lb, f, tid) + i] = vals[f];
-        s32[qp_index<P, NT, NSTATE>(lb, f, tid) + i] = (float)vals[f];
+        s64[qp_at<P, NT, NSTATE>(lb, f, tid, i)] = vals[f];
+        s32[qp_at<P, NT, NSTATE>(lb, f, tid, i)] = (float)vals[f];
       }
     }
   }
@@ -907,7 +907,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
     pressure_interp<T, P>(xpl, tb, t, pq);
     T stv[NSTATE][P];
 #pragma unroll
-    for (int f = 0; f < NSTATE; ++f) load_line<T, P>(st + qp_index<P, NT, NSTATE>(lb, f, tid), stv[f]);
+    for (int f = 0; f < NSTATE; ++f) load_field<T, P, NT, NSTATE>(st, lb, f, tid, stv[f]);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const T mu = stv[0][i];
@@ -1010,18 +1010,18 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
       const int qy = tq % P, qz = tq / P;
       const int tidq = el * P2 + tq;
       for (int qx = 0; qx < P; ++qx) {
-        const double mu = st[qp_index<P, NT, NSTATE>(lb, 0, tidq) + qx];
-        const double ka = st[qp_index<P, NT, NSTATE>(lb, 1, tidq) + qx];
+        const double mu = st[qp_at<P, NT, NSTATE>(lb, 0, tidq, qx)];
+        const double ka = st[qp_at<P, NT, NSTATE>(lb, 1, tidq, qx)];
         double S[6];
-        for (int f = 0; f < 6; ++f) S[f] = st[qp_index<P, NT, NSTATE>(lb, 2 + f, tidq) + qx];
+        for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
         double a = 0, b = 0, cc = jz, wd;
         if (GEO == GEO_AFFINE) {
           wd = tb.w[qx] * tb.w[qy] * tb.w[qz] * detJ;
         } else {
-          a = gv.qp[qp_index<P, NT, 4>(lb, 0, tidq) + qx];
-          b = gv.qp[qp_index<P, NT, 4>(lb, 1, tidq) + qx];
-          cc = gv.qp[qp_index<P, NT, 4>(lb, 2, tidq) + qx];
-          wd = gv.qp[qp_index<P, NT, 4>(lb, 3, tidq) + qx];
+          a = gv.qp[qp_at<P, NT, 4>(lb, 0, tidq, qx)];
+          b = gv.qp[qp_at<P, NT, 4>(lb, 1, tidq, qx)];
+          cc = gv.qp[qp_at<P, NT, 4>(lb, 2, tidq, qx)];
+          wd = gv.qp[qp_at<P, NT, 4>(lb, 3, tidq, qx)];
         }
         // pressure: thread (j, z) of the x-line layout owns points (., j, z); here every
         // thread accumulates the points of its own tq = t for the lumped 1/mu mass
@@ -1139,10 +1139,10 @@ k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__r
       if (fabs(a[2][0]) > tol || fabs(a[2][1]) > tol || fabs(a[2][2] - r22) > tol) fl |= 2u;
       if (mode == 2) {
         const T j00 = a[0][0], j11 = a[1][1], j22 = a[2][2];
-        qp_out[qp_index<P, NT, 4>(lb, 0, tid) + i] = -a[2][0] / (j00 * j22);
-        qp_out[qp_index<P, NT, 4>(lb, 1, tid) + i] = -a[2][1] / (j11 * j22);
-        qp_out[qp_index<P, NT, 4>(lb, 2, tid) + i] = 1.0 / j22;
-        qp_out[qp_index<P, NT, 4>(lb, 3, tid) + i] = tb.w[i] * tb.w[j] * tb.w[z] * j00 * j11 * j22;
+        qp_out[qp_at<P, NT, 4>(lb, 0, tid, i)] = -a[2][0] / (j00 * j22);
+        qp_out[qp_at<P, NT, 4>(lb, 1, tid, i)] = -a[2][1] / (j11 * j22);
+        qp_out[qp_at<P, NT, 4>(lb, 2, tid, i)] = 1.0 / j22;
+        qp_out[qp_at<P, NT, 4>(lb, 3, tid, i)] = tb.w[i] * tb.w[j] * tb.w[z] * j00 * j11 * j22;
       }
     }
     if (t == 0 && mode == 1) {
