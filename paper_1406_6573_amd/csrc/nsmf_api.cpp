@@ -2,6 +2,7 @@
 // residual / Jacobian-apply / VJP entry points declared in include/nsmf.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -46,7 +47,9 @@ struct nsmf_ctx {
   HostTables tab;
   DevBuf<uint32_t> en, cmask;
   DevBuf<int32_t> bface_of, inc_ptr;   // node -> first entry of its segment of the element vector
-  DevBuf<int32_t> pos;                // element slot -> its entry in the element vector
+  DevBuf<int32_t> pos;                // P = 4: element slot -> its entry in the element vector
+  DevBuf<int32_t> spos;               // P = 3, 5, per block: element-vector entries of its slots, ascending
+  DevBuf<uint16_t> sslot;             // per block: LDS staging index of each of those slots
   DevBuf<uint8_t> dmask;
   DevBuf<double> tabs;                // TabSet<P> of the mesh's degree
   DevBuf<double> geo_el64, geo_qp64, face64;
@@ -81,6 +84,8 @@ struct nsmf_ctx {
     m.cmask = cmask.p;
     m.bface_of = bface_of.p;
     m.pos = pos.p;
+    m.spos = spos.p;
+    m.sslot = sslot.p;
     m.n_inc = n_inc;
     m.n_el = n_el;
     m.n_nodes = n_nodes;
@@ -90,7 +95,7 @@ struct nsmf_ctx {
   GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p}; }
   GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p}; }
   void free_mesh() {
-    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); pos.free(); dmask.free(); ev.free(); tabs.free();
+    en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); pos.free(); spos.free(); sslot.free(); dmask.free(); ev.free(); tabs.free();
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
@@ -205,7 +210,34 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->bface_of.alloc(n_el), "hipMalloc");
   NSMF_TRY(ctx, ctx->dmask.alloc(3 * N), "hipMalloc");
   NSMF_TRY(ctx, ctx->inc_ptr.alloc(iptr.size()), "hipMalloc");
-  NSMF_TRY(ctx, ctx->pos.alloc(ipos.size()), "hipMalloc");
+  // store order per block: the block's slots sorted by their entry, so that adjacent lanes write
+  // adjacent entries; the LDS staging index of slot (el, x, y, z) is z E P^2 + el P^2 + x + P y
+  // (P = 3, 5; P = 4 stores per thread through pos)
+  const bool sorted_store = P != 4;
+  const int SB = P == 5 ? store_slots<5>() : (P == 4 ? store_slots<4>() : store_slots<3>());
+  const int E = ctx->epb;
+  std::vector<int32_t> spos(sorted_store ? (size_t)ctx->nblocks * SB : 0, -1);
+  std::vector<uint16_t> sslot(sorted_store ? (size_t)ctx->nblocks * SB : 0, 0);
+  if (sorted_store) {
+    std::vector<std::pair<int32_t, uint16_t>> blk;
+    for (int64_t lb = 0; lb < ctx->nblocks; ++lb) {
+      blk.clear();
+      for (int el = 0; el < E; ++el) {
+        const int64_t e = lb * E + el;
+        if (e >= n_el) break;
+        for (int a = 0; a < P3; ++a)
+          blk.emplace_back(ipos[e * P3 + a], (uint16_t)((a / P2) * E * P2 + el * P2 + a % P2));
+      }
+      std::sort(blk.begin(), blk.end());
+      for (size_t k = 0; k < blk.size(); ++k) {
+        spos[lb * SB + k] = blk[k].first;
+        sslot[lb * SB + k] = blk[k].second;
+      }
+    }
+  }
+  if (!sorted_store) NSMF_TRY(ctx, ctx->pos.alloc(ipos.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->spos.alloc(spos.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->sslot.alloc(sslot.size()), "hipMalloc");
   NSMF_TRY(ctx, ctx->ev.alloc((size_t)3 * n_inc), "hipMalloc");
   ctx->n_inc = n_inc;
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->en.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s), "copy");
@@ -213,7 +245,12 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->bface_of.p, bof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->dmask.p, dm.data(), 3 * N, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->inc_ptr.p, iptr.data(), iptr.size() * 4, hipMemcpyHostToDevice, s), "copy");
-  NSMF_TRY(ctx, hipMemcpyAsync(ctx->pos.p, ipos.data(), ipos.size() * 4, hipMemcpyHostToDevice, s), "copy");
+  if (sorted_store) {
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->spos.p, spos.data(), spos.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->sslot.p, sslot.data(), sslot.size() * 2, hipMemcpyHostToDevice, s), "copy");
+  } else {
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->pos.p, ipos.data(), ipos.size() * 4, hipMemcpyHostToDevice, s), "copy");
+  }
   std::vector<double> tabset((tabset_bytes(P) + 7) / 8);
   fill_tabset(ctx->tab, tabset.data());
   NSMF_TRY(ctx, ctx->tabs.alloc(tabset.size()), "hipMalloc");

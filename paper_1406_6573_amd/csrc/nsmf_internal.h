@@ -33,6 +33,8 @@ template <int P> struct Launch;
 template <> struct Launch<3> { static constexpr int E = NSMF_E3; static constexpr int NT = (E * 9 + 63) / 64 * 64; };
 template <> struct Launch<4> { static constexpr int E = NSMF_E4; static constexpr int NT = (E * 16 + 63) / 64 * 64; };
 template <> struct Launch<5> { static constexpr int E = NSMF_E5; static constexpr int NT = (E * 25 + 63) / 64 * 64; };
+// element-vector store entries per block: the block's E P^3 slots, padded to a multiple of NT
+template <int P> constexpr int store_slots() { return (Launch<P>::E * P * P * P + Launch<P>::NT - 1) / Launch<P>::NT * Launch<P>::NT; }
 
 // Reference-element tables (passed by value as kernel arguments, read through the
 // scalar cache).  Indices: q = Gauss point, a = Gauss-Lobatto node.
@@ -75,7 +77,12 @@ struct MeshView {
   const uint32_t *en;        // [n_el][P^3] node word (id | mask bits)
   const uint32_t *cmask;     // [n_el]
   const int32_t *bface_of;   // [n_el] basal face id or -1
-  const int32_t *pos;        // [n_el][P^3] entry of each element slot in the node-ordered element vector
+  // entries of the element slots in the node-ordered element vector.  P = 4: pos[e][a] per slot.
+  // P = 3, 5: per block, the entries of its slots in ascending order (spos, -1 = padding) with the
+  // slot's index in the block's LDS staging order (sslot), [nblocks][store_slots]
+  const int32_t *pos;
+  const int32_t *spos;
+  const uint16_t *sslot;
   int64_t n_el, n_nodes, n_inc;
   int nblocks;
 };
