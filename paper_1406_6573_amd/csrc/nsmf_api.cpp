@@ -180,18 +180,30 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   if (m->dmask)
     for (int64_t i = 0; i < 3 * N; ++i) dm[i] = m->dmask[i] ? 1 : 0;
   if (3 * N >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EINVAL, "3*n_nodes must fit in int32");
-  // node-ordered element vector: node n owns entries [iptr[n], iptr[n+1]); slot (e, a) takes
-  // entry pos[e][a] = iptr[node] + (number of earlier slots of the same node, in element order)
+  // Shared z-faces inside a block: when element e and the next element of the same block name the
+  // same node at (x, y, top) and (x, y, bottom), the kernel adds the upper element's bottom value
+  // to the lower element's top value and stores one entry (merged[bottom slot] = 1).
   const int64_t n_inc = n_el * P3;
   if (n_inc >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EUNSUP, "mesh too large for int32 entries");
+  const int E = launch_elems(P);
+  std::vector<uint8_t> merged((size_t)n_inc, 0);
+  for (int64_t e = 0; e + 1 < n_el; ++e) {
+    if (e % E == E - 1) continue;
+    for (int t = 0; t < P2; ++t)
+      if (words[e * P3 + P2 * (P - 1) + t] == words[(e + 1) * P3 + t]) merged[(e + 1) * P3 + t] = 1;
+  }
+  // node-ordered element vector: node n owns entries [iptr[n], iptr[n+1]); slot (e, a) takes
+  // entry pos[e][a] = iptr[node] + (number of earlier stored slots of the same node, in element
+  // order), or -1 if merged into the element below
   std::vector<int32_t> iptr((size_t)N + 1, 0), ipos((size_t)n_inc);
-  for (int64_t i = 0; i < n_inc; ++i) iptr[(words[i] & NODE_MASK) + 1]++;
+  for (int64_t i = 0; i < n_inc; ++i)
+    if (!merged[i]) iptr[(words[i] & NODE_MASK) + 1]++;
   for (int64_t n = 0; n < N; ++n) {
     iptr[n + 1] += iptr[n];
   }
   {
     std::vector<int32_t> next(iptr.begin(), iptr.end() - 1);
-    for (int64_t i = 0; i < n_inc; ++i) ipos[i] = next[words[i] & NODE_MASK]++;
+    for (int64_t i = 0; i < n_inc; ++i) ipos[i] = merged[i] ? -1 : next[words[i] & NODE_MASK]++;
   }
   ctx->k = m->k;
   ctx->P = P;
@@ -210,12 +222,12 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->bface_of.alloc(n_el), "hipMalloc");
   NSMF_TRY(ctx, ctx->dmask.alloc(3 * N), "hipMalloc");
   NSMF_TRY(ctx, ctx->inc_ptr.alloc(iptr.size()), "hipMalloc");
-  // store order per block: the block's slots sorted by their entry, so that adjacent lanes write
-  // adjacent entries; the LDS staging index of slot (el, x, y, z) is z E P^2 + el P^2 + x + P y
+  // store order per block: the block's stored slots sorted by their entry, so that adjacent lanes
+  // write adjacent entries; the LDS staging index of slot (el, x, y, z) is z E P^2 + el P^2 + x + P y,
+  // with bit 15 set on a top slot that also takes the merged bottom slot of the element above
   // (P = 3, 5; P = 4 stores per thread through pos)
   const bool sorted_store = P != 4;
   const int SB = P == 5 ? store_slots<5>() : (P == 4 ? store_slots<4>() : store_slots<3>());
-  const int E = ctx->epb;
   std::vector<int32_t> spos(sorted_store ? (size_t)ctx->nblocks * SB : 0, -1);
   std::vector<uint16_t> sslot(sorted_store ? (size_t)ctx->nblocks * SB : 0, 0);
   if (sorted_store) {
@@ -225,8 +237,12 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
       for (int el = 0; el < E; ++el) {
         const int64_t e = lb * E + el;
         if (e >= n_el) break;
-        for (int a = 0; a < P3; ++a)
-          blk.emplace_back(ipos[e * P3 + a], (uint16_t)((a / P2) * E * P2 + el * P2 + a % P2));
+        for (int a = 0; a < P3; ++a) {
+          if (ipos[e * P3 + a] < 0) continue;
+          uint16_t sl = (uint16_t)((a / P2) * E * P2 + el * P2 + a % P2);
+          if (a / P2 == P - 1 && el + 1 < E && e + 1 < n_el && merged[(e + 1) * P3 + a % P2]) sl |= 0x8000u;
+          blk.emplace_back(ipos[e * P3 + a], sl);
+        }
       }
       std::sort(blk.begin(), blk.end());
       for (size_t k = 0; k < blk.size(); ++k) {

@@ -629,24 +629,37 @@ __device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t
 
 // Element-vector store in node order.  The result of element slot (e, a) for component c goes
 // to ev[c * n_inc + pos], pos being the slot's entry in its node's contiguous segment (built at
-// upload).  P = 4: each thread stores its z-line through pos[e][a] (loaded only now, so it holds
-// no registers during the element work).  P = 3, 5: the block first stages its results in LDS;
-// then lane l writes the l-th entry of the block's slots sorted by entry, so that adjacent lanes
-// write adjacent entries (measured 3% faster there, slower for P = 4).  All threads of the block
-// must call; the staging area reuses the block's workspace.
+// upload).  Where two vertically adjacent elements of the block share a z-face, the lower
+// element's top slot also takes the upper element's bottom value and the latter is not stored
+// (pos = -1): fewer element-vector entries to write and to assemble.  P = 4: each thread stores
+// its z-line through pos[e][a] (loaded only now, so it holds no registers during the element
+// work); the block is one wavefront, and the upper element's bottom values come from lane
+// + P^2.  P = 3, 5: the block first stages its results in LDS; then lane l writes the l-th entry
+// of the block's stored slots sorted by entry, so that adjacent lanes write adjacent entries
+// (measured 3% faster there, slower for P = 4).  All threads of the block must call; the
+// staging area reuses the block's workspace.
 template <typename T, int P>
 __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int64_t e, T *stage, int el, int t,
                                            bool act, const T (&v)[3][P]) {
   constexpr int E = Launch<P>::E, NT = Launch<P>::NT, P2 = P * P, EP3 = E * P2 * P, SB = store_slots<P>();
   if constexpr (P == 4) {
-    if (!act || ev == nullptr) return;
+    static_assert(NT == 64 && E * P2 == 64, "one wavefront per block expected");
     int32_t pos[P];
 #pragma unroll
-    for (int z = 0; z < P; ++z) pos[z] = m.pos[e * EP3 / E + t + P2 * z];
+    for (int z = 0; z < P; ++z) pos[z] = act ? m.pos[e * EP3 / E + t + P2 * z] : 0;
+    // bottom slot of the element above (lane + P^2; lanes past the wavefront read their own)
+    const int32_t up_pos = __shfl_down(pos[0], P2);
+    T up[3];
 #pragma unroll
-    for (int z = 0; z < P; ++z)
+    for (int c = 0; c < 3; ++c) up[c] = __shfl_down(v[c][0], P2);
+    if (!act || ev == nullptr) return;
+    const bool take_up = el + 1 < E && up_pos < 0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ev[c * m.n_inc + pos[z]] = v[c][z];
+    for (int z = 0; z < P; ++z) {
+      if (pos[z] < 0) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ev[c * m.n_inc + pos[z]] = (z == P - 1 && take_up) ? v[c][z] + up[c] : v[c][z];
+    }
   } else {
     static_assert(3 * EP3 <= E * Ws<T, P>::ES, "staging area exceeds the block workspace");
     __syncthreads();
@@ -664,9 +677,12 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
       const int k = r * NT + (int)threadIdx.x;
       const int32_t pos = sp[k];
       if (pos >= 0) {
-        const int sl = ss[k];
+        const int code = ss[k], sl = code & 0x7FFF;
+        // merged top slot: add the bottom slot (el + 1, x, y, 0) of the element above
+        const int below = sl - (P - 1) * E * P2 + P2;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ev[c * m.n_inc + pos] = stage[c * EP3 + sl];
+        for (int c = 0; c < 3; ++c)
+          ev[c * m.n_inc + pos] = (code & 0x8000) ? stage[c * EP3 + sl] + stage[c * EP3 + below] : stage[c * EP3 + sl];
       }
     }
   }
