@@ -72,6 +72,7 @@ class ColumnMesh:
     dmask: np.ndarray            # uint8 [3, n_nodes]
     extent: tuple = (1.0, 1.0, 1.0)
     meta: dict = field(default_factory=dict)
+    pspace: str = "P"            # pressure space: "P" = P_{k-1}, "Q" = Q_{k-2} (a label only)
 
     @property
     def P(self) -> int:
@@ -91,9 +92,9 @@ class ColumnMesh:
 
     @property
     def n_p(self) -> int:
-        """dim P_{k-1} on the reference cube."""
+        """Pressure unknowns per element: dim P_{k-1} or dim Q_{k-2} on the reference cube."""
         k = self.k
-        return k * (k + 1) * (k + 2) // 6
+        return (k - 1) ** 3 if self.pspace == "Q" else k * (k + 1) * (k + 2) // 6
 
     @property
     def n_dof(self) -> int:
@@ -149,14 +150,17 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                 refined: Optional[np.ndarray] = None,
                 geometry: Optional[Callable[[np.ndarray], np.ndarray]] = None,
                 extent=(1.0, 1.0, 1.0),
-                base_normal_dirichlet: bool = False) -> ColumnMesh:
+                base_normal_dirichlet: bool = False, pspace: str = "P") -> ColumnMesh:
     """Build a column mesh.
 
     ``geometry`` maps logical positions [n, 3] (coarse-cell units, x in
     [0, nx], ...) to physical coordinates [n, 3].  Default: the axis-aligned
     box ``extent`` (affine slab).  ``base_normal_dirichlet`` flags the
-    z-component of every base node (logical z = 0) in ``dmask``.
+    z-component of every base node (logical z = 0) in ``dmask``.  ``pspace``
+    labels the pressure space the mesh is used with ("P" or "Q").
     """
+    if pspace not in ("P", "Q"):
+        raise ValueError("pspace must be 'P' or 'Q'")
     if k not in (2, 3, 4):
         raise ValueError("k must be 2, 3 or 4")
     P = k + 1
@@ -293,7 +297,7 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                       elem_level=elem_level, elem_cell=elem_cell,
                       elem_nodes=elem_nodes.astype(np.int32), cmask=cmask,
                       node_logical=node_logical, coords=coords,
-                      bface_elem=bface_elem, dmask=dmask, extent=tuple(extent))
+                      bface_elem=bface_elem, dmask=dmask, extent=tuple(extent), pspace=pspace)
 
 
 def random_refined_columns(nx: int, ny: int, fraction: float, rng: np.random.Generator) -> np.ndarray:

@@ -56,10 +56,10 @@ def _uniform_dirs(rng, mesh, count):
     return out
 
 
-def config1(seed: int = 0, n_dirs: int = 10, nx: int = 8, ny: int = 8, nz: int = 2) -> Workload:
+def config1(seed: int = 0, n_dirs: int = 10, nx: int = 8, ny: int = 8, nz: int = 2, pspace: str = "P") -> Workload:
     """Unit box 8x8x2, conforming affine Q2 x P1, beta = 0, no Dirichlet mask."""
     r_u, r_p, r_d = _rngs(1, seed, 3)
-    mesh = column_mesh(2, nx, ny, nz, extent=(1.0, 1.0, 1.0))
+    mesh = column_mesh(2, nx, ny, nz, extent=(1.0, 1.0, 1.0), pspace=pspace)
     u = r_u.uniform(-1, 1, (3, mesh.n_nodes))
     p = r_p.uniform(-1, 1, (mesh.n_el, mesh.n_p))
     return Workload("config1", mesh, 3.0, 1e-10, 0.5, np.zeros(mesh.n_el), np.zeros(mesh.n_bface),
@@ -78,10 +78,10 @@ def _slab_state(mesh: ColumnMesh, L: float, rng) -> tuple:
 
 def slab(config_id: int, k: int, nx: int, ny: int, nz: int, L: float, H: float,
          frac_refined: float, seed: int, beta_lognormal: bool, n_dirs: int = 1,
-         adjoint: bool = False) -> Workload:
+         adjoint: bool = False, pspace: str = "P") -> Workload:
     r_ref, r_a, r_b, r_s, r_d, r_w = _rngs(config_id, seed, 6)
     refined = random_refined_columns(nx, ny, frac_refined, r_ref)
-    mesh = column_mesh(k, nx, ny, nz, refined=refined, extent=(L, L, H), base_normal_dirichlet=True)
+    mesh = column_mesh(k, nx, ny, nz, refined=refined, extent=(L, L, H), base_normal_dirichlet=True, pspace=pspace)
     logA = r_a.normal(0.0, 0.5, mesh.n_el)
     beta = np.exp(r_b.normal(0.0, 1.0, mesh.n_bface)) if beta_lognormal else np.ones(mesh.n_bface)
     u, p = _slab_state(mesh, L, r_s)
@@ -92,20 +92,20 @@ def slab(config_id: int, k: int, nx: int, ny: int, nz: int, L: float, H: float,
     return wl
 
 
-def config2(seed: int = 0, nx: int = 64, ny: int = 64, nz: int = 8, n_dirs: int = 1) -> Workload:
+def config2(seed: int = 0, nx: int = 64, ny: int = 64, nz: int = 8, n_dirs: int = 1, pspace: str = "P") -> Workload:
     """Slab with element size 15.625 x 15.625 x 0.125 (aspect 125), Q3 x P2, 20% refined columns."""
     return slab(2, 3, nx, ny, nz, L=15.625 * nx, H=0.125 * nz, frac_refined=0.2, seed=seed,
-                beta_lognormal=False, n_dirs=n_dirs)
+                beta_lognormal=False, n_dirs=n_dirs, pspace=pspace)
 
 
 def config4(seed: int = 0, nx: int = 96, ny: int = 96, nz: int = 12, frac_refined: float = 0.2,
-            n_dirs: int = 1) -> Workload:
+            n_dirs: int = 1, pspace: str = "P") -> Workload:
     """Config-2 geometry at 96x96x12 (element 1000/96 x 1000/96 x 1/12), beta = exp(N(0,1)), adjoint w."""
     return slab(4, 3, nx, ny, nz, L=1000.0 / 96 * nx, H=nz / 12.0, frac_refined=frac_refined, seed=seed,
-                beta_lognormal=True, n_dirs=n_dirs, adjoint=True)
+                beta_lognormal=True, n_dirs=n_dirs, adjoint=True, pspace=pspace)
 
 
-def config3(seed: int = 0, nx: int = 128, ny: int = 128, nz: int = 16, n_dirs: int = 1) -> Workload:
+def config3(seed: int = 0, nx: int = 128, ny: int = 128, nz: int = 16, n_dirs: int = 1, pspace: str = "P") -> Workload:
     """Terrain-mapped slab, Q4 x P3: base b and thickness H from 8-mode Fourier fields over 500 x 500."""
     r_b, r_h, r_ux, r_uy, r_uz, r_n, r_d = _rngs(3, seed, 7)
     Lfull = 500.0
@@ -123,7 +123,7 @@ def config3(seed: int = 0, nx: int = 128, ny: int = 128, nz: int = 16, n_dirs: i
         H = 0.5 + 1.5 * (fh(x, y) - hmin) / (hmax - hmin)
         return np.stack([x, y, b + lg[:, 2] / nz * H], 1)
 
-    mesh = column_mesh(4, nx, ny, nz, geometry=geometry, extent=(h * nx, h * ny, 1.0))
+    mesh = column_mesh(4, nx, ny, nz, geometry=geometry, extent=(h * nx, h * ny, 1.0), pspace=pspace)
     fields = [FourierField(r, 10, Lfull) for r in (r_ux, r_uy, r_uz)]
     x, y, _ = mesh.coords
     u = np.stack([f(x, y) for f in fields]) + 1e-2 * r_n.uniform(-1, 1, (3, mesh.n_nodes))
@@ -132,7 +132,7 @@ def config3(seed: int = 0, nx: int = 128, ny: int = 128, nz: int = 16, n_dirs: i
                     (0.0, 0.0, 0.0), u, p, _uniform_dirs(r_d, mesh, n_dirs))
 
 
-def config5(seed: int = 0, nx: int = 256, ny: int = 256, nz: int = 8, n_dirs: int = 0) -> Workload:
+def config5(seed: int = 0, nx: int = 256, ny: int = 256, nz: int = 8, n_dirs: int = 0, pspace: str = "P") -> Workload:
     """Dome ice sheet on a flat bed over [-500, 500]^2, Q2 x P1, refined columns along the margin r = 1."""
     r_noise, r_d = _rngs(5, seed, 2)
     half, H0 = 500.0, 2.0
@@ -157,7 +157,7 @@ def config5(seed: int = 0, nx: int = 256, ny: int = 256, nz: int = 8, n_dirs: in
         return np.stack([-half + s * hx, -half + t * (2.0 * half / ny), lg[:, 2] / nz * H], 1)
 
     mesh = column_mesh(2, nx, ny, nz, refined=crossed, geometry=geometry,
-                       extent=(2 * half, 2 * half, H0), base_normal_dirichlet=True)
+                       extent=(2 * half, 2 * half, H0), base_normal_dirichlet=True, pspace=pspace)
     u = np.zeros((3, mesh.n_nodes))
     p = np.zeros((mesh.n_el, mesh.n_p))
     return Workload("config5", mesh, 3.0, 1e-10, 0.5, np.zeros(mesh.n_el), np.ones(mesh.n_bface),

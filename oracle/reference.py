@@ -6,13 +6,16 @@
 * Quadrature: tensor Gauss-Legendre rule with k+1 points per direction (the
   paper says "Gauss nodes of order k"; read as k+1 points, exact for
   polynomials of degree 2k+1 per direction).
-* Pressure: P_{k-1} on the reference cube (Sec. 3.2.2), basis of products of
-  normalised Legendre polynomials Lhat_i(x) Lhat_j(y) Lhat_l(z) with
-  i+j+l <= k-1 and Lhat_i = sqrt((2i+1)/2) P_i, ordered by (i+j+l, l, j, i).
-  The paper does not fix the basis for this pair; this one is orthonormal on
-  the reference cube, so the pressure mass is near-diagonal on near-affine
-  elements, which is the property the paper asks of its pressure basis
-  (Sec. 6).
+* Pressure, two spaces (Sec. 3.2.2):
+  - "P": P_{k-1} on the reference cube, basis of products of normalised
+    Legendre polynomials Lhat_i(x) Lhat_j(y) Lhat_l(z) with i+j+l <= k-1 and
+    Lhat_i = sqrt((2i+1)/2) P_i, ordered by (i+j+l, l, j, i).  The paper does
+    not fix the basis for this pair; this one is orthonormal on the reference
+    cube, so the pressure mass is near-diagonal on near-affine elements, which
+    is the property the paper asks of its pressure basis (Sec. 6);
+  - "Q": Q_{k-2}, the Lagrange basis on the tensor product of the k-1 Gauss
+    points per direction (the basis Sec. 6 gives for this pair), ordered with
+    the x index fastest.
 
 The 3D tables are formed as dense products over all (quadrature point, node)
 pairs -- deliberately no sum factorisation.
@@ -69,6 +72,12 @@ def legendre_normalised(i: int, x: np.ndarray) -> np.ndarray:
     return npleg.legval(x, c)
 
 
+def pressure_q_indices(k: int):
+    """(i, j, l) of the Q_{k-2} Gauss-point Lagrange basis, x index fastest."""
+    m = k - 1
+    return [(i, j, l) for l in range(m) for j in range(m) for i in range(m)]
+
+
 def pressure_exponents(k: int):
     """(i, j, l) with i+j+l <= k-1, ordered by (i+j+l, l, j, i)."""
     out = []
@@ -82,8 +91,9 @@ def pressure_exponents(k: int):
 class ReferenceElement:
     """Dense tables on the reference cube for polynomial degree k."""
 
-    def __init__(self, k: int):
+    def __init__(self, k: int, pspace: str = "P"):
         self.k = k
+        self.pspace = pspace
         self.P = k + 1
         P = self.P
         self.xi = gll_nodes(k)
@@ -106,10 +116,20 @@ class ReferenceElement:
         self.wq = self.w1[i0] * self.w1[i1] * self.w1[i2]
         self.qpts = np.stack([self.g[i0], self.g[i1], self.g[i2]], 1)
         # pressure basis psi_m at volume quadrature points
-        self.pexp = pressure_exponents(k)
+        if pspace == "P":
+            self.pexp = pressure_exponents(k)
+            self.Psi = np.stack([legendre_normalised(i, self.qpts[:, 0]) * legendre_normalised(j, self.qpts[:, 1])
+                                 * legendre_normalised(l, self.qpts[:, 2]) for (i, j, l) in self.pexp], 1)
+        elif pspace == "Q":
+            self.pexp = pressure_q_indices(k)
+            self.gp, _ = npleg.leggauss(k - 1)
+            Lx, _ = lagrange(self.gp, self.qpts[:, 0])
+            Ly, _ = lagrange(self.gp, self.qpts[:, 1])
+            Lz, _ = lagrange(self.gp, self.qpts[:, 2])
+            self.Psi = np.stack([Lx[:, i] * Ly[:, j] * Lz[:, l] for (i, j, l) in self.pexp], 1)
+        else:
+            raise ValueError("pspace must be 'P' or 'Q'")
         self.n_p = len(self.pexp)
-        self.Psi = np.stack([legendre_normalised(i, self.qpts[:, 0]) * legendre_normalised(j, self.qpts[:, 1])
-                             * legendre_normalised(l, self.qpts[:, 2]) for (i, j, l) in self.pexp], 1)
         # bottom face zeta = -1: face Gauss points (g_i, g_j, -1), face weights w_i w_j
         f0 = np.tile(idx, P)
         f1 = np.repeat(idx, P)
@@ -120,6 +140,16 @@ class ReferenceElement:
         dPhif[:, :, 1] = B1[f0][:, i0] * D1[f1][:, i1] * Bm1[0][i2][None, :]
         self.dPhif = dPhif
         self.wf = self.w1[f0] * self.w1[f1]
+
+    def eval_pressure_basis(self, xi3: np.ndarray) -> np.ndarray:
+        """Values of the n_p pressure basis functions at reference points xi3 [m, 3] -> [m, n_p]."""
+        if self.pspace == "P":
+            return np.stack([legendre_normalised(i, xi3[:, 0]) * legendre_normalised(j, xi3[:, 1])
+                             * legendre_normalised(l, xi3[:, 2]) for (i, j, l) in self.pexp], 1)
+        Lx, _ = lagrange(self.gp, xi3[:, 0])
+        Ly, _ = lagrange(self.gp, xi3[:, 1])
+        Lz, _ = lagrange(self.gp, xi3[:, 2])
+        return np.stack([Lx[:, i] * Ly[:, j] * Lz[:, l] for (i, j, l) in self.pexp], 1)
 
     def eval_basis(self, xi3: np.ndarray) -> np.ndarray:
         """Values of all P^3 nodal basis functions at reference points xi3 [m, 3] -> [m, P^3]."""

@@ -55,7 +55,7 @@ class StokesOracle:
                  elems=None):
         self.mesh = mesh
         self.n, self.eps, self.B0 = float(n), float(eps), float(B0)
-        self.ref = ReferenceElement(mesh.k)
+        self.ref = ReferenceElement(mesh.k, getattr(mesh, "pspace", "P"))
         ref = self.ref
         self.S = ref.P ** 3
         self.elems = np.arange(mesh.n_el) if elems is None else np.asarray(elems, dtype=np.int64)

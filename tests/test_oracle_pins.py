@@ -17,10 +17,23 @@ from oracle.stokes import newton_tensor
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def hanging_mesh(k, seed=1, nx=4, ny=4, nz=2, frac=0.3, extent=(40.0, 40.0, 1.0), mask=False, geometry=None):
+def hanging_mesh(k, seed=1, nx=4, ny=4, nz=2, frac=0.3, extent=(40.0, 40.0, 1.0), mask=False, geometry=None,
+                 pspace="P"):
     rng = np.random.default_rng(seed)
     ref = random_refined_columns(nx, ny, frac, rng)
-    return column_mesh(k, nx, ny, nz, refined=ref, extent=extent, base_normal_dirichlet=mask, geometry=geometry)
+    return column_mesh(k, nx, ny, nz, refined=ref, extent=extent, base_normal_dirichlet=mask, geometry=geometry,
+                       pspace=pspace)
+
+
+def exact_gauss(m):
+    """m-point Gauss-Legendre nodes and weights from the exact roots of P_m (sympy), w = 2/((1-x^2) P_m'(x)^2)."""
+    x = sympy.Symbol("x")
+    if m == 1:
+        return np.array([0.0]), np.array([2.0])
+    roots = sorted(sympy.solve(sympy.legendre(m, x), x), key=lambda r: float(r))
+    dP = sympy.diff(sympy.legendre(m, x), x)
+    w = [2 / ((1 - r ** 2) * dP.subs(x, r) ** 2) for r in roots]
+    return np.array([float(r) for r in roots]), np.array([float(sympy.nsimplify(v)) for v in w])
 
 
 def terrain(nx, ny, nz, L):
@@ -59,6 +72,25 @@ def test_pressure_basis_orthonormal(k):
     M = ref.Psi.T @ (ref.wq[:, None] * ref.Psi)
     assert ref.n_p == k * (k + 1) * (k + 2) // 6
     assert np.allclose(M, np.eye(ref.n_p), atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_pressure_q_basis(k):
+    """Q_{k-2} pressure basis (Sec. 6: Lagrange basis on the tensor Gauss points): dimension (k-1)^3, the
+    interpolation property at the exact Gauss points, partition of unity, and a diagonal reference mass equal
+    to the products of the exact Gauss weights (the (k+1)-point rule integrates psi_m psi_n exactly)."""
+    ref = ReferenceElement(k, "Q")
+    m = k - 1
+    assert ref.n_p == m ** 3
+    gx, gw = exact_gauss(m)
+    pts = np.array([(gx[i], gx[j], gx[l]) for l in range(m) for j in range(m) for i in range(m)])
+    assert np.allclose(ref.eval_pressure_basis(pts), np.eye(ref.n_p), atol=1e-13)
+    rng = np.random.default_rng(5)
+    r = rng.uniform(-1, 1, (50, 3))
+    assert np.allclose(ref.eval_pressure_basis(r).sum(axis=1), 1.0, atol=1e-13)
+    M = ref.Psi.T @ (ref.wq[:, None] * ref.Psi)
+    W = np.array([gw[i] * gw[j] * gw[l] for l in range(m) for j in range(m) for i in range(m)])
+    assert np.allclose(M, np.diag(W), atol=1e-13)
 
 
 # ---------------------------------------------------------------- P8 worked example (figure "interp")
@@ -116,11 +148,11 @@ def test_hanging_continuity(k):
 
 
 # ---------------------------------------------------------------- P1 rigid modes, P2 kernel of B
-@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("k,pspace", [(2, "P"), (3, "P"), (4, "P"), (3, "Q"), (4, "Q")])
 @pytest.mark.parametrize("mapped", [False, True])
-def test_rigid_modes_in_kernel(k, mapped):
+def test_rigid_modes_in_kernel(k, pspace, mapped):
     geo = terrain(4, 4, 2, 40.0) if mapped else None
-    mesh = hanging_mesh(k, geometry=geo)
+    mesh = hanging_mesh(k, geometry=geo, pspace=pspace)
     rng = np.random.default_rng(2)
     o = StokesOracle(mesh, 3.0, 1e-10, 0.5, rng.normal(0, 0.5, mesh.n_el), np.zeros(mesh.n_bface))
     o.set_state(rng.uniform(-1, 1, (3, mesh.n_nodes)), rng.uniform(-1, 1, (mesh.n_el, mesh.n_p)))
@@ -137,8 +169,9 @@ def test_rigid_modes_in_kernel(k, mapped):
 
 
 @pytest.mark.parametrize("k", [2, 3, 4])
-def test_divergence_free_in_kernel_of_B(k):
-    mesh = hanging_mesh(k, extent=(4.0, 4.0, 1.0))
+@pytest.mark.parametrize("pspace", ["P", "Q"])
+def test_divergence_free_in_kernel_of_B(k, pspace):
+    mesh = hanging_mesh(k, extent=(4.0, 4.0, 1.0), pspace=pspace)
     o = StokesOracle(mesh)
     o.set_state(np.zeros((3, mesh.n_nodes)), np.zeros((mesh.n_el, mesh.n_p)))
     x, y, z = mesh.coords
@@ -147,12 +180,19 @@ def test_divergence_free_in_kernel_of_B(k):
     Bg = K[N:, :N]
     u = np.stack([y ** 2, z ** 2, x ** 2]).ravel()                    # div u = 0, degree 2 <= k
     assert np.max(np.abs(Bg @ u)) < 1e-12 * np.max(np.abs(Bg)) * np.max(np.abs(u)) * 10
-    # u = (x, 0, 0): div u = 1, so (B u)_m = -int psi_m = -2 sqrt(2) |K| delta_m0 (orthonormal basis)
+    # u = (x, 0, 0): div u = 1, so (B u)_m = -int psi_m: P_{k-1} (orthonormal) -2 sqrt(2) |K|/8 delta_m0;
+    # Q_{k-2} (Gauss-point Lagrange) -|K|/8 times the product of the exact Gauss weights of mode m
     u1 = np.concatenate([x, 0 * x, 0 * x])
     Bu = (Bg @ u1).reshape(mesh.n_el, mesh.n_p)
     vol = np.where(mesh.elem_level == 0, 1.0, 0.125) * (4.0 / 4) * (4.0 / 4) * (1.0 / 2)
     expect = np.zeros_like(Bu)
-    expect[:, 0] = -2.0 * np.sqrt(2.0) * vol / 8.0
+    if pspace == "P":
+        expect[:, 0] = -2.0 * np.sqrt(2.0) * vol / 8.0
+    else:
+        m = k - 1
+        _, gw = exact_gauss(m)
+        W = np.array([gw[i] * gw[j] * gw[l] for l in range(m) for j in range(m) for i in range(m)])
+        expect[:] = -vol[:, None] / 8.0 * W[None, :]
     assert np.allclose(Bu, expect, atol=1e-13)
 
 
@@ -238,10 +278,10 @@ def test_linear_stokes_residual_is_linear():
 
 
 # ---------------------------------------------------------------- P4 symmetry, P5 Newton consistency
-@pytest.mark.parametrize("k", [2, 3])
-def test_jacobian_symmetric_and_complex_step(k):
+@pytest.mark.parametrize("k,pspace", [(2, "P"), (3, "P"), (3, "Q")])
+def test_jacobian_symmetric_and_complex_step(k, pspace):
     geo = terrain(3, 3, 2, 30.0)
-    mesh = hanging_mesh(k, seed=7, nx=3, ny=3, frac=0.35, mask=True, geometry=geo)
+    mesh = hanging_mesh(k, seed=7, nx=3, ny=3, frac=0.35, mask=True, geometry=geo, pspace=pspace)
     rng = np.random.default_rng(11)
     o = StokesOracle(mesh, 3.0, 1e-10, 0.5, rng.normal(0, 0.5, mesh.n_el), np.exp(rng.normal(0, 1, mesh.n_bface)),
                      body=(0.0, 0.1, -1.0))
