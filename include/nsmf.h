@@ -1,8 +1,8 @@
 /*
  * nsmf.h -- matrix-free Newton-Stokes operator engine for AMD MI355X (gfx950).
  *
- * C ABI of the engine that applies, matrix-free on hexahedral Q_k x P_{k-1}^disc
- * meshes (k = 2, 3, 4) with 2:1 hanging nodes:
+ * C ABI of the engine that applies, matrix-free on hexahedral Q_k x P_{k-1}^disc or
+ * Q_k x Q_{k-2}^disc meshes (k = 2, 3, 4; Sec. 3.2.2) with 2:1 hanging nodes:
  *   - the nonlinear residual of the Glen-law Stokes problem, eq. (weak) with the
  *     viscosity of eq. (glen) (Sec. 2.1-2.2 of the paper);
  *   - the Newton-linearised saddle-point operator A(u) = [[F(u), B^T], [B, 0]]
@@ -17,9 +17,12 @@
  *     the work enqueued on the context's stream has completed.  Host arrays appear
  *     only in nsmf_mesh and are copied during nsmf_upload_mesh.
  *   - Velocity vectors are structure-of-arrays [3][n_nodes] (x, y, z components),
- *     pressure vectors are element-major [n_el][n_p], n_p = k(k+1)(k+2)/6, with the
- *     basis of normalised Legendre products Lhat_i(xi) Lhat_j(eta) Lhat_l(zeta),
- *     i+j+l <= k-1, ordered by (i+j+l, l, j, i) on each element's reference cube.
+ *     pressure vectors are element-major [n_el][n_p] on each element's reference cube:
+ *       P_{k-1} (nsmf_mesh.pspace = NSMF_PSPACE_P): n_p = k(k+1)(k+2)/6, basis of
+ *         normalised Legendre products Lhat_i(xi) Lhat_j(eta) Lhat_l(zeta), i+j+l <= k-1,
+ *         ordered by (i+j+l, l, j, i);
+ *       Q_{k-2} (NSMF_PSPACE_Q): n_p = (k-1)^3, the Lagrange basis on the tensor product
+ *         of the k-1 Gauss points per direction (Sec. 6), mode i + (k-1)(j + (k-1) l).
  *   - Work is enqueued asynchronously on the stream given by nsmf_set_stream
  *     (default: the null stream); no call synchronises except nsmf_upload_mesh
  *     (which validates the geometry on the device) and nsmf_kernel_time.
@@ -80,6 +83,8 @@ typedef enum {
  *   9..20  hanging edge 4*dir + s0 + 2*s1, dir 0/1/2 = parallel to x/y/z, (s0, s1)
  *          the side (0 low / 1 high) along the two other axes in increasing order.
  */
+typedef enum { NSMF_PSPACE_P = 0, NSMF_PSPACE_Q = 1 } nsmf_pspace;
+
 typedef struct {
   int32_t k;                    /* polynomial degree of velocity: 2, 3 or 4                 */
   int64_t n_el;                 /* number of elements (> 0)                                  */
@@ -90,6 +95,7 @@ typedef struct {
   const double *coords;         /* [3][n_nodes] node coordinates                             */
   const int32_t *bface_elem;    /* [n_bface] elements whose zeta = -1 face lies on the base  */
   const uint8_t *dmask;         /* [3][n_nodes] 1 = Dirichlet-constrained component; may be NULL */
+  int32_t pspace;               /* pressure space, nsmf_pspace (0 = P_{k-1}, 1 = Q_{k-2})    */
 } nsmf_mesh;
 
 /* Glen law (eq. (glen)): mu = B0 * exp(-logA_e / n) * (II + eps)^((1-n)/(2n)),

@@ -42,7 +42,7 @@ struct nsmf_ctx {
   std::string err = "";
   // mesh
   bool have_mesh = false;
-  int k = 0, P = 0, n_p = 0, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0;
+  int k = 0, P = 0, n_p = 0, ps = PS_P, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0;
   int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_inc = 0;
   HostTables tab;
   DevBuf<uint32_t> en, cmask;
@@ -149,6 +149,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   if (!ctx || !m) return NSMF_EINVAL;
   NSMF_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (m->k < 2 || m->k > 4) return ctx->fail(NSMF_EUNSUP, "k must be 2, 3 or 4");
+  if (m->pspace != PS_P && m->pspace != PS_Q) return ctx->fail(NSMF_EINVAL, "pspace must be 0 (P_{k-1}) or 1 (Q_{k-2})");
   if (m->n_el <= 0 || m->n_nodes <= 0 || m->n_bface < 0) return ctx->fail(NSMF_EINVAL, "sizes must be positive");
   if (m->n_nodes >= (int64_t)NODE_MASK) return ctx->fail(NSMF_EINVAL, "n_nodes must be below 2^28");
   if (!m->elem_nodes || !m->cmask || !m->coords || (m->n_bface > 0 && !m->bface_elem))
@@ -207,7 +208,8 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   }
   ctx->k = m->k;
   ctx->P = P;
-  build_tables(m->k, &ctx->tab);
+  build_tables(m->k, m->pspace, &ctx->tab);
+  ctx->ps = m->pspace;
   ctx->n_p = ctx->tab.n_p;
   ctx->n_el = n_el;
   ctx->n_nodes = N;
@@ -375,7 +377,7 @@ int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p) {
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "residual needs a state");
   hipStream_t s = ctx->stream;
   NSMF_TRY(ctx,
-           launch_residual(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->fst64.p,
+           launch_residual(ctx->P, ctx->geo, ctx->ps, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->fst64.p,
                            ctx->beta64.p, ctx->p.p, ctx->prm.body, ctx->ev.p, r_p),
            "residual kernel");
   NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p,
@@ -404,7 +406,7 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
   const void *fst = prec == 0 ? (const void *)ctx->fst64.p : (const void *)ctx->fst32.p;
   const void *beta = prec == 0 ? (const void *)ctx->beta64.p : (const void *)ctx->beta32.p;
   NSMF_TRY(ctx,
-           launch_apply(ctx->P, ctx->geo, prec, vjp, s, ctx->mesh_view(), gv, ctx->tabs.p, st, fst, beta, x_u, x_p,
+           launch_apply(ctx->P, ctx->geo, ctx->ps, prec, vjp, s, ctx->mesh_view(), gv, ctx->tabs.p, st, fst, beta, x_u, x_p,
                         y_u ? (void *)ctx->ev.p : nullptr, y_p, 1.0 / ctx->prm.n, g_logA, g_beta),
            "apply kernel");
   if (y_u)
@@ -432,7 +434,7 @@ int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p) {
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "jacobi_diag needs a state");
   hipStream_t s = ctx->stream;
   NSMF_TRY(ctx,
-           launch_diag(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->beta64.p,
+           launch_diag(ctx->P, ctx->geo, ctx->ps, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->beta64.p,
                        ctx->ev.p, d_p),
            "diagonal kernel");
   NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p, nullptr,

@@ -36,17 +36,22 @@ template <> struct Launch<5> { static constexpr int E = NSMF_E5; static constexp
 // element-vector store entries per block: the block's E P^3 slots, padded to a multiple of NT
 template <int P> constexpr int store_slots() { return (Launch<P>::E * P * P * P + Launch<P>::NT - 1) / Launch<P>::NT * Launch<P>::NT; }
 
-// Reference-element tables (passed by value as kernel arguments, read through the
-// scalar cache).  Indices: q = Gauss point, a = Gauss-Lobatto node.
+// Reference-element tables (device memory, read through a restrict pointer).  Indices: q =
+// Gauss point, a = Gauss-Lobatto node.
 template <typename T, int P> struct Tab {
   T B[P][P];        // B[q][a]  = l_a(g_q)         Lagrange basis at Gauss points
   T D[P][P];        // D[q][a]  = l_a'(g_q)        its derivative
   T I[P][P];        // I[i][m] = l_m(child node i of the lower half [-1, 0]); the upper half is its
                     // mirror image, I_upper[i][m] = I[P-1-i][P-1-m] (symmetric nodes)
-  T L[P - 1][P];    // L[j][q]  = sqrt((2j+1)/2) P_j(g_q)  normalised Legendre at Gauss points
+  T L[P - 1][P];    // 1D pressure factors at the Gauss points: P_{k-1} space, L[j][q] =
+                    // sqrt((2j+1)/2) P_j(g_q) (normalised Legendre, j < k); Q_{k-2} space,
+                    // L[j][q] = lambda_j(g_q), the Lagrange basis on the k-1 Gauss points (j < k-1)
   T w[P];           // Gauss weights
-  int8_t pe[(P - 1) * P * (P + 1) / 6][3];  // pressure basis exponents (i, j, l)
 };
+
+// Pressure spaces (Sec. 3.2.2): P_{k-1} with normalised Legendre products, or Q_{k-2} with the
+// Lagrange basis on the tensor Gauss points (Sec. 6).
+enum PSpace { PS_P = 0, PS_Q = 1 };
 
 // FP64 tables for degree k = P-1 computed on the host (Newton iterations for the nodes).
 struct HostTables {
@@ -54,9 +59,8 @@ struct HostTables {
   double xi[5], g[5], w[5];
   double B[5][5], D[5][5], I[2][5][5], L[4][5];
   int n_p;
-  int8_t pe[20][3];
 };
-void build_tables(int k, HostTables *t);
+void build_tables(int k, int pspace, HostTables *t);
 
 template <typename T, int P> Tab<T, P> make_tab(const HostTables &h, bool bf16_ops);
 
@@ -100,14 +104,14 @@ hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &
 hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                         const void *tabs, const double *u, const double *logA, double n, double eps,
                         double B0, double *st64, float *st32, double *fst64, float *fst32);
-hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *geo_view,
+hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *geo_view,
                         const void *tabs, const void *state, const void *fstate, const void *beta,
                         const void *x_u, const void *x_p, void *y_u, void *y_p, double inv_n,
                         double *g_logA, double *g_beta);
-hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
+hipError_t launch_residual(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                            const void *tabs, const double *st64, const double *fst64, const double *beta,
                            const double *p, const double *body, double *r_u, double *r_p);
-hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+hipError_t launch_diag(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                        const double *st, const double *beta, double *ev, double *dp);
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,

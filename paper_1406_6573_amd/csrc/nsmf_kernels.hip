@@ -453,29 +453,43 @@ __device__ __forceinline__ void to_ref(const QpGeo<T, P, GEO> &g, int i, const T
 }
 
 // ---------------------------------------------------------------- pressure basis
-// Exponents (i, j, l) of the pressure basis, i+j+l <= k-1 ordered by (i+j+l, l, j, i), as
-// compile-time constants so that register arrays indexed by them stay in registers.
-template <int P> struct PExp {
-  static constexpr int NP = (P - 1) * P * (P + 1) / 6;
+// Pressure modes: number per element, and the (i, j, l) indices of the 1D factors of each mode,
+// as compile-time constants so that register arrays indexed by them stay in registers.
+// P_{k-1}: exponents i+j+l <= k-1, ordered by (i+j+l, l, j, i); Q_{k-2}: the k-1 Gauss points
+// per direction, i fastest.  psi_m(x_i, y_j, z_l) = L[e0][i] L[e1][j] L[e2][l] at Gauss points.
+template <int P, int PS> constexpr int n_pres() { return PS == PS_P ? (P - 1) * P * (P + 1) / 6 : (P - 2) * (P - 2) * (P - 2); }
+template <int P, int PS> struct PExp {
+  static constexpr int NP = n_pres<P, PS>();
   int e[NP][3];
   constexpr PExp() : e{} {
     int m = 0;
-    for (int d = 0; d < P - 1; ++d)
-      for (int l = 0; l <= d; ++l)
-        for (int j = 0; j <= d - l; ++j) {
-          e[m][0] = d - l - j;
-          e[m][1] = j;
-          e[m][2] = l;
-          ++m;
-        }
+    if (PS == PS_P) {
+      for (int d = 0; d < P - 1; ++d)
+        for (int l = 0; l <= d; ++l)
+          for (int j = 0; j <= d - l; ++j) {
+            e[m][0] = d - l - j;
+            e[m][1] = j;
+            e[m][2] = l;
+            ++m;
+          }
+    } else {
+      for (int l = 0; l < P - 2; ++l)
+        for (int j = 0; j < P - 2; ++j)
+          for (int i = 0; i < P - 2; ++i) {
+            e[m][0] = i;
+            e[m][1] = j;
+            e[m][2] = l;
+            ++m;
+          }
+    }
   }
 };
 // x-line thread (j, z): p(i) = sum_m xp[m] L_{e0}(g_i) L_{e1}(g_j) L_{e2}(g_z)
-template <typename T, int P>
+template <typename T, int P, int PS>
 __device__ __forceinline__ void pressure_interp(const T *xp, const Tab<T, P> &tb, int t, T (&pq)[P]) {
-  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  constexpr int NP = n_pres<P, PS>();
   const int j = t % P, z = t / P;
-  constexpr PExp<P> pe{};
+  constexpr PExp<P, PS> pe{};
   T pa[P - 1];
 #pragma unroll
   for (int a = 0; a < P - 1; ++a) pa[a] = 0;
@@ -490,10 +504,9 @@ __device__ __forceinline__ void pressure_interp(const T *xp, const Tab<T, P> &tb
   }
 }
 // partial test sums: part[m] = sum_i d[i] psi_m(i, j, z) on the thread's x-line
-template <typename T, int P>
-__device__ __forceinline__ void pressure_test(const T (&d)[P], const Tab<T, P> &tb, int t,
-                                              T (&part)[(P - 1) * P * (P + 1) / 6]) {
-  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+template <typename T, int P, int PS>
+__device__ __forceinline__ void pressure_test(const T (&d)[P], const Tab<T, P> &tb, int t, T (&part)[n_pres<P, PS>()]) {
+  constexpr int NP = n_pres<P, PS>();
   const int j = t % P, z = t / P;
   T qa[P - 1];
 #pragma unroll
@@ -503,29 +516,31 @@ __device__ __forceinline__ void pressure_test(const T (&d)[P], const Tab<T, P> &
     for (int i = 0; i < P; ++i) s += tb.L[a][i] * d[i];
     qa[a] = s;
   }
-  constexpr PExp<P> pe{};
+  constexpr PExp<P, PS> pe{};
 #pragma unroll
   for (int m = 0; m < NP; ++m) part[m] = qa[pe.e[m][0]] * tb.L[pe.e[m][1]][j] * tb.L[pe.e[m][2]][z];
 }
-
-// Sum the NP partials over the P*P threads of each element and store -sum into y_p[e].
-// Uses buffers 0..4 of the element workspace; all threads call; two barriers.
-template <typename T, int P>
-__device__ void pressure_reduce(const T (&part)[(P - 1) * P * (P + 1) / 6], Ws<T, P> w, int t, bool act,
-                                T *yp_e) {
-  constexpr int NP = (P - 1) * P * (P + 1) / 6, P2 = P * P;
-  if (act)
+// Sum the NP partials over the P*P threads of each element and store -sum into y_p[e], in passes
+// of as many modes as the element workspace holds.  All threads of the block must call.
+template <typename T, int P, int NP>
+__device__ void pressure_reduce(const T (&part)[NP], Ws<T, P> w, int t, bool act, T *yp_e) {
+  constexpr int P2 = P * P, MC = Ws<T, P>::ES / (P2 + 1);
+  static_assert(MC >= 1, "element workspace too small for the pressure reduction");
 #pragma unroll
-    for (int m = 0; m < NP; ++m) w.s[m * (P2 + 1) + t] = part[m];
-  __syncthreads();
-  if (act && yp_e != nullptr) {
-    for (int m = t; m < NP; m += P2) {
-      T s = 0;
-      for (int r = 0; r < P2; ++r) s += w.s[m * (P2 + 1) + r];
-      yp_e[m] = -s;
+  for (int m0 = 0; m0 < NP; m0 += MC) {
+    if (act)
+#pragma unroll
+      for (int m = m0; m < (m0 + MC < NP ? m0 + MC : NP); ++m) w.s[(m - m0) * (P2 + 1) + t] = part[m];
+    __syncthreads();
+    if (act && yp_e != nullptr) {
+      for (int m = m0 + t; m < (m0 + MC < NP ? m0 + MC : NP); m += P2) {
+        T s = 0;
+        for (int r = 0; r < P2; ++r) s += w.s[(m - m0) * (P2 + 1) + r];
+        yp_e[m] = -s;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // double-precision sum over the P*P threads of an element (for parameter gradients)
@@ -690,14 +705,14 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
 
 // ================================================================= kernels
 // Jacobian apply (and VJP): y = J_c x at the stored linearisation point.
-template <typename T, int P, int GEO, bool VJP>
+template <typename T, int P, int GEO, bool VJP, int PS>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *__restrict__ st, const T *__restrict__ fst,
         const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
         T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
   const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
-  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  constexpr int NP = n_pres<P, PS>();
   __shared__ T smem[E * Ws<T, P>::ES];
   __shared__ double red[E * P2];
   const int lb = logical_block();
@@ -742,7 +757,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   __syncthreads();
 
   T pq[P];
-  if (act) pressure_interp<T, P>(xpl, tb, t, pq);
+  if (act) pressure_interp<T, P, PS>(xpl, tb, t, pq);
   T dw[P];
   double gA = 0.0;
   if constexpr (!kEarlyState) {
@@ -790,8 +805,8 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   // pressure rows: y_p[e][m] = -sum_q w detJ psi_m div x
   {
     T part[NP];
-    if (act) pressure_test<T, P>(dw, tb, t, part);
-    pressure_reduce<T, P>(part, w, t, act, (act && yp != nullptr) ? yp + e * NP : nullptr);
+    if (act) pressure_test<T, P, PS>(dw, tb, t, part);
+    pressure_reduce<T, P, NP>(part, w, t, act, (act && yp != nullptr) ? yp + e * NP : nullptr);
   }
   if (VJP) {
     const double sA = elem_sum64<P>(gA, redl, t, act);
@@ -912,7 +927,7 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
 
 // Residual at the linearisation point (FP64): tau = Sigma0 - p w detJ I, body force,
 // basal term beta w|S| T u, pressure rows -int psi div u.
-template <int P, int GEO>
+template <int P, int GEO, int PS>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ st,
            const double *__restrict__ fst, const double *__restrict__ beta, const double *__restrict__ p, double bx,
@@ -920,7 +935,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
   using T = double;
   const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
-  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  constexpr int NP = n_pres<P, PS>();
   __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
@@ -940,7 +955,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
     T pq[P], xpl[NP];
 #pragma unroll
     for (int mm = 0; mm < NP; ++mm) xpl[mm] = p[e * NP + mm];
-    pressure_interp<T, P>(xpl, tb, t, pq);
+    pressure_interp<T, P, PS>(xpl, tb, t, pq);
     T stv[NSTATE][P];
 #pragma unroll
     for (int f = 0; f < NSTATE; ++f) load_field<T, P, NT, NSTATE>(st, lb, f, tid, stv[f]);
@@ -976,8 +991,8 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
   }
   {
     T part[NP];
-    if (act) pressure_test<T, P>(dw, tb, t, part);
-    pressure_reduce<T, P>(part, w, t, act, act ? rp + e * NP : nullptr);
+    if (act) pressure_test<T, P, PS>(dw, tb, t, part);
+    pressure_reduce<T, P, NP>(part, w, t, act, act ? rp + e * NP : nullptr);
   }
   T y[3][P];
 #pragma unroll
@@ -1005,7 +1020,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
 // beta w|S| phi_a^2 (1 - n_c^2); hanging slots reach their parent nodes through squared
 // interpolation weights (tb2), i.e. sum_e sum_a R_e[a,n]^2 F_e[a,a].  Pressure: the lumped
 // mass weighted by 1/mu with a minus sign, the Schur-complement approximation of Sec. 6.
-template <int P, int GEO>
+template <int P, int GEO, int PS>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
        const Tab<double, P> *__restrict__ tb2p, const double *__restrict__ st,
@@ -1013,7 +1028,7 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   using T = double;
   const Tab<T, P> &tb = *tbp, &tb2 = *tb2p;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
-  constexpr int NP = (P - 1) * P * (P + 1) / 6;
+  constexpr int NP = n_pres<P, PS>();
   __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
@@ -1061,7 +1076,7 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
         // thread accumulates the points of its own tq = t for the lumped 1/mu mass
         if (tq == t) {
           const double g = wd * wd / mu;
-          constexpr PExp<P> pe{};
+          constexpr PExp<P, PS> pe{};
 #pragma unroll
           for (int mm = 0; mm < NP; ++mm) {
             const double psi = tb.L[pe.e[mm][0]][qx] * tb.L[pe.e[mm][1]][qy] * tb.L[pe.e[mm][2]][qz];
@@ -1099,7 +1114,7 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
     }
   }
   // lumped -M(1/mu): thread t holds the points of x-line t, reduce over the element's threads
-  pressure_reduce<T, P>(part, w, t, act, act ? dp + e * NP : nullptr);
+  pressure_reduce<T, P, NP>(part, w, t, act, act ? dp + e * NP : nullptr);
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb2, t, act);
   evec_store<T, P>(ev, m, lb, e, smem, els, t, act, y);
 }
@@ -1368,44 +1383,46 @@ hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const 
   return hipErrorInvalidValue;
 }
 
-template <int P, int GEO>
+template <int P, int GEO, int PS>
 static hipError_t residual_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                               const double *st, const double *fst, const double *beta, const double *p,
                               const double *body, double *ru, double *rp) {
-  hipLaunchKernelGGL((k_residual<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &((const TabSet<P> *)tabs)->d, st, fst, beta, p,
+  hipLaunchKernelGGL((k_residual<P, GEO, PS>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &((const TabSet<P> *)tabs)->d, st, fst, beta, p,
                      body[0], body[1], body[2], ru, rp);
   return hipGetLastError();
 }
-hipError_t launch_residual(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
+hipError_t launch_residual(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                            const void *tabs, const double *st, const double *fst, const double *beta,
                            const double *p, const double *body, double *ru, double *rp) {
-#define NSMF_RS(PP, GG) \
-  if (P == PP && geo == GG) return residual_pg<PP, GG>(s, m, g, tabs, st, fst, beta, p, body, ru, rp);
+#define NSMF_RS(PP, GG)                                                                                  \
+  if (P == PP && geo == GG && ps == PS_P) return residual_pg<PP, GG, PS_P>(s, m, g, tabs, st, fst, beta, p, body, ru, rp); \
+  if (P == PP && geo == GG && ps == PS_Q) return residual_pg<PP, GG, PS_Q>(s, m, g, tabs, st, fst, beta, p, body, ru, rp);
   NSMF_RS(3, GEO_AFFINE) NSMF_RS(3, GEO_COLUMN) NSMF_RS(4, GEO_AFFINE) NSMF_RS(4, GEO_COLUMN)
   NSMF_RS(5, GEO_AFFINE) NSMF_RS(5, GEO_COLUMN)
 #undef NSMF_RS
   return hipErrorInvalidValue;
 }
 
-template <int P, int GEO>
+template <int P, int GEO, int PS>
 static hipError_t diag_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                           const double *st, const double *beta, double *ev, double *dp) {
   const TabSet<P> *ts = (const TabSet<P> *)tabs;
-  hipLaunchKernelGGL((k_diag<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &ts->d, &ts->dsq, st, beta, ev,
+  hipLaunchKernelGGL((k_diag<P, GEO, PS>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &ts->d, &ts->dsq, st, beta, ev,
                      dp);
   return hipGetLastError();
 }
-hipError_t launch_diag(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+hipError_t launch_diag(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                        const double *st, const double *beta, double *ev, double *dp) {
-#define NSMF_DG(PP, GG) \
-  if (P == PP && geo == GG) return diag_pg<PP, GG>(s, m, g, tabs, st, beta, ev, dp);
+#define NSMF_DG(PP, GG)                                                                           \
+  if (P == PP && geo == GG && ps == PS_P) return diag_pg<PP, GG, PS_P>(s, m, g, tabs, st, beta, ev, dp); \
+  if (P == PP && geo == GG && ps == PS_Q) return diag_pg<PP, GG, PS_Q>(s, m, g, tabs, st, beta, ev, dp);
   NSMF_DG(3, GEO_AFFINE) NSMF_DG(3, GEO_COLUMN) NSMF_DG(4, GEO_AFFINE) NSMF_DG(4, GEO_COLUMN)
   NSMF_DG(5, GEO_AFFINE) NSMF_DG(5, GEO_COLUMN)
 #undef NSMF_DG
   return hipErrorInvalidValue;
 }
 
-template <typename T, int P, int GEO, bool VJP>
+template <typename T, int P, int GEO, bool VJP, int PS>
 static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, const void *tabs, bool bf16,
                           const void *st, const void *fst, const void *beta, const void *xu, const void *xp, void *yu,
                           void *yp, double inv_n, double *gA, double *gB) {
@@ -1413,18 +1430,20 @@ static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, c
   const Tab<T, P> *tb;
   if constexpr (sizeof(T) == 8) tb = &ts->d;
   else tb = bf16 ? &ts->fb : &ts->f;
-  hipLaunchKernelGGL((k_apply<T, P, GEO, VJP>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m,
+  hipLaunchKernelGGL((k_apply<T, P, GEO, VJP, PS>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m,
                      *(const GeoView<T> *)gview, tb, (const T *)st, (const T *)fst, (const T *)beta, (const T *)xu,
                      (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
   return hipGetLastError();
 }
-hipError_t launch_apply(int P, int geo, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *gview,
+hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *gview,
                         const void *tabs, const void *st, const void *fst, const void *beta, const void *xu,
                         const void *xp, void *yu, void *yp, double inv_n, double *gA, double *gB) {
   const bool bf = prec == 2;
 #define NSMF_AP(TT, PP, GG, VV)                                                                                   \
-  if (P == PP && geo == GG && vjp == VV && (sizeof(TT) == 8) == (prec == 0))                                     \
-    return apply_t<TT, PP, GG, VV>(s, m, gview, tabs, bf, st, fst, beta, xu, xp, yu, yp, inv_n, gA, gB);
+  if (P == PP && geo == GG && vjp == VV && (sizeof(TT) == 8) == (prec == 0) && ps == PS_P)                       \
+    return apply_t<TT, PP, GG, VV, PS_P>(s, m, gview, tabs, bf, st, fst, beta, xu, xp, yu, yp, inv_n, gA, gB);  \
+  if (P == PP && geo == GG && vjp == VV && (sizeof(TT) == 8) == (prec == 0) && ps == PS_Q)                       \
+    return apply_t<TT, PP, GG, VV, PS_Q>(s, m, gview, tabs, bf, st, fst, beta, xu, xp, yu, yp, inv_n, gA, gB);
 #define NSMF_AP2(TT, PP) \
   NSMF_AP(TT, PP, GEO_AFFINE, false) NSMF_AP(TT, PP, GEO_COLUMN, false) NSMF_AP(TT, PP, GEO_AFFINE, true) \
   NSMF_AP(TT, PP, GEO_COLUMN, true)

@@ -48,7 +48,7 @@ static double lagrange_deriv(const double *nodes, int n, int a, double x) {
   return tot;
 }
 
-void build_tables(int k, HostTables *t) {
+void build_tables(int k, int pspace, HostTables *t) {
   std::memset(t, 0, sizeof(*t));
   const int P = k + 1;
   t->P = P;
@@ -100,22 +100,39 @@ void build_tables(int k, HostTables *t) {
       double xc = 0.5 * (t->xi[i] + (h ? 1.0 : -1.0));
       for (int m = 0; m < P; ++m) t->I[h][i][m] = lagrange(t->xi, P, m, xc);
     }
-  for (int j = 0; j < k; ++j)
-    for (int q = 0; q < P; ++q) {
-      double p, dp;
-      legendre(j, t->g[q], &p, &dp);
-      t->L[j][q] = std::sqrt((2.0 * j + 1.0) / 2.0) * p;
-    }
-  int m = 0;
-  for (int d = 0; d < k; ++d)
-    for (int l = 0; l <= d; ++l)
-      for (int j = 0; j <= d - l; ++j) {
-        t->pe[m][0] = (int8_t)(d - l - j);
-        t->pe[m][1] = (int8_t)j;
-        t->pe[m][2] = (int8_t)l;
-        ++m;
+  if (pspace == PS_P) {
+    for (int j = 0; j < k; ++j)
+      for (int q = 0; q < P; ++q) {
+        double p, dp;
+        legendre(j, t->g[q], &p, &dp);
+        t->L[j][q] = std::sqrt((2.0 * j + 1.0) / 2.0) * p;
       }
-  t->n_p = m;
+    t->n_p = k * (k + 1) * (k + 2) / 6;
+  } else {
+    // the k-1 Gauss points (roots of P_{k-1}), symmetrised, and their Lagrange basis
+    const int m = k - 1;
+    double gp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < m; ++i) {
+      double x = -std::cos(M_PI * (i + 0.75) / (m + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p, dp;
+        legendre(m, x, &p, &dp);
+        const double dx = p / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-17) break;
+      }
+      gp[i] = x;
+    }
+    for (int i = 0; i < m / 2; ++i) {
+      const double x = 0.5 * (gp[m - 1 - i] - gp[i]);
+      gp[i] = -x;
+      gp[m - 1 - i] = x;
+    }
+    if (m % 2) gp[m / 2] = 0.0;
+    for (int j = 0; j < m; ++j)
+      for (int q = 0; q < P; ++q) t->L[j][q] = lagrange(gp, m, j, t->g[q]);
+    t->n_p = m * m * m;
+  }
 }
 
 static float round_bf16(double v) {
@@ -143,8 +160,6 @@ Tab<T, P> make_tab(const HostTables &h, bool bf16_ops) {
   for (int j = 0; j < P - 1; ++j)
     for (int q = 0; q < P; ++q) t.L[j][q] = (T)h.L[j][q];
   for (int q = 0; q < P; ++q) t.w[q] = (T)h.w[q];
-  for (int m = 0; m < (P - 1) * P * (P + 1) / 6; ++m)
-    for (int d = 0; d < 3; ++d) t.pe[m][d] = h.pe[m][d];
   return t;
 }
 

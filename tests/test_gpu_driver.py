@@ -26,13 +26,14 @@ def setup(torch, case):
     return eng, t
 
 
-@pytest.mark.parametrize("k,mapped", [(2, False), (3, True), (4, False)])
-def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped):
+@pytest.mark.parametrize("k,mapped,pspace", [(2, False, "P"), (3, True, "P"), (4, False, "P"), (3, True, "Q"),
+                                             (4, False, "Q")])
+def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace):
     """d_u = sum_e sum_a R_e[a, n]^2 F_e[aa] (exact diagonal of F on conforming parts), 1 on masked
     rows; d_p = -sum_q w detJ psi_m^2 / mu."""
     from oracle import StokesOracle
     torch = torch_cuda
-    case = small_case(k, mapped=mapped)
+    case = small_case(k, mapped=mapped, pspace=pspace)
     m = case["mesh"]
     eng, t = setup(torch, case)
     d_u, d_p = eng.jacobi_diag()

@@ -12,6 +12,9 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 ROWS = {2: (150, 40), 3: (40, 12), 4: (120, 40), 5: (200, 60)}
+# the workloads as stated (P_{k-1} pressure), and config 2 with the Q_{k-2} pair (Q3 x Q1, the pair of
+# the paper's large runs)
+CASES = [(2, "P"), (3, "P"), (4, "P"), (5, "P"), (2, "Q")]
 
 
 @pytest.fixture(scope="module")
@@ -31,15 +34,15 @@ def sampled(mesh, rng, n_vel, n_pres):
     return nodes, comps, pel, elems
 
 
-@pytest.mark.parametrize("cfg", [2, 3, 4, 5])
-def test_fullsize_sampled_parity(torch_cuda, cfg):
+@pytest.mark.parametrize("cfg,pspace", CASES)
+def test_fullsize_sampled_parity(torch_cuda, cfg, pspace):
     torch = torch_cuda
     from meshgen import make_config
     from oracle import StokesOracle
     from paper_1406_6573_amd import Engine
-    w = make_config(cfg, n_dirs=1)
+    w = make_config(cfg, n_dirs=1, pspace=pspace)
     m = w.mesh
-    print(f"[gpu] full-size config{cfg}: n_el={m.n_el} n_dof={m.n_dof}", flush=True)
+    print(f"[gpu] full-size config{cfg} pressure {pspace}: n_el={m.n_el} n_dof={m.n_dof}", flush=True)
     eng = Engine()
     eng.upload_mesh(m)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")

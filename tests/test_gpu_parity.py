@@ -116,6 +116,22 @@ def test_hanging_small(torch_cuda, k, mapped):
     check_case(torch_cuda, case, f"hanging k={k} mapped={mapped}")
 
 
+def test_config1_qspace(torch_cuda):
+    """Config 1 with the Q_{k-2} pressure pair (Q2 x Q0)."""
+    from meshgen import make_config
+    w = make_config(1, pspace="Q")
+    case = dict(mesh=w.mesh, n=w.n, eps=w.eps, B0=w.B0, logA=w.logA, beta=w.beta, u=w.u, p=w.p, dirs=w.directions)
+    check_case(torch_cuda, case, "config1 8x8x2 Q2xQ0")
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("mapped", [False, True])
+def test_hanging_small_qspace(torch_cuda, k, mapped):
+    """Q_k x Q_{k-2} (Gauss-point Lagrange pressure basis) on hanging, masked, optionally mapped meshes."""
+    case = small_case(k, mapped=mapped, body=(0.0, 0.1, -1.0) if mapped else (0.0, 0.0, 0.0), pspace="Q")
+    check_case(torch_cuda, case, f"hanging k={k} mapped={mapped} Q_(k-2) pressure")
+
+
 def test_rigid_modes_gpu(torch_cuda):
     torch = torch_cuda
     case = small_case(3, mapped=True, mask=False)
