@@ -156,6 +156,23 @@ int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p,
  * preconditioner's action).  Requires a state. */
 int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p);
 
+/* Vertical-line block preconditioner for the velocity block (a plain fallback beside the
+ * block-diagonal preconditioner of Sec. 4.2, whose AMG for F is not part of this engine).
+ * The mesh's nodes form vertical lines: chains linked through the z-lines of the elements
+ * (Sec. 3.1 column structure), built at upload.  For every line and velocity component,
+ * nsmf_line_setup forms the block of F restricted to the line at the current state (eq. (rank4)
+ * tested with the line's basis functions, plus the basal Robin term; couplings through hanging
+ * slots are left out; Dirichlet rows are unit rows) -- banded with bandwidth k, symmetric
+ * positive definite -- and factors it by banded Cholesky in FP64 (with an FP32 copy).
+ * *n_lines (may be NULL) receives the number of lines.  Requires a state; the factors are
+ * invalidated by nsmf_set_state and nsmf_set_params.  Returns NSMF_EUNSUP if the mesh's lines
+ * are not consistent (a node linked to two different nodes above or below it). */
+int nsmf_line_setup(nsmf_ctx *ctx, int64_t *n_lines);
+/* y_u = (line blocks)^{-1} x_u, per component, by forward and backward substitution along each
+ * line.  x_u, y_u [3][n_nodes] DEVICE, double (prec 0, FP64 factors) or float (prec 1, FP32
+ * factors); x_u and y_u must not overlap.  Requires nsmf_line_setup at the current state. */
+int nsmf_line_apply(nsmf_ctx *ctx, int prec, const void *x_u, void *y_u);
+
 /* Vector kernels of the Krylov driver (classical Gram-Schmidt FGMRES, Sec. 4.2) on DEVICE
  * vectors of length n; prec 0: double vectors, 1: float vectors.  Inner products always
  * accumulate in FP64 with a fixed reduction order (deterministic).

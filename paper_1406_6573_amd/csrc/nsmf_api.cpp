@@ -65,6 +65,14 @@ struct nsmf_ctx {
   DevBuf<float> st32, fst32;
   // Krylov vector kernels: partial sums of the multi-dot products
   DevBuf<double> dot_partial;
+  // vertical node lines of the line-block preconditioner: chains of nodes linked through the
+  // conforming z-lines of the elements (host arrays built at upload, copied at the first setup)
+  bool lines_ok = false, have_lines = false;
+  int64_t n_lines = 0;
+  std::vector<int32_t> h_line_ptr, h_line_node, h_lptr, h_lslot;
+  DevBuf<int32_t> line_ptr, line_node, lptr, lslot;
+  DevBuf<double> lbuf, lfac64;
+  DevBuf<float> lfac32;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -99,6 +107,10 @@ struct nsmf_ctx {
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
+    line_ptr.free(); line_node.free(); lptr.free(); lslot.free(); lbuf.free(); lfac64.free(); lfac32.free();
+    h_line_ptr.clear(); h_line_node.clear(); h_lptr.clear(); h_lslot.clear();
+    lines_ok = have_lines = false;
+    n_lines = 0;
     have_mesh = have_params = have_state = false;
   }
 };
@@ -181,6 +193,51 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   if (m->dmask)
     for (int64_t i = 0; i < 3 * N; ++i) dm[i] = m->dmask[i] ? 1 : 0;
   if (3 * N >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EINVAL, "3*n_nodes must fit in int32");
+  // ---- vertical node lines (line-block preconditioner): node n links to the node above it
+  // through every conforming z-line of an element (no slot on a hanging face or edge); the
+  // chains of links are the lines.  A node linked to two different nodes above (or below) makes
+  // the lines inconsistent and disables the preconditioner for this mesh.
+  {
+    std::vector<int32_t> up((size_t)N, -1), down((size_t)N, -1);
+    bool ok = true;
+    std::vector<int32_t> cnt((size_t)N + 1, 0);
+    for (int64_t e = 0; e < n_el && ok; ++e)
+      for (int t = 0; t < P2; ++t) {
+        if (!zline_conforming_host(m->cmask[e], P, t % P, t / P)) continue;
+        for (int z = 0; z < P; ++z) cnt[(words[e * P3 + t + P2 * z] & NODE_MASK) + 1]++;
+        for (int z = 0; z + 1 < P; ++z) {
+          const int32_t a = words[e * P3 + t + P2 * z] & NODE_MASK, b = words[e * P3 + t + P2 * (z + 1)] & NODE_MASK;
+          if ((up[a] != -1 && up[a] != b) || (down[b] != -1 && down[b] != a)) ok = false;
+          up[a] = b;
+          down[b] = a;
+        }
+      }
+    if (ok) {
+      for (int64_t n = 0; n < N; ++n) cnt[n + 1] += cnt[n];
+      ctx->h_lptr.assign(cnt.begin(), cnt.end());
+      ctx->h_lslot.resize(cnt[N]);
+      std::vector<int32_t> next(cnt.begin(), cnt.end() - 1);
+      for (int64_t e = 0; e < n_el; ++e)
+        for (int t = 0; t < P2; ++t) {
+          if (!zline_conforming_host(m->cmask[e], P, t % P, t / P)) continue;
+          for (int z = 0; z < P; ++z) {
+            const int64_t slot = e * P3 + t + P2 * z;
+            ctx->h_lslot[next[words[slot] & NODE_MASK]++] = (int32_t)slot;
+          }
+        }
+      ctx->h_line_ptr.assign(1, 0);
+      ctx->h_line_node.clear();
+      ctx->h_line_node.reserve((size_t)N);
+      for (int64_t n = 0; n < N; ++n) {
+        if (down[n] != -1) continue;
+        for (int32_t c = (int32_t)n; c != -1; c = up[c]) ctx->h_line_node.push_back(c);
+        ctx->h_line_ptr.push_back((int32_t)ctx->h_line_node.size());
+      }
+      ok = (int64_t)ctx->h_line_node.size() == N;
+    }
+    ctx->lines_ok = ok;
+    ctx->n_lines = ok ? (int64_t)ctx->h_line_ptr.size() - 1 : 0;
+  }
   // Shared z-faces inside a block: when element e and the next element of the same block name the
   // same node at (x, y, top) and (x, y, bottom), the kernel adds the upper element's bottom value
   // to the lower element's top value and stores one entry (merged[bottom slot] = 1).
@@ -355,6 +412,7 @@ int nsmf_set_params(nsmf_ctx *ctx, const nsmf_params *prm, const double *logA, c
   }
   ctx->have_params = true;
   ctx->have_state = false;
+  ctx->have_lines = false;
   return NSMF_OK;
 }
 
@@ -369,6 +427,7 @@ int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p) {
                         ctx->prm.n, ctx->prm.eps, ctx->prm.B0, ctx->st64.p, ctx->st32.p, ctx->fst64.p, ctx->fst32.p),
            "state kernel");
   ctx->have_state = true;
+  ctx->have_lines = false;
   return NSMF_OK;
 }
 
@@ -444,6 +503,52 @@ int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p) {
     NSMF_TRY(ctx, launch_recip(s, 3 * ctx->n_nodes, d_u), "reciprocal");
     NSMF_TRY(ctx, launch_recip(s, ctx->n_el * ctx->n_p, d_p), "reciprocal");
   }
+  return NSMF_OK;
+}
+
+int nsmf_line_setup(nsmf_ctx *ctx, int64_t *n_lines) {
+  if (!ctx) return NSMF_EINVAL;
+  if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "line_setup needs a state");
+  if (!ctx->lines_ok) return ctx->fail(NSMF_EUNSUP, "the mesh's vertical node lines are not consistent");
+  hipStream_t s = ctx->stream;
+  const int W = ctx->P;   // upper band entries per row: offsets 0..k
+  if (!ctx->line_ptr.p) {
+    NSMF_TRY(ctx, ctx->line_ptr.alloc(ctx->h_line_ptr.size()), "hipMalloc");
+    NSMF_TRY(ctx, ctx->line_node.alloc(ctx->h_line_node.size()), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lptr.alloc(ctx->h_lptr.size()), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lslot.alloc(ctx->h_lslot.size() ? ctx->h_lslot.size() : 1), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lbuf.alloc((size_t)3 * ctx->n_inc * W), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lfac64.alloc((size_t)3 * ctx->n_nodes * W), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lfac32.alloc((size_t)3 * ctx->n_nodes * W), "hipMalloc");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_ptr.p, ctx->h_line_ptr.data(), ctx->h_line_ptr.size() * 4,
+                                 hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_node.p, ctx->h_line_node.data(), ctx->h_line_node.size() * 4,
+                                 hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->lptr.p, ctx->h_lptr.data(), ctx->h_lptr.size() * 4, hipMemcpyHostToDevice, s),
+             "copy");
+    if (ctx->h_lslot.size())
+      NSMF_TRY(ctx, hipMemcpyAsync(ctx->lslot.p, ctx->h_lslot.data(), ctx->h_lslot.size() * 4,
+                                   hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, hipStreamSynchronize(s), "copy");   // the host vectors are not kept alive by the copy
+  }
+  NSMF_TRY(ctx,
+           launch_lines(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->beta64.p,
+                        ctx->lptr.p, ctx->lslot.p, ctx->dmask.p, ctx->line_ptr.p, ctx->line_node.p, ctx->n_lines,
+                        ctx->lbuf.p, ctx->lfac64.p, ctx->lfac32.p),
+           "line blocks");
+  ctx->have_lines = true;
+  if (n_lines) *n_lines = ctx->n_lines;
+  return NSMF_OK;
+}
+
+int nsmf_line_apply(nsmf_ctx *ctx, int prec, const void *x_u, void *y_u) {
+  if (!ctx || !x_u || !y_u) return NSMF_EINVAL;
+  if (prec != 0 && prec != 1) return ctx->fail(NSMF_EINVAL, "line_apply precision must be 0 (double) or 1 (float)");
+  if (!ctx->have_lines) return ctx->fail(NSMF_ESTATE, "line_apply needs nsmf_line_setup at the current state");
+  NSMF_TRY(ctx,
+           launch_line_apply(ctx->stream, prec, ctx->P, ctx->n_nodes, ctx->line_ptr.p, ctx->line_node.p, ctx->n_lines,
+                             prec == 0 ? (const void *)ctx->lfac64.p : (const void *)ctx->lfac32.p, x_u, y_u),
+           "line solve");
   return NSMF_OK;
 }
 

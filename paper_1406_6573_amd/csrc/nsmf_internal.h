@@ -114,6 +114,34 @@ hipError_t launch_residual(int P, int geo, int ps, hipStream_t s, const MeshView
 hipError_t launch_diag(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                        const double *st, const double *beta, double *ev, double *dp);
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
+// vertical-line block preconditioner: element line blocks, node assembly, banded Cholesky
+hipError_t launch_lines(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                        const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
+                        const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
+                        double *buf, double *fac64, float *fac32);
+hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const int32_t *line_ptr, const int32_t *line_node,
+                             int64_t n_lines, const void *fac, const void *x, void *y);
+
+// A z-line (x = i, y = j) of an element with no slot on a hanging face or edge.  cmask bits:
+// 3..8 faces -x, +x, -y, +y, -z, +z; 9 + 4 dir + s0 + 2 s1 edge parallel to axis dir with sides
+// (s0, s1) along the other two axes in increasing order.
+inline bool zline_conforming_host(uint32_t cm, int P, int i, int j) {
+  const uint32_t f = cm >> 3;
+  auto side = [P](int a) { return a == 0 ? 0 : (a == P - 1 ? 1 : -1); };
+  auto edge = [&](int dir, int a, int b) {
+    const int s0 = side(a), s1 = side(b);
+    return s0 >= 0 && s1 >= 0 && ((cm >> (9 + 4 * dir + s0 + 2 * s1)) & 1u);
+  };
+  if (((f >> 0) & 1u) && i == 0) return false;
+  if (((f >> 1) & 1u) && i == P - 1) return false;
+  if (((f >> 2) & 1u) && j == 0) return false;
+  if (((f >> 3) & 1u) && j == P - 1) return false;
+  if ((f >> 4) & 3u) return false;                        // a hanging z-normal face touches every z-line
+  if (edge(2, i, j)) return false;                        // z-parallel edge along the line
+  if (edge(0, j, 0) || edge(0, j, P - 1)) return false;   // x-parallel edges through its end slots
+  if (edge(1, i, 0) || edge(1, i, P - 1)) return false;   // y-parallel edges through its end slots
+  return true;
+}
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
                            const uint8_t *dm, const void *xm, const void *f, void *y);
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);

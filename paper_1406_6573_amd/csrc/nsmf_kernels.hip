@@ -1119,6 +1119,257 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   evec_store<T, P>(ev, m, lb, e, smem, els, t, act, y);
 }
 
+// ---------------------------------------------------------------- vertical-line blocks
+// Preconditioner data beside block Jacobi (the paper's AMG is not part of this engine): for every
+// vertical line of nodes and velocity component, the block of F restricted to the line.  Thin
+// columns couple strongly along z (element aspect ratios 16-300), which point Jacobi cannot
+// resolve; the line blocks are banded (bandwidth k) and symmetric positive definite.
+
+// Device twin of zline_conforming_host: no slot of the z-line (i, j) on a hanging face or edge.
+template <int P> __device__ __forceinline__ bool zline_conforming(uint32_t cm, int i, int j) {
+  const uint32_t f = cm >> 3;
+  if (zline_hanging<P>(cm, i, j)) return false;
+  if ((f >> 4) & 3u) return false;
+  if (edge_on<P>(cm, 0, j, 0) || edge_on<P>(cm, 0, j, P - 1)) return false;
+  if (edge_on<P>(cm, 1, i, 0) || edge_on<P>(cm, 1, i, P - 1)) return false;
+  return true;
+}
+
+// Element line blocks at the linearisation point (FP64).  For a conforming z-line (i, j) of
+// element e and component c: F_e[(i,j,za,c), (i,j,zb,c)] = sum over the element's quadrature
+// points of mu'/2 (grad phi_a . grad phi_b + d_c phi_a d_c phi_b) - kappa (Sigma0 grad phi_a)_c
+// (Sigma0 grad phi_b)_c (eq. (rank4) tested with phi_a e_c and phi_b e_c), plus the basal term on
+// za = zb = 0.  Each slot stores its row towards the slots below it: buf[(c n_inc + slot) P + d] =
+// F_e[zb, zb - d], d = 0..k (0 where zb - d < 0).  Lines with a dependent slot store nothing
+// (their couplings through hanging constraints are left out of the preconditioner).
+template <int P, int GEO>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ st,
+        const double *__restrict__ beta, double *__restrict__ buf) {
+  const Tab<double, P> &tb = *tbp;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = (int64_t)lb * E + el;
+  if (el >= E || e >= m.n_el) return;      // no barriers in this kernel
+  const int i = t % P, j = t / P;
+  if (!zline_conforming<P>(m.cmask[e], i, j)) return;
+  double rows[3][P][P];                     // rows[c][za][d] = F_e[za, za + d]
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+      for (int d = 0; d < P; ++d) rows[c][a][d] = 0;
+  double jx = 0, jy = 0, jz = 0;
+  if (GEO == GEO_AFFINE) {
+    jx = gv.el[4 * e]; jy = gv.el[4 * e + 1]; jz = gv.el[4 * e + 2];
+  } else {
+    jx = gv.el[2 * e]; jy = gv.el[2 * e + 1];
+  }
+  for (int tq = 0; tq < P2; ++tq) {
+    const int qy = tq % P, qz = tq / P, tidq = el * P2 + tq;
+    for (int qx = 0; qx < P; ++qx) {
+      const double mu = st[qp_at<P, NT, NSTATE>(lb, 0, tidq, qx)];
+      const double ka = st[qp_at<P, NT, NSTATE>(lb, 1, tidq, qx)];
+      double S[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
+      double a = 0, b = 0, cc = jz;
+      if (GEO != GEO_AFFINE) {
+        a = gv.qp[qp_at<P, NT, 4>(lb, 0, tidq, qx)];
+        b = gv.qp[qp_at<P, NT, 4>(lb, 1, tidq, qx)];
+        cc = gv.qp[qp_at<P, NT, 4>(lb, 2, tidq, qx)];
+      }
+      double G[P][3], SG[P][3];
+#pragma unroll
+      for (int z = 0; z < P; ++z) {
+        const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
+        const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
+        const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
+        if (GEO == GEO_AFFINE) {
+          G[z][0] = gr0 * jx; G[z][1] = gr1 * jy; G[z][2] = gr2 * jz;
+        } else {
+          G[z][0] = gr0 * jx + gr2 * a; G[z][1] = gr1 * jy + gr2 * b; G[z][2] = gr2 * cc;
+        }
+        SG[z][0] = S[0] * G[z][0] + S[3] * G[z][1] + S[4] * G[z][2];
+        SG[z][1] = S[3] * G[z][0] + S[1] * G[z][1] + S[5] * G[z][2];
+        SG[z][2] = S[4] * G[z][0] + S[5] * G[z][1] + S[2] * G[z][2];
+      }
+#pragma unroll
+      for (int za = 0; za < P; ++za)
+#pragma unroll
+        for (int d = 0; d < P; ++d) {
+          if (za + d >= P) continue;
+          const int zb = za + d;
+          const double g = G[za][0] * G[zb][0] + G[za][1] * G[zb][1] + G[za][2] * G[zb][2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rows[c][za][d] += 0.5 * mu * (g + G[za][c] * G[zb][c]) - ka * SG[za][c] * SG[zb][c];
+        }
+    }
+  }
+  const int fid = m.bface_of[e];
+  if (fid >= 0) {
+    const double *fg = gv.face + (size_t)fid * NFACEGEO * P2;
+    for (int fq = 0; fq < P2; ++fq) {
+      const double phi = tb.B[fq % P][i] * tb.B[fq / P][j];
+      const double bw = beta[fid] * fg[fq] * phi * phi;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double nc = fg[(1 + c) * P2 + fq];
+        rows[c][0][0] += bw * (1.0 - nc * nc);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int zb = 0; zb < P; ++zb)
+#pragma unroll
+      for (int d = 0; d < P; ++d)
+        buf[((size_t)c * m.n_inc + e * P3 + t + P2 * zb) * P + d] = zb >= d ? rows[c][zb - d][d] : 0.0;
+}
+
+// Node rows of the line blocks: A[(c N + n) W + d] = sum of the rows of the node's conforming slots
+// (fixed order, deterministic); entry d couples n with the node d places below it on its line.
+__global__ void k_line_band(int64_t N, int64_t n_inc, int W, const int32_t *__restrict__ lptr,
+                            const int32_t *__restrict__ lslot, const double *__restrict__ buf, double *__restrict__ A) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int32_t k0 = lptr[n], k1 = lptr[n + 1];
+  for (int c = 0; c < 3; ++c)
+    for (int d = 0; d < W; ++d) {
+      double s = 0.0;
+      for (int32_t k = k0; k < k1; ++k) s += buf[((size_t)c * n_inc + lslot[k]) * W + d];
+      A[((size_t)c * N + n) * W + d] = s;
+    }
+}
+
+// Banded Cholesky of each line block, one thread per (line, component), in place: row i of the
+// line holds A[i][i - d] on entry and the factor entry G[i][i - d] on exit (A = G G^T).  Rows of
+// Dirichlet-flagged components are unit rows, and couplings with them are dropped (the blocks of
+// J_c = P K P + (I - P)).  A non-positive pivot (not expected: the blocks are principal
+// submatrices of an SPD matrix) falls back to a diagonal row.
+template <int W>
+__global__ void k_line_factor(int64_t N, int64_t n_lines, const int32_t *__restrict__ line_ptr,
+                              const int32_t *__restrict__ line_node, const uint8_t *__restrict__ dm,
+                              double *__restrict__ F, float *__restrict__ F32) {
+  constexpr int K = W - 1;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 3 * n_lines) return;
+  const int c = (int)(g / n_lines);
+  const int64_t l = g % n_lines;
+  const int32_t b0 = line_ptr[l], len = line_ptr[l + 1] - b0;
+  double prev[K + 1][W];   // prev[r] = factor row of line row i - r (r = 1..K)
+  bool pmask[K + 1];
+#pragma unroll
+  for (int r = 0; r <= K; ++r) {
+    pmask[r] = true;
+#pragma unroll
+    for (int d = 0; d < W; ++d) prev[r][d] = 0.0;
+  }
+  for (int32_t i = 0; i < len; ++i) {
+    const int32_t n = line_node[b0 + i];
+    const bool mi = dm[(size_t)c * N + n] != 0;
+    double *row = F + ((size_t)c * N + n) * W;
+    double a[W], gi[W];
+#pragma unroll
+    for (int d = 0; d < W; ++d) {
+      const bool keep = d == 0 ? !mi : (!mi && i - d >= 0 && !pmask[d]);
+      a[d] = keep ? row[d] : (d == 0 ? 1.0 : 0.0);
+      gi[d] = 0.0;
+    }
+    // G[i][i-d] for d = K..1, then the pivot
+#pragma unroll
+    for (int d = K; d >= 1; --d) {
+      if (i - d < 0) continue;
+      double s = a[d];
+#pragma unroll
+      for (int t2 = 1; t2 + d <= K; ++t2) s -= gi[d + t2] * prev[d][t2];
+      gi[d] = s / prev[d][0];
+    }
+    double s = a[0];
+#pragma unroll
+    for (int d = 1; d < W; ++d) s -= gi[d] * gi[d];
+    if (!(s > 0.0)) {
+#pragma unroll
+      for (int d = 1; d < W; ++d) gi[d] = 0.0;
+      s = a[0] != 0.0 ? (a[0] > 0 ? a[0] : -a[0]) : 1.0;
+    }
+    gi[0] = sqrt(s);
+#pragma unroll
+    for (int d = 0; d < W; ++d) {
+      row[d] = gi[d];
+      F32[((size_t)c * N + n) * W + d] = (float)gi[d];
+    }
+#pragma unroll
+    for (int r = K; r >= 2; --r) {
+      pmask[r] = pmask[r - 1];
+#pragma unroll
+      for (int d = 0; d < W; ++d) prev[r][d] = prev[r - 1][d];
+    }
+    pmask[1] = mi;
+#pragma unroll
+    for (int d = 0; d < W; ++d) prev[1][d] = gi[d];
+  }
+}
+
+// y = (line blocks)^{-1} x per component: forward G v = x, backward G^T y = v along each line.
+template <typename T, int W>
+__global__ void k_line_apply(int64_t N, int64_t n_lines, const int32_t *__restrict__ line_ptr,
+                             const int32_t *__restrict__ line_node, const T *__restrict__ F, const T *__restrict__ x,
+                             T *__restrict__ y) {
+  constexpr int K = W - 1;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 3 * n_lines) return;
+  const int c = (int)(g / n_lines);
+  const int64_t l = g % n_lines;
+  const int32_t b0 = line_ptr[l], len = line_ptr[l + 1] - b0;
+  T v[K + 1];
+#pragma unroll
+  for (int r = 0; r <= K; ++r) v[r] = 0;
+  for (int32_t i = 0; i < len; ++i) {
+    const int32_t n = line_node[b0 + i];
+    const T *row = F + ((size_t)c * N + n) * W;
+    T s = x[(size_t)c * N + n];
+#pragma unroll
+    for (int d = 1; d < W; ++d)
+      if (i - d >= 0) s -= row[d] * v[d];
+    s /= row[0];
+    y[(size_t)c * N + n] = s;
+#pragma unroll
+    for (int r = K; r >= 2; --r) v[r] = v[r - 1];
+    v[1] = s;
+  }
+  // backward: z_i = (v_i - sum_d G[i+d][i] z_{i+d}) / G[i][i]
+  T zr[K + 1], gr[K + 1][W];
+#pragma unroll
+  for (int r = 0; r <= K; ++r) {
+    zr[r] = 0;
+#pragma unroll
+    for (int d = 0; d < W; ++d) gr[r][d] = 0;
+  }
+  for (int32_t i = len - 1; i >= 0; --i) {
+    const int32_t n = line_node[b0 + i];
+    const T *row = F + ((size_t)c * N + n) * W;
+    T s = y[(size_t)c * N + n];
+#pragma unroll
+    for (int d = 1; d < W; ++d)
+      if (i + d < len) s -= gr[d][d] * zr[d];
+    const T z = s / row[0];
+    y[(size_t)c * N + n] = z;
+#pragma unroll
+    for (int r = K; r >= 2; --r) {
+      zr[r] = zr[r - 1];
+#pragma unroll
+      for (int d = 0; d < W; ++d) gr[r][d] = gr[r - 1][d];
+    }
+    zr[1] = z;
+#pragma unroll
+    for (int d = 0; d < W; ++d) gr[1][d] = row[d];
+  }
+}
+
 // Geometry at upload (FP64).  mode 0: classify (flags bit0 not column-mapped, bit1 not
 // affine, bit2 det J <= 0 or not finite, bit3 degenerate basal face).  mode 1: store
 // affine data.  mode 2: store column data.  Face data are stored in modes 1 and 2.
@@ -1451,6 +1702,53 @@ hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t 
   NSMF_AP2(float, 5)
 #undef NSMF_AP2
 #undef NSMF_AP
+  return hipErrorInvalidValue;
+}
+
+
+template <int P, int GEO>
+static hipError_t lines_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                           const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
+                           const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
+                           double *buf, double *fac64, float *fac32) {
+  hipLaunchKernelGGL((k_lines<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
+                     &((const TabSet<P> *)tabs)->d, st, beta, buf);
+  hipLaunchKernelGGL(k_line_band, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, P, lptr, lslot,
+                     (const double *)buf, fac64);
+  if (n_lines > 0)
+    hipLaunchKernelGGL(k_line_factor<P>, dim3(grid1(3 * n_lines, 256)), dim3(256), 0, s, m.n_nodes, n_lines, line_ptr,
+                       line_node, dm, fac64, fac32);
+  return hipGetLastError();
+}
+hipError_t launch_lines(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                        const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
+                        const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
+                        double *buf, double *fac64, float *fac32) {
+#define NSMF_LN(PP, GG)                                                                                        \
+  if (P == PP && geo == GG)                                                                                    \
+    return lines_pg<PP, GG>(s, m, g, tabs, st, beta, lptr, lslot, dm, line_ptr, line_node, n_lines, buf, fac64, \
+                            fac32);
+  NSMF_LN(3, GEO_AFFINE) NSMF_LN(3, GEO_COLUMN) NSMF_LN(4, GEO_AFFINE) NSMF_LN(4, GEO_COLUMN)
+  NSMF_LN(5, GEO_AFFINE) NSMF_LN(5, GEO_COLUMN)
+#undef NSMF_LN
+  return hipErrorInvalidValue;
+}
+hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const int32_t *line_ptr, const int32_t *line_node,
+                             int64_t n_lines, const void *fac, const void *x, void *y) {
+  if (n_lines <= 0) return hipSuccess;
+  const dim3 grid(grid1(3 * n_lines, 256)), blk(256);
+#define NSMF_LA(WW)                                                                                             \
+  if (P == WW) {                                                                                                \
+    if (prec == 0)                                                                                              \
+      hipLaunchKernelGGL((k_line_apply<double, WW>), grid, blk, 0, s, N, n_lines, line_ptr, line_node,          \
+                         (const double *)fac, (const double *)x, (double *)y);                                  \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_line_apply<float, WW>), grid, blk, 0, s, N, n_lines, line_ptr, line_node,           \
+                         (const float *)fac, (const float *)x, (float *)y);                                     \
+    return hipGetLastError();                                                                                   \
+  }
+  NSMF_LA(3) NSMF_LA(4) NSMF_LA(5)
+#undef NSMF_LA
   return hipErrorInvalidValue;
 }
 

@@ -26,7 +26,7 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_set_state", "nsmf_residual", "nsmf_jacobian_apply", "nsmf_residual_vjp", "nsmf_query",
             "nsmf_geometry_kind", "nsmf_set_kernel_timing", "nsmf_kernel_time", "nsmf_last_error",
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
-            "nsmf_vec_convert"]
+            "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply"]
 
 
 class NsmfError(RuntimeError):
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_version.restype = ctypes.c_char_p
     i64, dbl, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_int
     lib.nsmf_jacobi_diag.argtypes = [vp, ci, vp, vp]
+    lib.nsmf_line_setup.argtypes = [vp, i64p]
+    lib.nsmf_line_apply.argtypes = [vp, ci, vp, vp]
     lib.nsmf_vec_dots.argtypes = [vp, ci, i64, ci, vp, i64, vp, vp]
     lib.nsmf_vec_gemv.argtypes = [vp, ci, i64, ci, vp, i64, vp, dbl, vp]
     lib.nsmf_vec_axpby.argtypes = [vp, ci, i64, dbl, vp, dbl, vp]
@@ -233,6 +235,20 @@ class Engine:
         d_u, d_p = out
         self._check(self.lib.nsmf_jacobi_diag(self.h, 1 if invert else 0, _ptr(d_u), _ptr(d_p)))
         return d_u, d_p
+
+    def line_setup(self):
+        """Factor the vertical-line blocks of the velocity block at the state; returns the number of lines."""
+        n = ctypes.c_int64(0)
+        self._check(self.lib.nsmf_line_setup(self.h, ctypes.byref(n)))
+        return int(n.value)
+
+    def line_apply(self, x_u, out=None):
+        """y_u = (line blocks)^{-1} x_u for x_u [3, n_nodes] (float64 or float32, contiguous)."""
+        sz = self.sizes
+        x_u = self._vec(x_u, (3, sz["n_nodes"]), x_u.dtype, "x_u")
+        y_u = self.torch.empty_like(x_u) if out is None else out
+        self._check(self.lib.nsmf_line_apply(self.h, self._prec_of(x_u), _ptr(x_u), _ptr(y_u)))
+        return y_u
 
     # Krylov vector kernels: 1D device tensors (float64 or float32), FP64 accumulation
     @staticmethod

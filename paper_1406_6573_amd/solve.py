@@ -1,9 +1,12 @@
 """Newton-Krylov driver on the engine (Sec. 4.1-4.2 of the paper).
 
 Each Newton step linearises at (u, p), evaluates the FP64 residual, builds the
-block-Jacobi preconditioner (diagonal of F, lumped -M(1/mu) for the Schur block)
-and solves J_c d = -r with right-preconditioned FGMRES(m) using classical
-Gram-Schmidt with a second pass.  A backtracking line search on ||r|| accepts
+block-diagonal preconditioner (an approximation of F, lumped -M(1/mu) for the
+Schur block) and solves J_c d = -r with right-preconditioned FGMRES(m) using
+classical Gram-Schmidt with a second pass.  The velocity block is approximated
+either by its diagonal ("jacobi") or by its vertical-line blocks ("line"):
+banded Cholesky factors of F restricted to each column of nodes, which resolve
+the strong vertical coupling of thin columns.  A backtracking line search on ||r|| accepts
 the step.  Every vector operation runs in the engine's kernels (multi-dots with
 FP64 accumulation, basis combinations, scaling); the host holds only the small
 Hessenberg least-squares problem.
@@ -14,9 +17,10 @@ Precision modes:
   accumulated in FP64, FP64 right-hand side and FP64 outer refinement of the
   correction (d += FGMRES_32(b - J_64 d) for ``refine`` cycles).
 
-The preconditioner is a plain fallback (the paper's AMG is not part of this
-engine); block Jacobi is not h-robust, so convergence per Krylov iteration
-degrades with mesh size and aspect ratio.
+The preconditioners are plain fallbacks (the paper's AMG is not part of this
+engine): neither is h-robust in the horizontal directions, so convergence per
+Krylov iteration degrades with mesh size; point Jacobi also degrades with the
+aspect ratio.
 """
 from __future__ import annotations
 
@@ -38,10 +42,13 @@ class SolveStats:
 
 
 class NewtonKrylov:
-    def __init__(self, engine, restart: int = 50, precision: str = "fp64", refine: int = 1):
+    def __init__(self, engine, restart: int = 50, precision: str = "fp64", refine: int = 1,
+                 precond: str = "jacobi"):
         if restart + 1 > 64:
             raise ValueError("restart must be at most 63")
-        self.eng, self.m, self.precision, self.refine = engine, restart, precision, refine
+        if precond not in ("jacobi", "line"):
+            raise ValueError("precond must be 'jacobi' or 'line'")
+        self.eng, self.m, self.precision, self.refine, self.precond = engine, restart, precision, refine, precond
         sz = engine.sizes
         self.N, self.n_el, self.n_p = sz["n_nodes"], sz["n_el"], sz["n_p"]
         self.n = 3 * self.N + self.n_el * self.n_p
@@ -66,6 +73,22 @@ class NewtonKrylov:
         prec = "fp64" if x.dtype == torch.float64 else "fp32"
         self.eng.jacobian_apply(*self.split(x), prec, out=self.split(y))
 
+    def precondition(self, v, z):
+        """z = M^-1 v (vectors of the Krylov precision)."""
+        if self.precond == "jacobi":
+            self.eng.vec_mul(self.minv, v, z)
+            return
+        vu, vp = self.split(v)
+        zu, zp = self.split(z)
+        self.eng.line_apply(vu, out=zu)
+        self.eng.vec_mul(self.minv[3 * self.N:], vp.reshape(-1), zp.reshape(-1))
+
+    def setup_preconditioner(self):
+        mu, mp = self.split(self.minv)
+        self.eng.jacobi_diag(invert=True, out=(mu, mp))
+        if self.precond == "line":
+            self.eng.line_setup()
+
     def norm(self, x):
         self.eng.vec_dots(x.view(1, -1), 1, x, self.h)
         return math.sqrt(max(float(self.h[0]), 0.0))
@@ -89,7 +112,7 @@ class NewtonKrylov:
         g[0] = beta
         k = 0
         for j in range(m):
-            eng.vec_mul(self.minv, V[j], Z[j])             # z_j = M^-1 v_j
+            self.precondition(V[j], Z[j])                  # z_j = M^-1 v_j
             wj = V[j + 1]
             self.apply(Z[j], wj)
             hcol = np.zeros(j + 2)
@@ -164,8 +187,7 @@ class NewtonKrylov:
         rn = self.norm(r)
         st.newton_residuals.append(rn)
         for it in range(n_newton):
-            mu, mp = self.split(self.minv)
-            eng.jacobi_diag(invert=True, out=(mu, mp))
+            self.setup_preconditioner()
             eng.vec_axpby(0.0, r, -1.0, r)                  # rhs = -r
             its, red = self.linear_solve(r, lin_tol)
             st.krylov_iterations.append(its)
