@@ -724,14 +724,15 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   double *redl = red + els * P2;
   const int64_t N = m.n_nodes;
   // connectivity first (the gather of x waits on it), then the linearisation data of the thread's
-  // P points: in FP32 requested here so that its latency overlaps the gather and the forward
-  // sweeps (in FP64 the extra live registers would cost occupancy, so it is loaded just before
-  // the quadrature-point step).  The block's slice is always allocated, also for threads
+  // P points: requested here so that its latency overlaps the gather and the forward sweeps,
+  // except in FP64 with P = 3, 5, where the extra live registers would cost occupancy (it is
+  // loaded just before the quadrature-point step there; P = 4 stays within 256 VGPRs, two
+  // wavefronts per SIMD either way).  The block's slice is always allocated, also for threads
   // without an element.
   uint32_t nw[P];
   load_words<P>(m.en + e * P3, t, act, nw);
   const uint32_t cm = act ? m.cmask[e] : 0u;
-  constexpr bool kEarlyState = sizeof(T) == 4;
+  constexpr bool kEarlyState = sizeof(T) == 4 || P == 4;
   T stv[NSTATE][P];
   if constexpr (kEarlyState) {
 #pragma unroll
