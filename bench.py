@@ -28,16 +28,17 @@ METRIC = "GDoF/s of Newton-Stokes Jacobian apply, mixed vs FP64 at stated rel. e
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(sz, geo_kind, word):
-    """Bytes one Jacobian apply must move with stored linearisation data:
-    8 values per quadrature point (mu', kappa, Sigma0), x read and y written once, per-element
-    geometry (affine) or per-point geometry (column-mapped), basal face data and beta."""
+def algorithmic_bytes(sz, geo_kind, word, nstate):
+    """Bytes one Jacobian apply must move with stored linearisation data: nstate values per
+    quadrature point (FP64: mu', kappa, Sigma0 = 8; FP32: mu', sqrt(kappa) Sigma0 = 7), x read and
+    y written once, per-element geometry (affine) or per-point geometry (column-mapped), basal face
+    data and beta."""
     k = sz["k"]
     nq = sz["n_el"] * (k + 1) ** 3
     nvec = 3 * sz["n_nodes"] + sz["n_el"] * sz["n_p"]
     geo = 4 * sz["n_el"] if geo_kind == "affine" else 2 * sz["n_el"] + 4 * nq
     face = sz["n_bface"] * (1 + 4 * (k + 1) ** 2)
-    return word * (8 * nq + 2 * nvec + geo + face)
+    return word * (nstate * nq + 2 * nvec + geo + face)
 
 
 def measured_traffic(config_id):
@@ -213,8 +214,8 @@ def main():
         errs[prec] = float((got - ref).norm() / ref.norm())
     n_dof = sz["n_dof"]
     gdofs = {k: n_dof / (v["ms"] * 1e-3) / 1e9 for k, v in out.items()}
-    b32 = algorithmic_bytes(sz, geo, 4)
-    b64 = algorithmic_bytes(sz, geo, 8)
+    b32 = algorithmic_bytes(sz, geo, 4, 7)
+    b64 = algorithmic_bytes(sz, geo, 8, 8)
     ach32 = b32 / (out["fp32"]["kernel_ms"] * 1e-3) / 1e9
     ach64 = b64 / (out["fp64"]["kernel_ms"] * 1e-3) / 1e9
     pair = f"Q{m.k}xP{m.k - 1}" if args.pspace == "P" else f"Q{m.k}xQ{m.k - 2}"

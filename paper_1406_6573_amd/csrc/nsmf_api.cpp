@@ -376,10 +376,12 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry");
   X.free();
 
-  NSMF_TRY(ctx, ctx->st64.alloc(8 * nqp), "hipMalloc");
-  NSMF_TRY(ctx, ctx->st32.alloc(8 * nqp), "hipMalloc");
-  NSMF_TRY(ctx, launch_fill(s, ctx->st64.p, 16 * nqp), "fill");
-  NSMF_TRY(ctx, launch_fill(s, ctx->st32.p, 8 * nqp), "fill");
+  // per-point state: FP64 mu', kappa, Sigma0 (8 values); FP32 mu', sqrt(kappa) Sigma0 (7 values)
+  constexpr size_t NS64 = 8, NS32 = 7;
+  NSMF_TRY(ctx, ctx->st64.alloc(NS64 * nqp), "hipMalloc");
+  NSMF_TRY(ctx, ctx->st32.alloc(NS32 * nqp), "hipMalloc");
+  NSMF_TRY(ctx, launch_fill(s, ctx->st64.p, 2 * NS64 * nqp), "fill");   // sizes in 32-bit words
+  NSMF_TRY(ctx, launch_fill(s, ctx->st32.p, NS32 * nqp), "fill");
   NSMF_TRY(ctx, ctx->fst64.alloc((size_t)NB * 3 * P2), "hipMalloc");
   NSMF_TRY(ctx, ctx->fst32.alloc((size_t)NB * 3 * P2), "hipMalloc");
   NSMF_TRY(ctx, ctx->u.alloc(3 * N), "hipMalloc");
@@ -461,7 +463,8 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
   GeoView<double> g64 = ctx->geo64();
   GeoView<float> g32 = ctx->geo32();
   const void *gv = prec == 0 ? (const void *)&g64 : (const void *)&g32;
-  const void *st = prec == 0 ? (const void *)ctx->st64.p : (const void *)ctx->st32.p;
+  // the FP32 apply reads the 7-value FP32 state; FP64 and every VJP the 8-value FP64 state
+  const void *st = (prec == 0 || vjp) ? (const void *)ctx->st64.p : (const void *)ctx->st32.p;
   const void *fst = prec == 0 ? (const void *)ctx->fst64.p : (const void *)ctx->fst32.p;
   const void *beta = prec == 0 ? (const void *)ctx->beta64.p : (const void *)ctx->beta32.p;
   NSMF_TRY(ctx,

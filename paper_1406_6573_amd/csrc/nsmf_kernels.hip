@@ -18,11 +18,16 @@
 // its P points with one wide load and a wavefront's load is one contiguous access.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "nsmf_internal.h"
 
 namespace nsmf {
 
 constexpr int NSTATE = 8;   // mu', kappa, Sigma_xx, Sigma_yy, Sigma_zz, Sigma_xy, Sigma_xz, Sigma_yz
+// FP32 apply: mu' and Sigma_hat = sqrt(kappa) Sigma0 (kappa >= 0 for n >= 1), so that the Newton term
+// kappa (Sigma0 : D) Sigma0 = (Sigma_hat : D) Sigma_hat takes one value less per point
+constexpr int NSTATE32 = 7;
 constexpr int NFACEGEO = 4; // w|S|, n_x, n_y, n_z
 constexpr int NFACEST = 3;  // w|S| T u
 
@@ -707,7 +712,7 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
 // Jacobian apply (and VJP): y = J_c x at the stored linearisation point.
 template <typename T, int P, int GEO, bool VJP, int PS>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *__restrict__ st, const T *__restrict__ fst,
+k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void *__restrict__ st_, const T *__restrict__ fst,
         const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
         T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
   const Tab<T, P> &tb = *tbp;
@@ -732,11 +737,17 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   uint32_t nw[P];
   load_words<P>(m.en + e * P3, t, act, nw);
   const uint32_t cm = act ? m.cmask[e] : 0u;
-  constexpr bool kEarlyState = sizeof(T) == 4 || P == 4;
-  T stv[NSTATE][P];
+  // FP32 apply: the 7-value FP32 state; FP64 and the VJP (which needs Sigma0 : D itself for the
+  // logA gradient): the 8-value FP64 state
+  constexpr bool kS32 = sizeof(T) == 4 && !VJP;
+  using ST = std::conditional_t<kS32, float, double>;
+  constexpr int NF = kS32 ? NSTATE32 : NSTATE;
+  const ST *__restrict__ st = reinterpret_cast<const ST *>(st_);
+  constexpr bool kEarlyState = sizeof(ST) == 4 || P == 4;
+  ST stv[NF][P];
   if constexpr (kEarlyState) {
 #pragma unroll
-    for (int f = 0; f < NSTATE; ++f) load_field<T, P, NT, NSTATE>(st, lb, f, tid, stv[f]);
+    for (int f = 0; f < NF; ++f) load_field<ST, P, NT, NF>(st, lb, f, tid, stv[f]);
   }
   T v[3][P];
   gather_words<T, P>(nw, xu, N, act, true, v);
@@ -763,7 +774,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
   double gA = 0.0;
   if constexpr (!kEarlyState) {
 #pragma unroll
-    for (int f = 0; f < NSTATE; ++f) load_field<T, P, NT, NSTATE>(st, lb, f, tid, stv[f]);
+    for (int f = 0; f < NF; ++f) load_field<ST, P, NT, NF>(st, lb, f, tid, stv[f]);
   }
 #pragma unroll
   for (int i = 0; i < P; ++i) {
@@ -774,9 +785,10 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
 #pragma unroll
       for (int r = 0; r < 3; ++r) grr[c][r] = gr[c][r][i];
     to_phys<T, P, GEO>(g, i, grr, G);
-    const T mu = stv[0][i], ka = stv[1][i];
-    const T sxx = stv[2][i], syy = stv[3][i], szz = stv[4][i];
-    const T sxy = stv[5][i], sxz = stv[6][i], syz = stv[7][i];
+    constexpr int S0 = kS32 ? 1 : 2;   // first Sigma field
+    const T mu = (T)stv[0][i], ka = kS32 ? T(1) : (T)stv[kS32 ? 0 : 1][i];
+    const T sxx = (T)stv[S0][i], syy = (T)stv[S0 + 1][i], szz = (T)stv[S0 + 2][i];
+    const T sxy = (T)stv[S0 + 3][i], sxz = (T)stv[S0 + 4][i], syz = (T)stv[S0 + 5][i];
     // D = sym(G): off-diagonal entries kept doubled (exy = 2 Dxy) so that Sigma0 : D takes no
     // extra factors; tau = mu' D - kappa (Sigma0 : D) Sigma0 - p w detJ I
     const T dxx = G[0][0], dyy = G[1][1], dzz = G[2][2];
@@ -788,7 +800,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *_
     s += sxz * exz;
     s += syz * eyz;
     if (VJP) gA += (double)s;
-    const T ks = ka * s, muh = T(0.5) * mu;
+    const T ks = kS32 ? s : ka * s, muh = T(0.5) * mu;
     const T pw = pq[i] * g.wd[i];
     tau[0][0] = mu * dxx - (ks * sxx + pw);
     tau[1][1] = mu * dyy - (ks * syy + pw);
@@ -902,10 +914,11 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
       const T ka = cf / ((II + eps) * mup);
       const T vals[NSTATE] = {mup, ka, mup * dxx, mup * dyy, mup * dzz, mup * dxy, mup * dxz, mup * dyz};
 #pragma unroll
-      for (int f = 0; f < NSTATE; ++f) {
-        s64[qp_at<P, NT, NSTATE>(lb, f, tid, i)] = vals[f];
-        s32[qp_at<P, NT, NSTATE>(lb, f, tid, i)] = (float)vals[f];
-      }
+      for (int f = 0; f < NSTATE; ++f) s64[qp_at<P, NT, NSTATE>(lb, f, tid, i)] = vals[f];
+      const T sk = sqrt(ka);
+      s32[qp_at<P, NT, NSTATE32>(lb, 0, tid, i)] = (float)mup;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) s32[qp_at<P, NT, NSTATE32>(lb, 1 + f, tid, i)] = (float)(sk * vals[2 + f]);
     }
   }
   const int fid = act ? m.bface_of[e] : -1;
@@ -1683,7 +1696,7 @@ static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, c
   if constexpr (sizeof(T) == 8) tb = &ts->d;
   else tb = bf16 ? &ts->fb : &ts->f;
   hipLaunchKernelGGL((k_apply<T, P, GEO, VJP, PS>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m,
-                     *(const GeoView<T> *)gview, tb, (const T *)st, (const T *)fst, (const T *)beta, (const T *)xu,
+                     *(const GeoView<T> *)gview, tb, st, (const T *)fst, (const T *)beta, (const T *)xu,
                      (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
   return hipGetLastError();
 }
