@@ -41,12 +41,17 @@ def algorithmic_bytes(sz, geo_kind, word, nstate):
     return word * (nstate * nq + 2 * nvec + geo + face)
 
 
+TRAFFIC_FILES = {2: "apply_slab64x64x8_q3_traffic.json", 3: "apply_terrain128x128x16_q4_traffic.json"}
+
+
 def measured_traffic(config_id):
-    """HBM bytes per apply from the committed counter summary, if it was taken with the current
-    kernel sources (otherwise None)."""
+    """HBM bytes per FP32 apply from the committed counter summary of the workload, if it was taken
+    with the current kernel sources (otherwise None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "apply_slab64x64x8_q3_traffic.json")
-    if config_id != 2 or not os.path.exists(path):
+    if config_id not in TRAFFIC_FILES:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[config_id])
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
