@@ -6,7 +6,11 @@ Schur block) and solves J_c d = -r with right-preconditioned FGMRES(m) using
 classical Gram-Schmidt with a second pass.  The velocity block is approximated
 either by its diagonal ("jacobi") or by its vertical-line blocks ("line"):
 banded Cholesky factors of F restricted to each column of nodes, which resolve
-the strong vertical coupling of thin columns.  A backtracking line search on ||r|| accepts
+the strong vertical coupling of thin columns.  With triangular=True the
+preconditioner is the block upper-triangular [[F~, B^T], [0, S~]] of Sec. 4.2
+instead of the block-diagonal one: z_p = S~^-1 v_p, z_u = F~^-1 (v_u - B^T z_p),
+with B^T z_p from the engine's Jacobian apply at zero velocity (one more apply
+per iteration, fewer iterations).  A backtracking line search on ||r|| accepts
 the step.  Every vector operation runs in the engine's kernels (multi-dots with
 FP64 accumulation, basis combinations, scaling); the host holds only the small
 Hessenberg least-squares problem.
@@ -43,12 +47,13 @@ class SolveStats:
 
 class NewtonKrylov:
     def __init__(self, engine, restart: int = 50, precision: str = "fp64", refine: int = 1,
-                 precond: str = "jacobi"):
+                 precond: str = "jacobi", triangular: bool = False):
         if restart + 1 > 64:
             raise ValueError("restart must be at most 63")
         if precond not in ("jacobi", "line"):
             raise ValueError("precond must be 'jacobi' or 'line'")
         self.eng, self.m, self.precision, self.refine, self.precond = engine, restart, precision, refine, precond
+        self.triangular = triangular
         sz = engine.sizes
         self.N, self.n_el, self.n_p = sz["n_nodes"], sz["n_el"], sz["n_p"]
         self.n = 3 * self.N + self.n_el * self.n_p
@@ -63,6 +68,9 @@ class NewtonKrylov:
         self.r64 = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.d64 = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.tmp = torch.empty(self.n, dtype=kt, device=dev)
+        if triangular:
+            self.zero_u = torch.zeros((3, self.N), dtype=kt, device=dev)
+            self.bt = torch.empty(self.n, dtype=kt, device=dev)
 
     # ------------------------------------------------------------ views
     def split(self, x):
@@ -75,13 +83,24 @@ class NewtonKrylov:
 
     def precondition(self, v, z):
         """z = M^-1 v (vectors of the Krylov precision)."""
-        if self.precond == "jacobi":
-            self.eng.vec_mul(self.minv, v, z)
+        eng = self.eng
+        if self.precond == "jacobi" and not self.triangular:
+            eng.vec_mul(self.minv, v, z)
             return
         vu, vp = self.split(v)
         zu, zp = self.split(z)
-        self.eng.line_apply(vu, out=zu)
-        self.eng.vec_mul(self.minv[3 * self.N:], vp.reshape(-1), zp.reshape(-1))
+        eng.vec_mul(self.minv[3 * self.N:], vp.reshape(-1), zp.reshape(-1))      # z_p = S~^-1 v_p
+        ru = vu
+        if self.triangular:                                                       # v_u - B^T z_p
+            bu, bp = self.split(self.bt)
+            prec = "fp64" if v.dtype == torch.float64 else "fp32"
+            eng.jacobian_apply(self.zero_u, zp, prec, out=(bu, bp))
+            eng.vec_axpby(1.0, vu.reshape(-1), -1.0, bu.reshape(-1))
+            ru = bu
+        if self.precond == "line":
+            eng.line_apply(ru, out=zu)
+        else:
+            eng.vec_mul(self.minv[:3 * self.N], ru.reshape(-1), zu.reshape(-1))
 
     def setup_preconditioner(self):
         mu, mp = self.split(self.minv)
