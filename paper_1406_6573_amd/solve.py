@@ -234,3 +234,26 @@ class NewtonKrylov:
         torch.cuda.synchronize()
         st.seconds = time.perf_counter() - t0
         return st
+
+
+def adjoint_gradient(nk: NewtonKrylov, u, p, dphi_u, dphi_p=None, tol: float = 1e-12):
+    """Gradient of a functional Phi(u(theta), p(theta)) of the solved state with respect to the
+    per-element log rate factors and the per-face basal friction, theta = (logA, beta)
+    (the inverse-problem use of the adjoint, Sec. 2.3):
+
+        J_c^T lambda = (dPhi/du, dPhi/dp),   dPhi/dtheta = -(dr/dtheta)^T lambda,
+
+    with J_c symmetric (the same FGMRES solve as a Newton step) and (dr/dtheta)^T lambda from the
+    residual VJP.  (u, p) must solve r(u, p) = 0; dphi_u [3, n_nodes] and dphi_p [n_el, n_p] are
+    FP64 device tensors.  Returns (dPhi/dlogA [n_el], dPhi/dbeta [n_bface], Krylov iterations,
+    relative residual of the adjoint solve)."""
+    eng = nk.eng
+    eng.set_state(u.contiguous(), p.contiguous())
+    nk.setup_preconditioner()
+    if dphi_p is None:
+        dphi_p = torch.zeros((nk.n_el, nk.n_p), dtype=torch.float64, device=u.device)
+    rhs = torch.cat([dphi_u.reshape(-1), dphi_p.reshape(-1)]).contiguous()
+    its, red = nk.linear_solve(rhs, tol)
+    lu, lp = nk.split(nk.d64)
+    _, _, g_logA, g_beta = eng.residual_vjp(lu.contiguous(), lp.contiguous(), "fp64")
+    return -g_logA, -g_beta, its, red

@@ -285,3 +285,44 @@ def test_upper_triangular_preconditioner(torch_cuda, precision):
         red[tri] = true
         eng.close()
     assert red[True] < 0.5 * red[False]
+
+
+def test_adjoint_gradient_matches_finite_differences(torch_cuda):
+    """Phi(u) = 1/2 |u - u_obs|^2 at the solved state: the adjoint gradient with respect to logA and beta
+    equals central differences (h = 1e-6) of Phi at re-solved states."""
+    torch = torch_cuda
+    from paper_1406_6573_amd import Engine
+    from paper_1406_6573_amd.solve import NewtonKrylov, adjoint_gradient
+    case = small_case(2, mapped=True, nx=2, ny=2, nz=1, frac=0.5, L=20.0, body=(0.0, 0.0, -1.0))
+    m = case["mesh"]
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    eng = Engine()
+    eng.upload_mesh(m)
+    nk = NewtonKrylov(eng, restart=60, precision="fp64", precond="line", triangular=True)
+    rng = np.random.default_rng(9)
+    u_obs = t(rng.uniform(-1, 1, (3, m.n_nodes)))
+
+    def solve_state(logA, beta, u0, p0):
+        eng.set_params(case["n"], case["eps"], case["B0"], case["body"], t(logA), t(beta))
+        u, p = u0.clone(), p0.clone()
+        st = nk.solve(u, p, n_newton=12, lin_tol=1e-13)
+        assert st.newton_residuals[-1] < 1e-10 * st.newton_residuals[0] + 1e-12
+        return u, p
+
+    phi = lambda u: 0.5 * float(((u - u_obs) ** 2).sum())
+    u, p = solve_state(case["logA"], case["beta"], t(case["u"]), t(case["p"]))
+    gA, gB, its, red = adjoint_gradient(nk, u, p, u - u_obs)
+    assert red < 1e-9
+    h = 1e-6
+    for kind, idx in (("logA", 0), ("logA", m.n_el - 1), ("beta", 0), ("beta", m.n_bface - 1)):
+        vals = []
+        for sgn in (1.0, -1.0):
+            la, be = case["logA"].copy(), case["beta"].copy()
+            (la if kind == "logA" else be)[idx] += sgn * h
+            up, _ = solve_state(la, be, u, p)
+            vals.append(phi(up))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        ad = float((gA if kind == "logA" else gB)[idx])
+        print(f"[gpu] adjoint d/d{kind}[{idx}]: {ad:.10e}  FD {fd:.10e}", flush=True)
+        assert abs(fd - ad) < 1e-5 * abs(ad) + 1e-9 * phi(u)
+    eng.close()
