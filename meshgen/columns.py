@@ -6,7 +6,11 @@ height).  A *refined* column is split isotropically 2x2x2 in every element,
 so it becomes 2x2 fine columns of ``2*nz`` elements; neighbouring columns
 differ by at most one level (the 2:1 condition of Sec. 3.1).  Fine elements
 next to unrefined columns have nonconforming (hanging) faces or edges
-(Sec. 3.2.1, figure "hanging").
+(Sec. 3.2.1, figure "hanging").  With ``refine_from = z0 > 0`` only layers
+z0 and above of a refined column are split (an octree-like mesh whose
+columns no longer span the full height in one level); the fine elements of
+the lowest refined layer then also hang on the coarse element below them
+through their -z face.
 
 Everything here is topology and node placement:
 
@@ -150,14 +154,17 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                 refined: Optional[np.ndarray] = None,
                 geometry: Optional[Callable[[np.ndarray], np.ndarray]] = None,
                 extent=(1.0, 1.0, 1.0),
-                base_normal_dirichlet: bool = False, pspace: str = "P") -> ColumnMesh:
+                base_normal_dirichlet: bool = False, pspace: str = "P", refine_from: int = 0) -> ColumnMesh:
     """Build a column mesh.
 
     ``geometry`` maps logical positions [n, 3] (coarse-cell units, x in
     [0, nx], ...) to physical coordinates [n, 3].  Default: the axis-aligned
     box ``extent`` (affine slab).  ``base_normal_dirichlet`` flags the
     z-component of every base node (logical z = 0) in ``dmask``.  ``pspace``
-    labels the pressure space the mesh is used with ("P" or "Q").
+    labels the pressure space the mesh is used with ("P" or "Q").  ``refine_from``
+    = z0 > 0 refines the marked columns only from coarse layer z0 upwards (an
+    octree-like mesh, T_xyz of the slab tests): the fine elements of layer 2 z0
+    then hang on the coarse elements below through their -z face.
     """
     if pspace not in ("P", "Q"):
         raise ValueError("pspace must be 'P' or 'Q'")
@@ -168,6 +175,8 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
         refined = np.zeros((nx, ny), dtype=bool)
     refined = np.asarray(refined, dtype=bool)
     assert refined.shape == (nx, ny)
+    z0 = int(refine_from)
+    assert 0 <= z0 < nz
 
     # ---- element list, column by column (y-major, then x), layers innermost
     lev, cx, cy, cz = [], [], [], []
@@ -177,12 +186,16 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                 lev.append(np.zeros(nz, np.int8))
                 cx.append(np.full(nz, i)); cy.append(np.full(nz, j)); cz.append(np.arange(nz))
             else:
+                if z0 > 0:                      # coarse layers below the refined part
+                    lev.append(np.zeros(z0, np.int8))
+                    cx.append(np.full(z0, i)); cy.append(np.full(z0, j)); cz.append(np.arange(z0))
+                nf = 2 * (nz - z0)
                 for hy in (0, 1):
                     for hx in (0, 1):
-                        lev.append(np.ones(2 * nz, np.int8))
-                        cx.append(np.full(2 * nz, 2 * i + hx))
-                        cy.append(np.full(2 * nz, 2 * j + hy))
-                        cz.append(np.arange(2 * nz))
+                        lev.append(np.ones(nf, np.int8))
+                        cx.append(np.full(nf, 2 * i + hx))
+                        cy.append(np.full(nf, 2 * j + hy))
+                        cz.append(np.arange(2 * z0, 2 * nz))
     elem_level = np.concatenate(lev)
     elem_cell = np.stack([np.concatenate(cx), np.concatenate(cy), np.concatenate(cz)], 1).astype(np.int32)
     n_el = elem_level.shape[0]
@@ -204,6 +217,7 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     face[:, 1] = fine & (hx == 1) & coarse_col(ci + 1, cj)
     face[:, 2] = fine & (hy == 0) & coarse_col(ci, cj - 1)
     face[:, 3] = fine & (hy == 1) & coarse_col(ci, cj + 1)
+    face[:, 4] = fine & (L == 2 * z0) & (z0 > 0)          # fine on top of the coarse part of the column
     # z-parallel edges at the column corners (sx, sy)
     zedge = np.zeros((n_el, 4), dtype=bool)
     for sy in (0, 1):
@@ -233,6 +247,7 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     on = [a0 == 0, a0 == k, a1 == 0, a1 == k]
     for f in range(4):
         dep |= face[:, f][:, None] & on[f][None, :]
+    dep |= face[:, 4][:, None] & (a2 == 0)[None, :]
     for sy in (0, 1):
         for sx in (0, 1):
             dep |= zedge[:, sx + 2 * sy][:, None] & (on[sx] & on[2 + sy])[None, :]
@@ -254,6 +269,10 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
             pc[d][sel] += (2 * side - 1)
             pa[d][sel] = (1 - side) * k
             done |= sel
+        sel = ~done & face[e_idx, 4] & (pa[2] == 0)          # -z face: the coarse element below
+        pc[2][sel] -= 1
+        pa[2][sel] = k
+        done |= sel
         for sy in (0, 1):
             for sx in (0, 1):
                 sel = (~done & zedge[e_idx, sx + 2 * sy]

@@ -194,8 +194,8 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
     for (int64_t i = 0; i < 3 * N; ++i) dm[i] = m->dmask[i] ? 1 : 0;
   if (3 * N >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EINVAL, "3*n_nodes must fit in int32");
   // ---- vertical node lines (line-block preconditioner): node n links to the node above it
-  // through every conforming z-line of an element (no slot on a hanging face or edge); the
-  // chains of links are the lines.  A node linked to two different nodes above (or below) makes
+  // through every z-line of an element on which neither of the two slots is dependent (on a
+  // hanging face or edge); the chains of links are the lines.  A node linked to two different nodes above (or below) makes
   // the lines inconsistent and disables the preconditioner for this mesh.
   {
     std::vector<int32_t> up((size_t)N, -1), down((size_t)N, -1);
@@ -203,9 +203,10 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
     std::vector<int32_t> cnt((size_t)N + 1, 0);
     for (int64_t e = 0; e < n_el && ok; ++e)
       for (int t = 0; t < P2; ++t) {
-        if (!zline_conforming_host(m->cmask[e], P, t % P, t / P)) continue;
-        for (int z = 0; z < P; ++z) cnt[(words[e * P3 + t + P2 * z] & NODE_MASK) + 1]++;
-        for (int z = 0; z + 1 < P; ++z) {
+        int lo, hi;
+        if (!zline_run_host(m->cmask[e], P, t % P, t / P, lo, hi)) continue;
+        for (int z = lo; z <= hi; ++z) cnt[(words[e * P3 + t + P2 * z] & NODE_MASK) + 1]++;
+        for (int z = lo; z < hi; ++z) {
           const int32_t a = words[e * P3 + t + P2 * z] & NODE_MASK, b = words[e * P3 + t + P2 * (z + 1)] & NODE_MASK;
           if ((up[a] != -1 && up[a] != b) || (down[b] != -1 && down[b] != a)) ok = false;
           up[a] = b;
@@ -219,8 +220,9 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
       std::vector<int32_t> next(cnt.begin(), cnt.end() - 1);
       for (int64_t e = 0; e < n_el; ++e)
         for (int t = 0; t < P2; ++t) {
-          if (!zline_conforming_host(m->cmask[e], P, t % P, t / P)) continue;
-          for (int z = 0; z < P; ++z) {
+          int lo, hi;
+          if (!zline_run_host(m->cmask[e], P, t % P, t / P, lo, hi)) continue;
+          for (int z = lo; z <= hi; ++z) {
             const int64_t slot = e * P3 + t + P2 * z;
             ctx->h_lslot[next[words[slot] & NODE_MASK]++] = (int32_t)slot;
           }

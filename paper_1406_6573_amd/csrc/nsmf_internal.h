@@ -122,10 +122,12 @@ hipError_t launch_lines(int P, int geo, hipStream_t s, const MeshView &m, const 
 hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const int32_t *line_ptr, const int32_t *line_node,
                              int64_t n_lines, const void *fac, const void *x, void *y);
 
-// A z-line (x = i, y = j) of an element with no slot on a hanging face or edge.  cmask bits:
-// 3..8 faces -x, +x, -y, +y, -z, +z; 9 + 4 dir + s0 + 2 s1 edge parallel to axis dir with sides
-// (s0, s1) along the other two axes in increasing order.
-inline bool zline_conforming_host(uint32_t cm, int P, int i, int j) {
+// The run of independent slots z = lo..hi on the z-line (x = i, y = j) of an element, false when
+// every slot of the line is dependent.  A hanging face or edge that contains the line makes all of
+// it dependent; a hanging z-normal face, or an x/y-parallel hanging edge through an end slot, makes
+// only that end slot dependent.  cmask bits: 3..8 faces -x, +x, -y, +y, -z, +z; 9 + 4 dir + s0 +
+// 2 s1 edge parallel to axis dir with sides (s0, s1) along the other two axes in increasing order.
+inline bool zline_run_host(uint32_t cm, int P, int i, int j, int &lo, int &hi) {
   const uint32_t f = cm >> 3;
   auto side = [P](int a) { return a == 0 ? 0 : (a == P - 1 ? 1 : -1); };
   auto edge = [&](int dir, int a, int b) {
@@ -136,10 +138,9 @@ inline bool zline_conforming_host(uint32_t cm, int P, int i, int j) {
   if (((f >> 1) & 1u) && i == P - 1) return false;
   if (((f >> 2) & 1u) && j == 0) return false;
   if (((f >> 3) & 1u) && j == P - 1) return false;
-  if ((f >> 4) & 3u) return false;                        // a hanging z-normal face touches every z-line
   if (edge(2, i, j)) return false;                        // z-parallel edge along the line
-  if (edge(0, j, 0) || edge(0, j, P - 1)) return false;   // x-parallel edges through its end slots
-  if (edge(1, i, 0) || edge(1, i, P - 1)) return false;   // y-parallel edges through its end slots
+  lo = (((f >> 4) & 1u) || edge(0, j, 0) || edge(1, i, 0)) ? 1 : 0;
+  hi = (((f >> 5) & 1u) || edge(0, j, P - 1) || edge(1, i, P - 1)) ? P - 2 : P - 1;
   return true;
 }
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,

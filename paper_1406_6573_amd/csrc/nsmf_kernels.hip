@@ -1139,23 +1139,23 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
 // columns couple strongly along z (element aspect ratios 16-300), which point Jacobi cannot
 // resolve; the line blocks are banded (bandwidth k) and symmetric positive definite.
 
-// Device twin of zline_conforming_host: no slot of the z-line (i, j) on a hanging face or edge.
-template <int P> __device__ __forceinline__ bool zline_conforming(uint32_t cm, int i, int j) {
+// Device twin of zline_run_host: the run lo..hi of independent slots on the z-line (i, j), false
+// when the whole line lies on a hanging face or edge.
+template <int P> __device__ __forceinline__ bool zline_run(uint32_t cm, int i, int j, int &lo, int &hi) {
   const uint32_t f = cm >> 3;
   if (zline_hanging<P>(cm, i, j)) return false;
-  if ((f >> 4) & 3u) return false;
-  if (edge_on<P>(cm, 0, j, 0) || edge_on<P>(cm, 0, j, P - 1)) return false;
-  if (edge_on<P>(cm, 1, i, 0) || edge_on<P>(cm, 1, i, P - 1)) return false;
+  lo = (((f >> 4) & 1u) || edge_on<P>(cm, 0, j, 0) || edge_on<P>(cm, 1, i, 0)) ? 1 : 0;
+  hi = (((f >> 5) & 1u) || edge_on<P>(cm, 0, j, P - 1) || edge_on<P>(cm, 1, i, P - 1)) ? P - 2 : P - 1;
   return true;
 }
 
-// Element line blocks at the linearisation point (FP64).  For a conforming z-line (i, j) of
-// element e and component c: F_e[(i,j,za,c), (i,j,zb,c)] = sum over the element's quadrature
+// Element line blocks at the linearisation point (FP64).  For the run lo..hi of independent slots
+// on the z-line (i, j) of element e and component c: F_e[(i,j,za,c), (i,j,zb,c)] = sum over the element's quadrature
 // points of mu'/2 (grad phi_a . grad phi_b + d_c phi_a d_c phi_b) - kappa (Sigma0 grad phi_a)_c
 // (Sigma0 grad phi_b)_c (eq. (rank4) tested with phi_a e_c and phi_b e_c), plus the basal term on
 // za = zb = 0.  Each slot stores its row towards the slots below it: buf[(c n_inc + slot) P + d] =
-// F_e[zb, zb - d], d = 0..k (0 where zb - d < 0).  Lines with a dependent slot store nothing
-// (their couplings through hanging constraints are left out of the preconditioner).
+// F_e[zb, zb - d], d = 0..k (0 where zb - d < lo), for zb = lo..hi.  Dependent slots store nothing
+// (couplings through hanging constraints are left out of the preconditioner).
 template <int P, int GEO>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ st,
@@ -1167,7 +1167,8 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
   const int64_t e = (int64_t)lb * E + el;
   if (el >= E || e >= m.n_el) return;      // no barriers in this kernel
   const int i = t % P, j = t / P;
-  if (!zline_conforming<P>(m.cmask[e], i, j)) return;
+  int lo, hi;
+  if (!zline_run<P>(m.cmask[e], i, j, lo, hi)) return;
   double rows[3][P][P];                     // rows[c][za][d] = F_e[za, za + d]
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -1241,7 +1242,8 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
     for (int zb = 0; zb < P; ++zb)
 #pragma unroll
       for (int d = 0; d < P; ++d)
-        buf[((size_t)c * m.n_inc + e * P3 + t + P2 * zb) * P + d] = zb >= d ? rows[c][zb - d][d] : 0.0;
+        if (zb >= lo && zb <= hi)
+          buf[((size_t)c * m.n_inc + e * P3 + t + P2 * zb) * P + d] = zb - d >= lo ? rows[c][zb - d][d] : 0.0;
 }
 
 // Node rows of the line blocks: A[(c N + n) W + d] = sum of the rows of the node's conforming slots

@@ -26,14 +26,15 @@ def setup(torch, case):
     return eng, t
 
 
-@pytest.mark.parametrize("k,mapped,pspace", [(2, False, "P"), (3, True, "P"), (4, False, "P"), (3, True, "Q"),
-                                             (4, False, "Q")])
-def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace):
+@pytest.mark.parametrize("k,mapped,pspace,refine_from", [(2, False, "P", 0), (3, True, "P", 0), (4, False, "P", 0),
+                                                         (3, True, "Q", 0), (4, False, "Q", 0), (2, True, "P", 1),
+                                                         (4, False, "P", 1)])
+def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, refine_from):
     """d_u = sum_e sum_a R_e[a, n]^2 F_e[aa] (exact diagonal of F on conforming parts), 1 on masked
     rows; d_p = -sum_q w detJ psi_m^2 / mu."""
     from oracle import StokesOracle
     torch = torch_cuda
-    case = small_case(k, mapped=mapped, pspace=pspace)
+    case = small_case(k, mapped=mapped, pspace=pspace, refine_from=refine_from)
     m = case["mesh"]
     eng, t = setup(torch, case)
     d_u, d_p = eng.jacobi_diag()
@@ -49,7 +50,8 @@ def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace):
     ref_p = -np.einsum("eq,qm->em", o.W / o.mu, o.ref.Psi ** 2)
     eu = np.max(np.abs(d_u.cpu().numpy() - ref_u) / np.abs(ref_u))
     ep = np.max(np.abs(d_p.cpu().numpy() - ref_p) / np.abs(ref_p))
-    print(f"[gpu] jacobi diag k={k} mapped={mapped}: rel err u {eu:.2e} p {ep:.2e}", flush=True)
+    print(f"[gpu] jacobi diag k={k} mapped={mapped} refine_from={refine_from}: rel err u {eu:.2e} p {ep:.2e}",
+          flush=True)
     assert eu < 1e-12 and ep < 1e-12
     # conforming slots: equals the assembled diagonal of J_c
     if not (m.cmask >> 3).any():
@@ -215,6 +217,119 @@ def test_line_blocks_match_oracle(torch_cuda, k, mapped):
     print(f"[gpu] line blocks k={k} mapped={mapped}: {n_lines} lines, rel err fp64 {err:.2e} fp32 {err32:.2e}",
           flush=True)
     assert err < 1e-11 and err32 < 1e-4
+    eng.close()
+
+
+def dependent_slots(cm, P):
+    """Slots of an element on one of its hanging faces or edges, from the cmask bits (faces -x, +x,
+    -y, +y, -z, +z at bits 3..8; the edge parallel to axis d with sides (s0, s1) along the other two
+    axes at bit 9 + 4 d + s0 + 2 s1)."""
+    a = np.arange(P ** 3)
+    co = [a % P, (a // P) % P, a // (P * P)]
+    side = lambda v: np.where(v == 0, 0, np.where(v == P - 1, 1, -1))
+    dep = np.zeros(P ** 3, dtype=bool)
+    for f in range(6):
+        if (cm >> (3 + f)) & 1:
+            dep |= co[f // 2] == (P - 1) * (f % 2)
+    for d in range(3):
+        o0, o1 = [c for c in range(3) if c != d]
+        for s0 in (0, 1):
+            for s1 in (0, 1):
+                if (cm >> (9 + 4 * d + s0 + 2 * s1)) & 1:
+                    dep |= (side(co[o0]) == s0) & (side(co[o1]) == s1)
+    return dep
+
+
+@pytest.mark.parametrize("k,mapped", [(2, True), (3, False), (4, True)])
+def test_line_blocks_hanging_runs(torch_cuda, k, mapped):
+    """Lateral and -z hanging faces: each line block is the sum, over the elements, of the oracle's
+    element matrix A_e restricted to the independent slots of one element z-line (couplings through
+    dependent slots left out), Dirichlet rows unit rows; the lines are the chains that these
+    element z-line runs link."""
+    torch = torch_cuda
+    from oracle import StokesOracle
+    case = small_case(k, mapped=mapped, frac=0.4, nx=3, ny=3, nz=2, refine_from=1)
+    m = case["mesh"]
+    P, N = k + 1, m.n_nodes
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"])
+    o.set_state(case["u"], case["p"])
+    A, _ = o.element_matrices()
+    S = P ** 3
+    up, down = {}, {}
+    blocks = [dict() for _ in range(3)]
+    for e in range(m.n_el):
+        dep = dependent_slots(int(m.cmask[e]), P)
+        for t in range(P * P):
+            run = [t + P * P * z for z in range(P) if not dep[t + P * P * z]]
+            for sa, sb in zip(run[:-1], run[1:]):
+                na, nb = int(m.elem_nodes[e, sa]), int(m.elem_nodes[e, sb])
+                assert up.get(na, nb) == nb and down.get(nb, na) == na
+                up[na], down[nb] = nb, na
+            for c in range(3):
+                for sa in run:
+                    for sb in run:
+                        key = (int(m.elem_nodes[e, sa]), int(m.elem_nodes[e, sb]))
+                        blocks[c][key] = blocks[c].get(key, 0.0) + A[e, c * S + sa, c * S + sb]
+    lines = []
+    for n in range(N):
+        if n in down:
+            continue
+        ln = [n]
+        while ln[-1] in up:
+            ln.append(up[ln[-1]])
+        lines.append(np.array(ln))
+    assert sum(len(ln) for ln in lines) == N
+    eng, t = setup(torch, case)
+    n_lines = eng.line_setup()
+    assert n_lines == len(lines)
+    rng = np.random.default_rng(6)
+    r = rng.uniform(-1, 1, (3, N))
+    ref = np.zeros_like(r)
+    for c in range(3):
+        msk = m.dmask[c].astype(bool)
+        for ln in lines:
+            B = np.array([[blocks[c].get((a, b), 0.0) for b in ln] for a in ln])
+            mk = msk[ln]
+            B[mk, :] = 0.0
+            B[:, mk] = 0.0
+            B[mk, mk] = 1.0
+            ref[c, ln] = np.linalg.solve(B, r[c, ln])
+    z = eng.line_apply(t(r)).cpu().numpy()
+    z32 = eng.line_apply(t(r).float()).double().cpu().numpy()
+    err, err32 = rel_err(z, ref), rel_err(z32, ref)
+    print(f"[gpu] hanging line runs k={k} mapped={mapped}: {n_lines} lines, rel err fp64 {err:.2e} fp32 {err32:.2e}",
+          flush=True)
+    assert err < 1e-11 and err32 < 1e-4
+    eng.close()
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "line"])
+def test_newton_step_zface_hanging(torch_cuda, precond):
+    """One Newton step on a mapped mesh with -z hanging faces: the reported linear reduction is the
+    true one (oracle Jacobian) and the next residual equals the oracle residual there."""
+    torch = torch_cuda
+    from oracle import StokesOracle
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    case = small_case(3, mapped=True, frac=0.4, nx=3, ny=3, nz=2, refine_from=1, body=(0.0, 0.0, -1.0))
+    m = case["mesh"]
+    eng, t = setup(torch, case)
+    u, p = t(case["u"]), t(case["p"])
+    nk = NewtonKrylov(eng, restart=60, precision="fp64", precond=precond)
+    st = nk.solve(u, p, n_newton=1, lin_tol=1e-10)
+    d = nk.d64.cpu().numpy()
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=(0.0, 0.0, -1.0))
+    o.set_state(case["u"], case["p"])
+    K = o.jacobian()
+    r0 = np.concatenate([a.ravel() for a in o.residual()])
+    true_red = np.linalg.norm(K @ d + r0) / np.linalg.norm(r0)
+    print(f"[gpu] newton step z-face hanging ({precond}): krylov {st.krylov_iterations[0]}, reported "
+          f"{st.linear_reductions[0]:.3e}, true {true_red:.3e}", flush=True)
+    assert abs(st.newton_residuals[0] - np.linalg.norm(r0)) < 1e-12 * np.linalg.norm(r0)
+    assert abs(st.linear_reductions[0] - true_red) < 1e-6 * max(true_red, 1e-8) + 1e-10
+    o.set_state(u.cpu().numpy(), p.cpu().numpy())
+    r1 = np.linalg.norm(np.concatenate([a.ravel() for a in o.residual()]))
+    assert abs(st.newton_residuals[1] - r1) < 1e-10 * r1
+    assert st.newton_residuals[1] < st.newton_residuals[0]
     eng.close()
 
 

@@ -132,6 +132,21 @@ def test_hanging_small_qspace(torch_cuda, k, mapped):
     check_case(torch_cuda, case, f"hanging k={k} mapped={mapped} Q_(k-2) pressure")
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("mapped", [False, True])
+def test_zface_hanging(torch_cuda, k, mapped):
+    """Refined columns that start one layer up: fine elements hang on the coarse element below
+    through their -z face (besides the lateral hanging faces and edges)."""
+    case = small_case(k, mapped=mapped, frac=0.4, refine_from=1, body=(0.0, 0.1, -1.0) if mapped else (0.0, 0.0, 0.0))
+    assert ((case["mesh"].cmask >> 7) & 1).any()
+    check_case(torch_cuda, case, f"z-face hanging k={k} mapped={mapped}")
+
+
+def test_zface_hanging_qspace(torch_cuda):
+    case = small_case(3, mapped=True, frac=0.4, refine_from=1, pspace="Q")
+    check_case(torch_cuda, case, "z-face hanging k=3 mapped Q_(k-2) pressure")
+
+
 def test_rigid_modes_gpu(torch_cuda):
     torch = torch_cuda
     case = small_case(3, mapped=True, mask=False)

@@ -18,11 +18,11 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def hanging_mesh(k, seed=1, nx=4, ny=4, nz=2, frac=0.3, extent=(40.0, 40.0, 1.0), mask=False, geometry=None,
-                 pspace="P"):
+                 pspace="P", refine_from=0):
     rng = np.random.default_rng(seed)
     ref = random_refined_columns(nx, ny, frac, rng)
     return column_mesh(k, nx, ny, nz, refined=ref, extent=extent, base_normal_dirichlet=mask, geometry=geometry,
-                       pspace=pspace)
+                       pspace=pspace, refine_from=refine_from)
 
 
 def exact_gauss(m):
@@ -117,8 +117,11 @@ def test_hanging_interpolation_worked_example():
 
 # ---------------------------------------------------------------- P9 continuity across hanging faces
 @pytest.mark.parametrize("k", [2, 3, 4])
-def test_hanging_continuity(k):
-    mesh = hanging_mesh(k, seed=3, nx=3, ny=3, frac=0.35)
+@pytest.mark.parametrize("refine_from", [0, 1])
+def test_hanging_continuity(k, refine_from):
+    """The gathered field is continuous across every face between a fine and a coarse element:
+    lateral faces, and with partially refined columns the -z face on top of a coarse element."""
+    mesh = hanging_mesh(k, seed=3, nx=3, ny=3, frac=0.35, refine_from=refine_from)
     o = StokesOracle(mesh)
     ref = o.ref
     rng = np.random.default_rng(0)
@@ -126,9 +129,9 @@ def test_hanging_continuity(k):
     ue = o.gather(u)
     lo, size = mesh.elem_box()
     coarse = {tuple(mesh.elem_cell[e]): e for e in range(mesh.n_el) if mesh.elem_level[e] == 0}
-    checked = 0
+    checked, checked_z = 0, 0
     for e in np.nonzero(mesh.elem_level == 1)[0]:
-        for d in range(2):
+        for d in range(3):
             for side in range(2):
                 # point on the fine element's face (d, side), random in the tangential directions
                 xi = rng.uniform(-1, 1, 3)
@@ -144,7 +147,9 @@ def test_hanging_continuity(k):
                 vc = ref.eval_basis(xc[None])[0] @ ue[ce]
                 assert np.allclose(vf, vc, atol=1e-13), (e, d, side)
                 checked += 1
+                checked_z += d == 2
     assert checked > 10
+    assert (checked_z > 4) == (refine_from > 0)
 
 
 # ---------------------------------------------------------------- P1 rigid modes, P2 kernel of B
@@ -166,6 +171,20 @@ def test_rigid_modes_in_kernel(k, pspace, mapped):
     mu_max = np.max(o.mu)
     assert np.max(np.abs(r_u)) < 1e-11 * mu_max * np.max(np.abs(rigid(mesh)))
     assert np.max(np.abs(r_p)) < 1e-12
+
+
+@pytest.mark.parametrize("k,pspace", [(2, "P"), (3, "Q"), (4, "P")])
+def test_rigid_modes_zface_hanging(k, pspace):
+    """Rigid motions stay in the kernel of the Jacobian on a mapped mesh whose refined columns start
+    one layer up (fine elements hanging on a coarse element through their -z face)."""
+    mesh = hanging_mesh(k, nx=3, ny=3, frac=0.35, geometry=terrain(3, 3, 2, 40.0), pspace=pspace, refine_from=1)
+    assert ((mesh.cmask >> 7) & 1).sum() > 0
+    rng = np.random.default_rng(5)
+    o = StokesOracle(mesh, 3.0, 1e-10, 0.5, rng.normal(0, 0.5, mesh.n_el), np.zeros(mesh.n_bface))
+    o.set_state(rng.uniform(-1, 1, (3, mesh.n_nodes)), rng.uniform(-1, 1, (mesh.n_el, mesh.n_p)))
+    K = o.jacobian()
+    x = np.concatenate([rigid(mesh).ravel(), np.zeros(mesh.n_el * mesh.n_p)])
+    assert np.max(np.abs(K @ x) / (scale_of(K, x) + 1e-300)) < 1e-11
 
 
 @pytest.mark.parametrize("k", [2, 3, 4])
