@@ -126,6 +126,16 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *mesh);
  * (DEVICE pointers, FP64; NULL means all zeros; copied).  Invalidates the state. */
 int nsmf_set_params(nsmf_ctx *ctx, const nsmf_params *params, const double *logA, const double *beta);
 
+/* Linearisation of the operator that nsmf_set_state prepares (Sec. 2.3):
+ *   NSMF_NEWTON (default): the Newton Jacobian with the tensor C(u) of eq. (rank4);
+ *   NSMF_PICARD: the Picard operator, which keeps the viscosity mu(u) and drops the
+ *     anisotropic (D (x) D) part of C(u); J_c is then the Stokes operator with frozen mu.
+ * Discards the stored state (call nsmf_set_state again).  nsmf_residual, nsmf_jacobi_diag and
+ * the line blocks follow the choice; nsmf_residual_vjp needs NSMF_NEWTON (its velocity part is
+ * the exact derivative J^T w) and fails with NSMF_ESTATE otherwise.  Errors: NSMF_EINVAL. */
+typedef enum { NSMF_NEWTON = 0, NSMF_PICARD = 1 } nsmf_linearization;
+int nsmf_set_linearization(nsmf_ctx *ctx, int kind);
+
 /* Linearisation point (u [3][n_nodes], p [n_el][n_p]; DEVICE, FP64; copied).  Computes
  * per quadrature point, in FP64, the viscosity and Newton-tensor data of eq. (rank4)
  * (and their FP32 roundings for the mixed path).  Requires mesh and params. */

@@ -10,6 +10,8 @@ Definitions followed (Sec. 2 and 3 of the paper):
   T = I - n n^T the tangential projector of eq. (robin);
 * Newton linearisation, eq. (newton) with the 4th-order tensor of eq. (rank4):
   C(u) = mu (I - (n-1)/(2n) D (x) D / (II + eps));
+  with picard=True the Picard operator of Sec. 2.3 instead: C(u) = mu I (the
+  D (x) D part dropped, the viscosity kept);
 * the saddle-point Jacobian A(u) = [[F, B^T], [B, 0]] (Sec. 4.1) assembled as
   sum_e R_e^T A_e R_e (Sec. 3.2.1);
 * normal Dirichlet condition u.n = 0 on flat bases (eq. (robin)) as a
@@ -52,8 +54,9 @@ class StokesOracle:
     """
 
     def __init__(self, mesh, n=3.0, eps=1e-10, B0=0.5, logA=None, beta=None, body=(0.0, 0.0, 0.0),
-                 elems=None):
+                 elems=None, picard=False):
         self.mesh = mesh
+        self.picard = bool(picard)
         self.n, self.eps, self.B0 = float(n), float(eps), float(B0)
         self.ref = ReferenceElement(mesh.k, getattr(mesh, "pspace", "P"))
         ref = self.ref
@@ -121,6 +124,8 @@ class StokesOracle:
         self.II = 0.5 * np.einsum("eqij,eqij->eq", self.D0, self.D0)
         self.mu = glen_viscosity(self.II, self.Be[:, None], self.n, self.eps)
         self.cpr = self.mu * (self.n - 1.0) / (2.0 * self.n) / (self.II + self.eps)
+        if self.picard:
+            self.cpr = np.zeros_like(self.cpr)
         self.pq = np.einsum("em,qm->eq", self.p[self.elems], self.ref.Psi)
         self.divu = np.einsum("eqcc->eq", G)
         if self.fl.size:

@@ -57,6 +57,7 @@ struct nsmf_ctx {
   // params
   bool have_params = false;
   nsmf_params prm;
+  int lin = NSMF_NEWTON;
   DevBuf<double> logA, beta64;
   DevBuf<float> beta32;
   // state
@@ -420,6 +421,15 @@ int nsmf_set_params(nsmf_ctx *ctx, const nsmf_params *prm, const double *logA, c
   return NSMF_OK;
 }
 
+int nsmf_set_linearization(nsmf_ctx *ctx, int kind) {
+  if (!ctx) return NSMF_EINVAL;
+  if (kind != NSMF_NEWTON && kind != NSMF_PICARD) return ctx->fail(NSMF_EINVAL, "linearization must be 0 or 1");
+  ctx->lin = kind;
+  ctx->have_state = false;
+  ctx->have_lines = false;
+  return NSMF_OK;
+}
+
 int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p) {
   if (!ctx || !u || !p) return NSMF_EINVAL;
   if (!ctx->have_mesh || !ctx->have_params) return ctx->fail(NSMF_ESTATE, "set_state needs mesh and params");
@@ -428,7 +438,8 @@ int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p) {
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->p.p, p, ctx->n_el * ctx->n_p * 8, hipMemcpyDeviceToDevice, s), "copy");
   NSMF_TRY(ctx,
            launch_state(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->u.p, ctx->logA.p,
-                        ctx->prm.n, ctx->prm.eps, ctx->prm.B0, ctx->st64.p, ctx->st32.p, ctx->fst64.p, ctx->fst32.p),
+                        ctx->prm.n, ctx->prm.eps, ctx->prm.B0, ctx->lin == NSMF_PICARD, ctx->st64.p, ctx->st32.p,
+                        ctx->fst64.p, ctx->fst32.p),
            "state kernel");
   ctx->have_state = true;
   ctx->have_lines = false;
@@ -455,6 +466,7 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
   if (!vjp && (!y_u || !y_p)) return NSMF_EINVAL;
   if (prec < 0 || prec > 2) return ctx->fail(NSMF_EINVAL, "precision must be 0, 1 or 2");
   if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "Jacobian apply needs a state");
+  if (vjp && ctx->lin != NSMF_NEWTON) return ctx->fail(NSMF_ESTATE, "residual_vjp needs the Newton linearization");
   hipStream_t s = ctx->stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {

@@ -103,7 +103,7 @@ hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &
                                 unsigned *flags);
 hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                         const void *tabs, const double *u, const double *logA, double n, double eps,
-                        double B0, double *st64, float *st32, double *fst64, float *fst32);
+                        double B0, bool picard, double *st64, float *st32, double *fst64, float *fst32);
 hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *geo_view,
                         const void *tabs, const void *state, const void *fstate, const void *beta,
                         const void *x_u, const void *x_p, void *y_u, void *y_p, double inv_n,

@@ -864,11 +864,12 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
 }
 
 // Linearisation point: per quadrature point mu' = w detJ mu, kappa, Sigma0 = mu' D(u)
-// (FP64, eq. (glen) and eq. (rank4)); per basal face point w|S| T u.
+// (FP64, eq. (glen) and eq. (rank4)); per basal face point w|S| T u.  The Picard operator keeps
+// mu and drops the D (x) D part of the tensor: kappa = 0.
 template <int P, int GEO>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ u,
-        const double *__restrict__ logA, double n, double eps, double B0, double *__restrict__ st64,
+        const double *__restrict__ logA, double n, double eps, double B0, int picard, double *__restrict__ st64,
         float *__restrict__ st32, double *__restrict__ fst64, float *__restrict__ fst32) {
   using T = double;
   const Tab<T, P> &tb = *tbp;
@@ -895,7 +896,7 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
     QpGeo<T, P, GEO> g;
     load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
     const double Be = B0 * exp(-logA[e] / n);
-    const double expo = (1.0 - n) / (2.0 * n), cf = (n - 1.0) / (2.0 * n);
+    const double expo = (1.0 - n) / (2.0 * n), cf = picard ? 0.0 : (n - 1.0) / (2.0 * n);
     double *s64 = st64;
     float *s32 = st32;
 #pragma unroll
@@ -1633,17 +1634,17 @@ hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &
 
 template <int P, int GEO>
 static hipError_t state_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
-                           const double *u, const double *logA, double n, double eps, double B0, double *st64,
-                           float *st32, double *fst64, float *fst32) {
+                           const double *u, const double *logA, double n, double eps, double B0, bool picard,
+                           double *st64, float *st32, double *fst64, float *fst32) {
   hipLaunchKernelGGL((k_state<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &((const TabSet<P> *)tabs)->d, u, logA, n, eps, B0,
-                     st64, st32, fst64, fst32);
+                     (int)picard, st64, st32, fst64, fst32);
   return hipGetLastError();
 }
 hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                         const void *tabs, const double *u, const double *logA, double n, double eps, double B0,
-                        double *st64, float *st32, double *fst64, float *fst32) {
+                        bool picard, double *st64, float *st32, double *fst64, float *fst32) {
 #define NSMF_ST(PP, GG) \
-  if (P == PP && geo == GG) return state_pg<PP, GG>(s, m, g, tabs, u, logA, n, eps, B0, st64, st32, fst64, fst32);
+  if (P == PP && geo == GG) return state_pg<PP, GG>(s, m, g, tabs, u, logA, n, eps, B0, picard, st64, st32, fst64, fst32);
   NSMF_ST(3, GEO_AFFINE) NSMF_ST(3, GEO_COLUMN) NSMF_ST(4, GEO_AFFINE) NSMF_ST(4, GEO_COLUMN)
   NSMF_ST(5, GEO_AFFINE) NSMF_ST(5, GEO_COLUMN)
 #undef NSMF_ST

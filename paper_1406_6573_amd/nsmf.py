@@ -26,7 +26,7 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_set_state", "nsmf_residual", "nsmf_jacobian_apply", "nsmf_residual_vjp", "nsmf_query",
             "nsmf_geometry_kind", "nsmf_set_kernel_timing", "nsmf_kernel_time", "nsmf_last_error",
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
-            "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply"]
+            "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization"]
 
 
 class NsmfError(RuntimeError):
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_jacobi_diag.argtypes = [vp, ci, vp, vp]
     lib.nsmf_line_setup.argtypes = [vp, i64p]
     lib.nsmf_line_apply.argtypes = [vp, ci, vp, vp]
+    lib.nsmf_set_linearization.argtypes = [vp, ci]
     lib.nsmf_vec_dots.argtypes = [vp, ci, i64, ci, vp, i64, vp, vp]
     lib.nsmf_vec_gemv.argtypes = [vp, ci, i64, ci, vp, i64, vp, dbl, vp]
     lib.nsmf_vec_axpby.argtypes = [vp, ci, i64, dbl, vp, dbl, vp]
@@ -174,6 +175,15 @@ class Engine:
             beta = self._vec(beta, (sz["n_bface"],), torch.float64, "beta")
         prm = _Params(float(n), float(eps), float(B0), (ctypes.c_double * 3)(*[float(b) for b in body]))
         self._check(self.lib.nsmf_set_params(self.h, ctypes.byref(prm), _ptr(logA), _ptr(beta)))
+        self.state_version += 1
+
+    def set_linearization(self, kind="newton"):
+        """Operator that set_state prepares: "newton" (default) or "picard" (mu kept, the
+        anisotropic part of the Newton tensor dropped).  Discards the stored state."""
+        codes = {"newton": 0, "picard": 1}
+        if kind not in codes:
+            raise ValueError("linearization must be 'newton' or 'picard'")
+        self._check(self.lib.nsmf_set_linearization(self.h, codes[kind]))
         self.state_version += 1
 
     def set_state(self, u, p):

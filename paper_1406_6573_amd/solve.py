@@ -11,8 +11,11 @@ preconditioner is the block upper-triangular [[F~, B^T], [0, S~]] of Sec. 4.2
 instead of the block-diagonal one: z_p = S~^-1 v_p, z_u = F~^-1 (v_u - B^T z_p),
 with B^T z_p from the engine's Jacobian apply at zero velocity (one more apply
 per iteration, fewer iterations).  A backtracking line search on ||r|| accepts
-the step.  Every vector operation runs in the engine's kernels (multi-dots with
-FP64 accumulation, basis combinations, scaling); the host holds only the small
+the step.  With linearization="picard" the steps solve with the Picard operator
+instead (viscosity kept, the anisotropic part of the Newton tensor dropped;
+Sec. 2.3), which converges linearly where Newton converges quadratically.
+Every vector operation runs in the engine's kernels (multi-dots with FP64
+accumulation, basis combinations, scaling); the host holds only the small
 Hessenberg least-squares problem.
 
 Precision modes:
@@ -47,11 +50,13 @@ class SolveStats:
 
 class NewtonKrylov:
     def __init__(self, engine, restart: int = 50, precision: str = "fp64", refine: int = 1,
-                 precond: str = "jacobi", triangular: bool = False):
+                 precond: str = "jacobi", triangular: bool = False, linearization: str = "newton"):
         if restart + 1 > 64:
             raise ValueError("restart must be at most 63")
         if precond not in ("jacobi", "line"):
             raise ValueError("precond must be 'jacobi' or 'line'")
+        engine.set_linearization(linearization)
+        self.linearization = linearization
         self.eng, self.m, self.precision, self.refine, self.precond = engine, restart, precision, refine, precond
         self.triangular = triangular
         sz = engine.sizes
@@ -247,6 +252,8 @@ def adjoint_gradient(nk: NewtonKrylov, u, p, dphi_u, dphi_p=None, tol: float = 1
     residual VJP.  (u, p) must solve r(u, p) = 0; dphi_u [3, n_nodes] and dphi_p [n_el, n_p] are
     FP64 device tensors.  Returns (dPhi/dlogA [n_el], dPhi/dbeta [n_bface], Krylov iterations,
     relative residual of the adjoint solve)."""
+    if nk.linearization != "newton":
+        raise ValueError("the adjoint needs the Newton linearization")
     eng = nk.eng
     eng.set_state(u.contiguous(), p.contiguous())
     nk.setup_preconditioner()

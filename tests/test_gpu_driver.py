@@ -333,6 +333,81 @@ def test_newton_step_zface_hanging(torch_cuda, precond):
     eng.close()
 
 
+@pytest.mark.parametrize("k,mapped,refine_from", [(2, True, 0), (3, False, 1), (4, True, 1)])
+def test_picard_operator_matches_oracle(torch_cuda, k, mapped, refine_from):
+    """The Picard operator (viscosity kept, anisotropic part of the Newton tensor dropped): FP64 and
+    FP32 applies and the Jacobi diagonal against the oracle's Picard J_c; the residual is unchanged;
+    the residual VJP is refused; switching back to Newton restores the Newton operator."""
+    torch = torch_cuda
+    from oracle import StokesOracle
+    from paper_1406_6573_amd.nsmf import NsmfError
+    case = small_case(k, mapped=mapped, refine_from=refine_from, body=(0.0, 0.1, -1.0))
+    m = case["mesh"]
+    eng, t = setup(torch, case)
+    r_newton = [a.cpu().numpy() for a in eng.residual()]
+    eng.set_linearization("picard")
+    with pytest.raises(NsmfError):
+        eng.residual()                                   # the state was discarded
+    eng.set_state(t(case["u"]), t(case["p"]))
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=(0.0, 0.1, -1.0),
+                     picard=True)
+    o.set_state(case["u"], case["p"])
+    K = o.jacobian()
+    absK = abs(K)
+    for (xu, xp) in case["dirs"][:2]:
+        x = np.concatenate([xu.ravel(), xp.ravel()])
+        yref, scale = K @ x, absK @ np.abs(x)
+        yu, yp = eng.jacobian_apply(t(xu), t(xp), "fp64")
+        y = np.concatenate([yu.cpu().numpy().ravel(), yp.cpu().numpy().ravel()])
+        yu32, yp32 = eng.jacobian_apply(t(xu).float(), t(xp).float(), "fp32")
+        y32 = np.concatenate([yu32.double().cpu().numpy().ravel(), yp32.double().cpu().numpy().ravel()])
+        e64, e32 = rel_err(y, yref), float(np.max(np.abs(y32 - yref) / np.maximum(scale, 1e-300)))
+        print(f"[gpu] picard k={k} mapped={mapped} refine_from={refine_from}: J fp64 rel {e64:.2e}, "
+              f"fp32 scaled {e32:.2e}", flush=True)
+        assert e64 < 1e-12 and e32 < 64 * 2.0 ** -24
+    ru, rp = eng.residual()
+    assert rel_err(np.concatenate([ru.cpu().numpy().ravel(), rp.cpu().numpy().ravel()]),
+                   np.concatenate([a.ravel() for a in r_newton])) < 1e-15
+    d_u, _ = eng.jacobi_diag()
+    A, _ = o.element_matrices()
+    S = o.S
+    dA = np.stack([np.diagonal(A, axis1=1, axis2=2)[:, c * S:(c + 1) * S].reshape(-1) for c in range(3)])
+    R2 = o.R.multiply(o.R)
+    ref_u = np.stack([R2.T @ dA[c] for c in range(3)])
+    ref_u[m.dmask.astype(bool)] = 1.0
+    assert np.max(np.abs(d_u.cpu().numpy() - ref_u) / np.abs(ref_u)) < 1e-12
+    with pytest.raises(NsmfError):
+        eng.residual_vjp(t(case["dirs"][0][0]), t(case["dirs"][0][1]), "fp64")
+    eng.set_linearization("newton")
+    eng.set_state(t(case["u"]), t(case["p"]))
+    on = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=(0.0, 0.1, -1.0))
+    on.set_state(case["u"], case["p"])
+    xu, xp = case["dirs"][0]
+    yu, yp = eng.jacobian_apply(t(xu), t(xp), "fp64")
+    y = np.concatenate([yu.cpu().numpy().ravel(), yp.cpu().numpy().ravel()])
+    assert rel_err(y, on.jacobian() @ np.concatenate([xu.ravel(), xp.ravel()])) < 1e-12
+    eng.close()
+
+
+def test_newton_converges_faster_than_picard(torch_cuda):
+    """Same start, same preconditioner and tolerance: after four steps the Newton residual is below
+    the Picard one, and the Picard residuals decrease monotonically."""
+    torch = torch_cuda
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    case = small_case(2, mapped=True, nx=3, ny=3, nz=2, body=(0.0, 0.0, -1.0))
+    res = {}
+    for lin in ("newton", "picard"):
+        eng, t = setup(torch, case)
+        u, p = t(case["u"]), t(case["p"])
+        nk = NewtonKrylov(eng, restart=60, precision="fp64", precond="line", linearization=lin)
+        st = nk.solve(u, p, n_newton=4, lin_tol=1e-10)
+        res[lin] = st.newton_residuals
+        print(f"[gpu] {lin}: residuals " + " ".join(f"{v:.3e}" for v in st.newton_residuals), flush=True)
+        eng.close()
+    assert all(b < a for a, b in zip(res["picard"][:-1], res["picard"][1:]))
+    assert res["newton"][-1] < res["picard"][-1]
+
+
 def test_line_preconditioner_beats_jacobi(torch_cuda):
     """Dome with hanging margin columns (aspect ratio ~30): one FGMRES(40) cycle reduces the Newton
     system's residual further with vertical-line blocks than with point Jacobi, and the reported

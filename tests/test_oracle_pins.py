@@ -187,6 +187,30 @@ def test_rigid_modes_zface_hanging(k, pspace):
     assert np.max(np.abs(K @ x) / (scale_of(K, x) + 1e-300)) < 1e-11
 
 
+@pytest.mark.parametrize("k,pspace", [(2, "P"), (3, "Q"), (4, "P")])
+def test_picard_operator_reproduces_residual(k, pspace):
+    """The Picard operator is the Stokes operator with the viscosity frozen at u, so applied to the
+    state itself it returns the residual: J_picard(u) (u, p) = r(u, p) + P f (P the Dirichlet mask,
+    f the load).  The Newton operator does not (its anisotropic term adds -c'(D:D) D), which the
+    second check confirms."""
+    mesh = hanging_mesh(k, nx=3, ny=3, frac=0.35, geometry=terrain(3, 3, 2, 40.0), mask=True, pspace=pspace)
+    rng = np.random.default_rng(8)
+    logA, beta = rng.normal(0, 0.5, mesh.n_el), np.exp(rng.normal(0, 1, mesh.n_bface))
+    u = rng.uniform(-1, 1, (3, mesh.n_nodes))
+    p = rng.uniform(-1, 1, (mesh.n_el, mesh.n_p))
+    x = np.concatenate([u.ravel(), p.ravel()])
+    gaps = {}
+    for picard in (True, False):
+        o = StokesOracle(mesh, 3.0, 1e-10, 0.5, logA, beta, body=(0.0, 0.1, -1.0), picard=picard)
+        o.set_state(u, p)
+        K = o.jacobian()
+        r = np.concatenate([a.ravel() for a in o.residual()])
+        f = np.concatenate([(o.pmask * o.load_vector()).ravel(), np.zeros(mesh.n_el * mesh.n_p)])
+        gaps[picard] = np.max(np.abs(K @ x - r - f) / (scale_of(K, x) + np.abs(f) + 1e-300))
+    assert gaps[True] < 1e-12
+    assert gaps[False] > 1e-3
+
+
 @pytest.mark.parametrize("k", [2, 3, 4])
 @pytest.mark.parametrize("pspace", ["P", "Q"])
 def test_divergence_free_in_kernel_of_B(k, pspace):
