@@ -82,6 +82,14 @@ typedef enum {
  *   3..8   hanging face -x, +x, -y, +y, -z, +z;
  *   9..20  hanging edge 4*dir + s0 + 2*s1, dir 0/1/2 = parallel to x/y/z, (s0, s1)
  *          the side (0 low / 1 high) along the two other axes in increasing order.
+ *
+ * Periodic lateral boundaries (the slab problem of Sec. 4.3): nodes on opposite periodic
+ * boundaries are one node (one id in elem_nodes; hanging faces across the boundary name the
+ * neighbour's nodes as usual) and coords holds one position per node.  period[d] > 0 is the
+ * translation between the identified boundaries along axis d (x or y); the engine moves every
+ * slot coordinate of an element by a multiple of it to within half a period of the element's
+ * first slot before building the geometry, so an element must be shorter than half a period
+ * along a periodic axis.  period = {0, 0, 0}: no periodic axis.
  */
 typedef enum { NSMF_PSPACE_P = 0, NSMF_PSPACE_Q = 1 } nsmf_pspace;
 
@@ -96,6 +104,7 @@ typedef struct {
   const int32_t *bface_elem;    /* [n_bface] elements whose zeta = -1 face lies on the base  */
   const uint8_t *dmask;         /* [3][n_nodes] 1 = Dirichlet-constrained component; may be NULL */
   int32_t pspace;               /* pressure space, nsmf_pspace (0 = P_{k-1}, 1 = Q_{k-2})    */
+  double period[3];             /* periodic translation per axis, 0 = not periodic; z must be 0 */
 } nsmf_mesh;
 
 /* Glen law (eq. (glen)): mu = B0 * exp(-logA_e / n) * (II + eps)^((1-n)/(2n)),

@@ -10,7 +10,11 @@ next to unrefined columns have nonconforming (hanging) faces or edges
 z0 and above of a refined column are split (an octree-like mesh whose
 columns no longer span the full height in one level); the fine elements of
 the lowest refined layer then also hang on the coarse element below them
-through their -z face.
+through their -z face.  With ``periodic = (px, py)`` the lateral boundaries
+of a periodic axis are identified (the slab problem of Sec. 4.3): nodes at
+logical x = nx are the nodes at x = 0, and columns on opposite boundaries are
+neighbours, with hanging faces across the boundary where their levels
+differ; ``period`` holds the physical translation between the boundaries.
 
 Everything here is topology and node placement:
 
@@ -77,6 +81,8 @@ class ColumnMesh:
     extent: tuple = (1.0, 1.0, 1.0)
     meta: dict = field(default_factory=dict)
     pspace: str = "P"            # pressure space: "P" = P_{k-1}, "Q" = Q_{k-2} (a label only)
+    periodic: tuple = (False, False)
+    period: tuple = (0.0, 0.0, 0.0)  # physical translation between identified boundaries, 0 = none
 
     @property
     def P(self) -> int:
@@ -154,7 +160,8 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                 refined: Optional[np.ndarray] = None,
                 geometry: Optional[Callable[[np.ndarray], np.ndarray]] = None,
                 extent=(1.0, 1.0, 1.0),
-                base_normal_dirichlet: bool = False, pspace: str = "P", refine_from: int = 0) -> ColumnMesh:
+                base_normal_dirichlet: bool = False, pspace: str = "P", refine_from: int = 0,
+                periodic=(False, False)) -> ColumnMesh:
     """Build a column mesh.
 
     ``geometry`` maps logical positions [n, 3] (coarse-cell units, x in
@@ -177,6 +184,13 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     assert refined.shape == (nx, ny)
     z0 = int(refine_from)
     assert 0 <= z0 < nz
+    per = (bool(periodic[0]), bool(periodic[1]))
+    ncell = (nx, ny)
+    # an element must be shorter than half a period along a periodic axis
+    assert all(ncell[d] >= 3 for d in range(2) if per[d]), "periodic axes need at least 3 columns"
+
+    def wrap(c, d):
+        return np.mod(c, ncell[d]) if per[d] else c
 
     # ---- element list, column by column (y-major, then x), layers innermost
     lev, cx, cy, cz = [], [], [], []
@@ -208,6 +222,7 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     hx, hy, hz = I % 2, J % 2, L % 2
 
     def coarse_col(ii, jj):
+        ii, jj = wrap(ii, 0), wrap(jj, 1)
         inside = (ii >= 0) & (ii < nx) & (jj >= 0) & (jj < ny)
         iic, jjc = np.clip(ii, 0, nx - 1), np.clip(jj, 0, ny - 1)
         return inside & ~refined[iic, jjc]
@@ -236,6 +251,9 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     nU = len(U)
     Cx, Cz = (nx + 1) * nU, (nz + 1) * nU
     codes = [_codes(elem_level, elem_cell[:, d], k, U, off, idx) for d in range(3)]  # [n_el, P]
+    for d in range(2):
+        if per[d]:
+            codes[d] = np.mod(codes[d], ncell[d] * nU)       # logical position n_d is position 0
     a = np.arange(P)
     a0 = np.tile(a, P * P)
     a1 = np.tile(np.repeat(a, P), P)
@@ -286,7 +304,8 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
         lev0 = np.zeros(e_idx.shape[0], dtype=np.int64)
         pcode = []
         for d in range(3):
-            c = _codes(lev0, pc[d], k, U, off, idx)          # [m, P]
+            c = _codes(lev0, wrap(pc[d], d) if d < 2 else pc[d], k, U, off, idx)          # [m, P]
+            c = np.mod(c, ncell[d] * nU) if d < 2 and per[d] else c
             pcode.append(c[np.arange(c.shape[0]), pa[d]])
         pkey = (pcode[1] * Cx + pcode[0]) * Cz + pcode[2]
         pos = np.searchsorted(keys, pkey)
@@ -302,10 +321,19 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     node_logical = np.stack([kc // nU + U[kc % nU] for kc in (kx, ky, kz)], 1)
     if geometry is None:
         Lx, Ly, Lz = extent
-        phys = node_logical * np.array([Lx / nx, Ly / ny, Lz / nz])
-    else:
-        phys = np.asarray(geometry(node_logical), dtype=np.float64)
+        geometry = lambda lg: lg * np.array([Lx / nx, Ly / ny, Lz / nz])
+    phys = np.asarray(geometry(node_logical), dtype=np.float64)
     coords = np.ascontiguousarray(phys.T)
+    period = [0.0, 0.0, 0.0]
+    for d in range(2):
+        if per[d]:
+            shift = np.zeros(3)
+            shift[d] = ncell[d]
+            dx = np.asarray(geometry(node_logical + shift), dtype=np.float64) - phys
+            period[d] = float(dx[0, d])
+            assert period[d] > 0 and np.allclose(dx, np.eye(3)[d] * period[d], rtol=0, atol=1e-12 * period[d]), \
+                "geometry is not periodic along a periodic axis"
+
 
     bface_elem = np.nonzero(elem_cell[:, 2] == 0)[0].astype(np.int32)
     dmask = np.zeros((3, keys.shape[0]), dtype=np.uint8)
@@ -316,7 +344,8 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                       elem_level=elem_level, elem_cell=elem_cell,
                       elem_nodes=elem_nodes.astype(np.int32), cmask=cmask,
                       node_logical=node_logical, coords=coords,
-                      bface_elem=bface_elem, dmask=dmask, extent=tuple(extent), pspace=pspace)
+                      bface_elem=bface_elem, dmask=dmask, extent=tuple(extent), pspace=pspace,
+                      periodic=per, period=tuple(period))
 
 
 def random_refined_columns(nx: int, ny: int, fraction: float, rng: np.random.Generator) -> np.ndarray:

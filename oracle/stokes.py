@@ -30,7 +30,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .reference import ReferenceElement
-from .restriction import build_restriction
+from .restriction import build_restriction, element_coordinates
 
 
 def glen_viscosity(II, Be, n, eps):
@@ -70,7 +70,7 @@ class StokesOracle:
 
         self.R = build_restriction(mesh, ref, self.elems)          # [E*S, n_nodes]
         # geometry: X_e = R_e X (watertight), J = dX/dxi at quadrature points
-        Xs = (self.R @ mesh.coords.T).reshape(E, self.S, 3)
+        Xs = element_coordinates(mesh, ref, self.R, self.elems)
         # the map's derivative is translation invariant: differentiate coordinates relative
         # to each element's first node so that rounding stays relative to the element size
         Xs = Xs - Xs[:, :1, :]

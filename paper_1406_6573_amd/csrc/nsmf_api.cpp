@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -167,6 +168,10 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   if (m->n_nodes >= (int64_t)NODE_MASK) return ctx->fail(NSMF_EINVAL, "n_nodes must be below 2^28");
   if (!m->elem_nodes || !m->cmask || !m->coords || (m->n_bface > 0 && !m->bface_elem))
     return ctx->fail(NSMF_EINVAL, "NULL mesh array");
+  for (int d = 0; d < 2; ++d)
+    if (!(m->period[d] >= 0.0) || !std::isfinite(m->period[d]))
+      return ctx->fail(NSMF_EINVAL, "period must be finite and >= 0");
+  if (m->period[2] != 0.0) return ctx->fail(NSMF_EUNSUP, "periodic z axis");
   ctx->free_mesh();
   const int P = m->k + 1, P2 = P * P, P3 = P2 * P;
   const int64_t n_el = m->n_el, N = m->n_nodes, NB = m->n_bface;
@@ -341,7 +346,8 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipMemcpyAsync(X.p, m->coords, 3 * N * 8, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, launch_fill(s, flags.p, 1), "fill");
   MeshView mv = ctx->mesh_view();
-  NSMF_TRY(ctx, launch_geometry_impl(P, 0, s, mv, ctx->tabs.p, X.p, nullptr, nullptr, nullptr, flags.p), "geometry");
+  NSMF_TRY(ctx, launch_geometry_impl(P, 0, s, mv, ctx->tabs.p, X.p, m->period, nullptr, nullptr, nullptr, flags.p),
+           "geometry");
   unsigned hflags = 0;
   NSMF_TRY(ctx, hipMemcpyAsync(&hflags, flags.p, 4, hipMemcpyDeviceToHost, s), "copy");
   NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry check");
@@ -370,7 +376,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   }
   NSMF_TRY(ctx, ctx->face64.alloc((size_t)NB * 4 * P2), "hipMalloc");
   NSMF_TRY(ctx, ctx->face32.alloc((size_t)NB * 4 * P2), "hipMalloc");
-  NSMF_TRY(ctx, launch_geometry_impl(P, ctx->geo == GEO_AFFINE ? 1 : 2, s, mv, ctx->tabs.p, X.p, ctx->geo_el64.p,
+  NSMF_TRY(ctx, launch_geometry_impl(P, ctx->geo == GEO_AFFINE ? 1 : 2, s, mv, ctx->tabs.p, X.p, m->period, ctx->geo_el64.p,
                                      ctx->geo_qp64.p, ctx->face64.p, nullptr),
            "geometry");
   NSMF_TRY(ctx, launch_d2f(s, ctx->geo_el64.p, ctx->geo_el32.p, nel_geo), "convert");

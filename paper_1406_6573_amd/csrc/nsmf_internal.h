@@ -99,8 +99,8 @@ template <typename T> struct GeoView {
 
 // Launchers (defined in nsmf_kernels.hip).  Return hipError_t of the launch.
 hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const void *tabs,
-                                const double *coords, double *el_out, double *qp_out, double *face_out,
-                                unsigned *flags);
+                                const double *coords, const double period[3], double *el_out, double *qp_out,
+                                double *face_out, unsigned *flags);
 hipError_t launch_state(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                         const void *tabs, const double *u, const double *logA, double n, double eps,
                         double B0, bool picard, double *st64, float *st32, double *fst64, float *fst32);

@@ -1392,8 +1392,9 @@ __global__ void k_line_apply(int64_t N, int64_t n_lines, const int32_t *__restri
 // affine data.  mode 2: store column data.  Face data are stored in modes 1 and 2.
 template <int P>
 __global__ void __launch_bounds__(Launch<P>::NT)
-k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ X, int mode, double *__restrict__ el_out,
-           double *__restrict__ qp_out, double *__restrict__ face_out, unsigned *__restrict__ flags) {
+k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ X, double px, double py,
+           int mode, double *__restrict__ el_out, double *__restrict__ qp_out, double *__restrict__ face_out,
+           unsigned *__restrict__ flags) {
   using T = double;
   const Tab<T, P> &tb = *tbp;
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
@@ -1419,9 +1420,15 @@ k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__r
     for (int c = 0; c < 3; ++c) ref0[els][c] = v[c][0];
   }
   __syncthreads();
+  // periodic axes: the periodic image of each slot nearest to the first slot
   if (act)
     for (int c = 0; c < 3; ++c)
-      for (int z = 0; z < P; ++z) v[c][z] -= ref0[els][c];
+      for (int z = 0; z < P; ++z) {
+        T d = v[c][z] - ref0[els][c];
+        const T per = c == 0 ? px : (c == 1 ? py : 0.0);
+        if (per > 0.0) d -= per * rint(d / per);
+        v[c][z] = d;
+      }
   __syncthreads();
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
@@ -1617,17 +1624,18 @@ hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n) {
 // ---------------------------------------------------------------- dispatch
 template <int P>
 static hipError_t geometry_p(int mode, hipStream_t s, const MeshView &m, const void *tabs, const double *X,
-                             double *el, double *qp, double *face, unsigned *flags) {
-  hipLaunchKernelGGL((k_geometry<P>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, &((const TabSet<P> *)tabs)->d, X, mode, el, qp, face,
-                     flags);
+                             const double *per, double *el, double *qp, double *face, unsigned *flags) {
+  hipLaunchKernelGGL((k_geometry<P>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, &((const TabSet<P> *)tabs)->d, X, per[0],
+                     per[1], mode, el, qp, face, flags);
   return hipGetLastError();
 }
 hipError_t launch_geometry_impl(int P, int mode, hipStream_t s, const MeshView &m, const void *tabs,
-                                const double *X, double *el, double *qp, double *face, unsigned *flags) {
+                                const double *X, const double period[3], double *el, double *qp, double *face,
+                                unsigned *flags) {
   switch (P) {
-    case 3: return geometry_p<3>(mode, s, m, tabs, X, el, qp, face, flags);
-    case 4: return geometry_p<4>(mode, s, m, tabs, X, el, qp, face, flags);
-    case 5: return geometry_p<5>(mode, s, m, tabs, X, el, qp, face, flags);
+    case 3: return geometry_p<3>(mode, s, m, tabs, X, period, el, qp, face, flags);
+    case 4: return geometry_p<4>(mode, s, m, tabs, X, period, el, qp, face, flags);
+    case 5: return geometry_p<5>(mode, s, m, tabs, X, period, el, qp, face, flags);
   }
   return hipErrorInvalidValue;
 }

@@ -26,15 +26,18 @@ def setup(torch, case):
     return eng, t
 
 
-@pytest.mark.parametrize("k,mapped,pspace,refine_from", [(2, False, "P", 0), (3, True, "P", 0), (4, False, "P", 0),
-                                                         (3, True, "Q", 0), (4, False, "Q", 0), (2, True, "P", 1),
-                                                         (4, False, "P", 1)])
-def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, refine_from):
+VARIANTS = {"": {}, "zface": dict(refine_from=1), "periodic": dict(periodic=(True, True), frac=0.4)}
+
+
+@pytest.mark.parametrize("k,mapped,pspace,variant", [(2, False, "P", ""), (3, True, "P", ""), (4, False, "P", ""),
+                                                     (3, True, "Q", ""), (4, False, "Q", ""), (2, True, "P", "zface"),
+                                                     (4, False, "P", "zface"), (3, True, "P", "periodic")])
+def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, variant):
     """d_u = sum_e sum_a R_e[a, n]^2 F_e[aa] (exact diagonal of F on conforming parts), 1 on masked
     rows; d_p = -sum_q w detJ psi_m^2 / mu."""
     from oracle import StokesOracle
     torch = torch_cuda
-    case = small_case(k, mapped=mapped, pspace=pspace, refine_from=refine_from)
+    case = small_case(k, mapped=mapped, pspace=pspace, **VARIANTS[variant])
     m = case["mesh"]
     eng, t = setup(torch, case)
     d_u, d_p = eng.jacobi_diag()
@@ -50,8 +53,7 @@ def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, refine_from):
     ref_p = -np.einsum("eq,qm->em", o.W / o.mu, o.ref.Psi ** 2)
     eu = np.max(np.abs(d_u.cpu().numpy() - ref_u) / np.abs(ref_u))
     ep = np.max(np.abs(d_p.cpu().numpy() - ref_p) / np.abs(ref_p))
-    print(f"[gpu] jacobi diag k={k} mapped={mapped} refine_from={refine_from}: rel err u {eu:.2e} p {ep:.2e}",
-          flush=True)
+    print(f"[gpu] jacobi diag k={k} mapped={mapped} {variant}: rel err u {eu:.2e} p {ep:.2e}", flush=True)
     assert eu < 1e-12 and ep < 1e-12
     # conforming slots: equals the assembled diagonal of J_c
     if not (m.cmask >> 3).any():
@@ -240,15 +242,16 @@ def dependent_slots(cm, P):
     return dep
 
 
-@pytest.mark.parametrize("k,mapped", [(2, True), (3, False), (4, True)])
-def test_line_blocks_hanging_runs(torch_cuda, k, mapped):
+@pytest.mark.parametrize("k,mapped,variant", [(2, True, "zface"), (3, False, "zface"), (4, True, "zface"),
+                                             (3, True, "periodic")])
+def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
     """Lateral and -z hanging faces: each line block is the sum, over the elements, of the oracle's
     element matrix A_e restricted to the independent slots of one element z-line (couplings through
     dependent slots left out), Dirichlet rows unit rows; the lines are the chains that these
     element z-line runs link."""
     torch = torch_cuda
     from oracle import StokesOracle
-    case = small_case(k, mapped=mapped, frac=0.4, nx=3, ny=3, nz=2, refine_from=1)
+    case = small_case(k, mapped=mapped, **{**dict(frac=0.4, nx=3, ny=3, nz=2), **VARIANTS[variant]})
     m = case["mesh"]
     P, N = k + 1, m.n_nodes
     o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"])
@@ -297,20 +300,22 @@ def test_line_blocks_hanging_runs(torch_cuda, k, mapped):
     z = eng.line_apply(t(r)).cpu().numpy()
     z32 = eng.line_apply(t(r).float()).double().cpu().numpy()
     err, err32 = rel_err(z, ref), rel_err(z32, ref)
-    print(f"[gpu] hanging line runs k={k} mapped={mapped}: {n_lines} lines, rel err fp64 {err:.2e} fp32 {err32:.2e}",
+    print(f"[gpu] hanging line runs k={k} mapped={mapped} {variant}: {n_lines} lines, rel err fp64 {err:.2e} fp32 {err32:.2e}",
           flush=True)
     assert err < 1e-11 and err32 < 1e-4
     eng.close()
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "line"])
-def test_newton_step_zface_hanging(torch_cuda, precond):
-    """One Newton step on a mapped mesh with -z hanging faces: the reported linear reduction is the
-    true one (oracle Jacobian) and the next residual equals the oracle residual there."""
+@pytest.mark.parametrize("precond,variant", [("jacobi", "zface"), ("line", "zface"), ("line", "periodic")])
+def test_newton_step_variants(torch_cuda, precond, variant):
+    """One Newton step on a mapped mesh with -z hanging faces, or periodic in x and y: the reported
+    linear reduction is the true one (oracle Jacobian) and the next residual equals the oracle
+    residual there."""
     torch = torch_cuda
     from oracle import StokesOracle
     from paper_1406_6573_amd.solve import NewtonKrylov
-    case = small_case(3, mapped=True, frac=0.4, nx=3, ny=3, nz=2, refine_from=1, body=(0.0, 0.0, -1.0))
+    case = small_case(3, mapped=True, **{**dict(frac=0.4, nx=3, ny=3, nz=2, body=(0.0, 0.0, -1.0)),
+                                         **VARIANTS[variant]})
     m = case["mesh"]
     eng, t = setup(torch, case)
     u, p = t(case["u"]), t(case["p"])
@@ -322,7 +327,7 @@ def test_newton_step_zface_hanging(torch_cuda, precond):
     K = o.jacobian()
     r0 = np.concatenate([a.ravel() for a in o.residual()])
     true_red = np.linalg.norm(K @ d + r0) / np.linalg.norm(r0)
-    print(f"[gpu] newton step z-face hanging ({precond}): krylov {st.krylov_iterations[0]}, reported "
+    print(f"[gpu] newton step {variant} ({precond}): krylov {st.krylov_iterations[0]}, reported "
           f"{st.linear_reductions[0]:.3e}, true {true_red:.3e}", flush=True)
     assert abs(st.newton_residuals[0] - np.linalg.norm(r0)) < 1e-12 * np.linalg.norm(r0)
     assert abs(st.linear_reductions[0] - true_red) < 1e-6 * max(true_red, 1e-8) + 1e-10
@@ -333,15 +338,15 @@ def test_newton_step_zface_hanging(torch_cuda, precond):
     eng.close()
 
 
-@pytest.mark.parametrize("k,mapped,refine_from", [(2, True, 0), (3, False, 1), (4, True, 1)])
-def test_picard_operator_matches_oracle(torch_cuda, k, mapped, refine_from):
+@pytest.mark.parametrize("k,mapped,variant", [(2, True, ""), (3, False, "zface"), (4, True, "periodic")])
+def test_picard_operator_matches_oracle(torch_cuda, k, mapped, variant):
     """The Picard operator (viscosity kept, anisotropic part of the Newton tensor dropped): FP64 and
     FP32 applies and the Jacobi diagonal against the oracle's Picard J_c; the residual is unchanged;
     the residual VJP is refused; switching back to Newton restores the Newton operator."""
     torch = torch_cuda
     from oracle import StokesOracle
     from paper_1406_6573_amd.nsmf import NsmfError
-    case = small_case(k, mapped=mapped, refine_from=refine_from, body=(0.0, 0.1, -1.0))
+    case = small_case(k, mapped=mapped, body=(0.0, 0.1, -1.0), **VARIANTS[variant])
     m = case["mesh"]
     eng, t = setup(torch, case)
     r_newton = [a.cpu().numpy() for a in eng.residual()]
@@ -362,7 +367,7 @@ def test_picard_operator_matches_oracle(torch_cuda, k, mapped, refine_from):
         yu32, yp32 = eng.jacobian_apply(t(xu).float(), t(xp).float(), "fp32")
         y32 = np.concatenate([yu32.double().cpu().numpy().ravel(), yp32.double().cpu().numpy().ravel()])
         e64, e32 = rel_err(y, yref), float(np.max(np.abs(y32 - yref) / np.maximum(scale, 1e-300)))
-        print(f"[gpu] picard k={k} mapped={mapped} refine_from={refine_from}: J fp64 rel {e64:.2e}, "
+        print(f"[gpu] picard k={k} mapped={mapped} {variant}: J fp64 rel {e64:.2e}, "
               f"fp32 scaled {e32:.2e}", flush=True)
         assert e64 < 1e-12 and e32 < 64 * 2.0 ** -24
     ru, rp = eng.residual()

@@ -142,6 +142,18 @@ def test_zface_hanging(torch_cuda, k, mapped):
     check_case(torch_cuda, case, f"z-face hanging k={k} mapped={mapped}")
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("mapped", [False, True])
+def test_periodic(torch_cuda, k, mapped):
+    """Periodic in x and y with refined columns on the boundaries (hanging faces and edges across
+    the identified boundaries)."""
+    case = small_case(k, mapped=mapped, frac=0.4, periodic=(True, True),
+                      body=(0.0, 0.1, -1.0) if mapped else (0.0, 0.0, 0.0))
+    m = case["mesh"]
+    assert m.period[0] > 0 and m.period[1] > 0
+    check_case(torch_cuda, case, f"periodic k={k} mapped={mapped}")
+
+
 def test_zface_hanging_qspace(torch_cuda):
     case = small_case(3, mapped=True, frac=0.4, refine_from=1, pspace="Q")
     check_case(torch_cuda, case, "z-face hanging k=3 mapped Q_(k-2) pressure")

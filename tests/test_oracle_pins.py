@@ -7,6 +7,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import sympy
 
 from meshgen.columns import column_mesh, random_refined_columns
@@ -150,6 +151,83 @@ def test_hanging_continuity(k, refine_from):
                 checked_z += d == 2
     assert checked > 10
     assert (checked_z > 4) == (refine_from > 0)
+
+
+def _element_at(mesh, q):
+    """An element whose logical box contains q (brute force), with q's reference coordinates."""
+    lo, size = mesh.elem_box()
+    inside = np.all((q >= lo - 1e-12) & (q <= lo + size[:, None] + 1e-12), axis=1)
+    e = int(np.nonzero(inside)[0][0])
+    return e, 2.0 * (q - lo[e]) / size[e] - 1.0
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_periodic_continuity(k):
+    """Periodic x and y with refined columns on the boundary: the gathered field of every element
+    agrees, at random points of its lateral faces, with the element on the other side -- across the
+    identified boundaries through the translate of the point by the number of columns."""
+    refined = np.zeros((4, 3), dtype=bool)
+    refined[0, 1] = refined[3, 0] = refined[1, 2] = True
+    mesh = column_mesh(k, 4, 3, 2, refined=refined, extent=(8.0, 6.0, 1.0), periodic=(True, True))
+    o = StokesOracle(mesh)
+    rng = np.random.default_rng(1)
+    ue = o.gather(rng.uniform(-1, 1, (3, mesh.n_nodes)))
+    lo, size = mesh.elem_box()
+    n = np.array([mesh.nx, mesh.ny, 1e9])
+    across = 0
+    for e in range(mesh.n_el):
+        for d in range(2):
+            for side in range(2):
+                xi = rng.uniform(-1, 1, 3)
+                xi[d] = 2 * side - 1
+                p = lo[e] + size[e] * (xi + 1) / 2
+                q = p.copy()
+                q[d] += (2 * side - 1) * 1e-9
+                wrapped = q[d] < 0 or q[d] > n[d]
+                q[d] = np.mod(q[d], n[d])
+                f, _ = _element_at(mesh, q)
+                q[d] -= (2 * side - 1) * 1e-9
+                xf = 2.0 * (q - lo[f]) / size[f] - 1.0
+                xf[d] = np.clip(xf[d], -1, 1)
+                vf = o.ref.eval_basis(xi[None])[0] @ ue[e]
+                vg = o.ref.eval_basis(xf[None])[0] @ ue[f]
+                assert np.allclose(vf, vg, atol=1e-12), (e, d, side)
+                across += wrapped
+    assert across > 20
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_periodic_equals_identified_assembly(k):
+    """Refined columns away from the boundary: the periodic residual and Jacobian equal those of the
+    non-periodic mesh with the boundary nodes identified, r_per = Pi^T r(Pi u), K_per = Pi^T K Pi, with
+    Pi the map from the non-periodic nodes to their periodic nodes (logical position modulo the
+    number of columns); the element geometry is the same."""
+    refined = np.zeros((4, 4), dtype=bool)
+    refined[1, 2] = refined[2, 1] = True
+    kw = dict(refined=refined, geometry=terrain(4, 4, 2, 40.0))
+    mp = column_mesh(k, 4, 4, 2, periodic=(True, True), **kw)
+    mn = column_mesh(k, 4, 4, 2, **kw)
+    key = lambda lg: np.round(np.mod(lg, [4, 4, 1e9]) * 64).astype(np.int64) @ np.array([1, 10 ** 5, 10 ** 10])
+    kp = {int(v): i for i, v in enumerate(key(mp.node_logical))}
+    pi = np.array([kp[int(v)] for v in key(mn.node_logical)])
+    Pi = sp.csr_matrix((np.ones(mn.n_nodes), (np.arange(mn.n_nodes), pi)), shape=(mn.n_nodes, mp.n_nodes))
+    rng = np.random.default_rng(4)
+    logA, beta = rng.normal(0, 0.5, mp.n_el), np.exp(rng.normal(0, 1, mp.n_bface))
+    u = rng.uniform(-1, 1, (3, mp.n_nodes))
+    p = rng.uniform(-1, 1, (mp.n_el, mp.n_p))
+    op = StokesOracle(mp, 3.0, 1e-10, 0.5, logA, beta, body=(0.0, 0.1, -1.0))
+    on = StokesOracle(mn, 3.0, 1e-10, 0.5, logA, beta, body=(0.0, 0.1, -1.0))
+    assert np.allclose(op.detJ, on.detJ, rtol=1e-13)
+    op.set_state(u, p)
+    on.set_state(np.stack([Pi @ u[c] for c in range(3)]), p)
+    ru_p, rp_p = op.residual()
+    ru_n, rp_n = on.residual()
+    assert np.allclose(ru_p, np.stack([Pi.T @ ru_n[c] for c in range(3)]), rtol=0, atol=1e-12 * np.abs(ru_n).max())
+    assert np.allclose(rp_p, rp_n, rtol=0, atol=1e-14)
+    P3 = sp.block_diag([Pi] * 3 + [sp.eye(mp.n_el * mp.n_p)], format="csr")
+    Kp, Kn = op.jacobian(), on.jacobian()
+    D = (Kp - P3.T @ Kn @ P3).tocoo()
+    assert np.max(np.abs(D.data), initial=0.0) < 1e-12 * np.abs(Kn.data).max()
 
 
 # ---------------------------------------------------------------- P1 rigid modes, P2 kernel of B
