@@ -395,21 +395,25 @@ def test_picard_operator_matches_oracle(torch_cuda, k, mapped, variant):
 
 
 def test_newton_converges_faster_than_picard(torch_cuda):
-    """Same start, same preconditioner and tolerance: after four steps the Newton residual is below
-    the Picard one, and the Picard residuals decrease monotonically."""
+    """Picard steps decrease the residual monotonically from a rough start; from the state they reach,
+    three Newton steps reduce the residual further than three more Picard steps (same preconditioner
+    and tolerance): Newton converges quadratically near the solution, Picard linearly."""
     torch = torch_cuda
     from paper_1406_6573_amd.solve import NewtonKrylov
     case = small_case(2, mapped=True, nx=3, ny=3, nz=2, body=(0.0, 0.0, -1.0))
+    eng, t = setup(torch, case)
+    u, p = t(case["u"]), t(case["p"])
+    st = NewtonKrylov(eng, restart=60, precision="fp64", precond="line", linearization="picard").solve(
+        u, p, n_newton=6, lin_tol=1e-10)
+    print("[gpu] picard from the start: " + " ".join(f"{v:.3e}" for v in st.newton_residuals), flush=True)
+    assert all(b < a for a, b in zip(st.newton_residuals[:-1], st.newton_residuals[1:]))
     res = {}
     for lin in ("newton", "picard"):
-        eng, t = setup(torch, case)
-        u, p = t(case["u"]), t(case["p"])
+        u1, p1 = u.clone(), p.clone()
         nk = NewtonKrylov(eng, restart=60, precision="fp64", precond="line", linearization=lin)
-        st = nk.solve(u, p, n_newton=4, lin_tol=1e-10)
-        res[lin] = st.newton_residuals
-        print(f"[gpu] {lin}: residuals " + " ".join(f"{v:.3e}" for v in st.newton_residuals), flush=True)
-        eng.close()
-    assert all(b < a for a, b in zip(res["picard"][:-1], res["picard"][1:]))
+        res[lin] = nk.solve(u1, p1, n_newton=3, lin_tol=1e-12).newton_residuals
+        print(f"[gpu] {lin}: residuals " + " ".join(f"{v:.3e}" for v in res[lin]), flush=True)
+    eng.close()
     assert res["newton"][-1] < res["picard"][-1]
 
 

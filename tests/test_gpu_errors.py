@@ -98,6 +98,13 @@ def test_mesh_validation(torch_cuda):
     s = _Mesh(2, en.shape[0], X.shape[1], bf.shape[0], en.ctypes.data, cm.ctypes.data, X.ctypes.data,
               bf.ctypes.data if bf.size else None, None, 7)
     assert eng.lib.nsmf_upload_mesh(eng.h, ctypes.byref(s)) == -1
+    # periods: negative -> EINVAL, periodic z -> EUNSUP
+    for per, code in (((-1.0, 0.0, 0.0), -1), ((0.0, 0.0, 2.0), -5)):
+        s = _Mesh(2, en.shape[0], X.shape[1], bf.shape[0], en.ctypes.data, cm.ctypes.data, X.ctypes.data,
+                  bf.ctypes.data if bf.size else None, None, 0, (ctypes.c_double * 3)(*per))
+        assert eng.lib.nsmf_upload_mesh(eng.h, ctypes.byref(s)) == code
+    # linearization kind out of range
+    assert eng.lib.nsmf_set_linearization(eng.h, 2) == -1
     # the context is still usable
     eng.upload_mesh(good)
     assert eng.sizes["n_el"] == good.n_el
