@@ -90,6 +90,16 @@ typedef enum {
  * slot coordinate of an element by a multiple of it to within half a period of the element's
  * first slot before building the geometry, so an element must be shorter than half a period
  * along a periodic axis.  period = {0, 0, 0}: no periodic axis.
+ *
+ * Nodal frames (eq. (robin), second line, u . n = 0 on a curved base): a node listed in
+ * frame_nodes holds its velocity unknowns in the local frame Q of frames (u = Q u_hat, the
+ * columns of Q the local axes); its dmask bits and every vector entry of the node (x_u, y_u,
+ * residual rows, f_u, the diagonal and the line blocks) refer to the local components.  With
+ * the unit normal as third column and dmask set on component 2 this imposes u . n = 0 by
+ * rotation.  Every slot naming such a node must be a bottom slot (a2 = 0): basal nodes, which
+ * elements above the base may name through hanging faces.  Q must be orthonormal to 1e-12.
+ * Errors: NSMF_EINVAL (n_frames < 0, NULL arrays), NSMF_EMESH (id out of range or repeated,
+ * Q not orthonormal, a framed node in a slot with a2 > 0).
  */
 typedef enum { NSMF_PSPACE_P = 0, NSMF_PSPACE_Q = 1 } nsmf_pspace;
 
@@ -105,6 +115,9 @@ typedef struct {
   const uint8_t *dmask;         /* [3][n_nodes] 1 = Dirichlet-constrained component; may be NULL */
   int32_t pspace;               /* pressure space, nsmf_pspace (0 = P_{k-1}, 1 = Q_{k-2})    */
   double period[3];             /* periodic translation per axis, 0 = not periodic; z must be 0 */
+  int64_t n_frames;             /* number of nodes with a local frame (>= 0)                 */
+  const int32_t *frame_nodes;   /* [n_frames] node ids, each at most once (NULL if none)     */
+  const double *frames;         /* [n_frames][3][3] row-major orthonormal Q (NULL if none)   */
 } nsmf_mesh;
 
 /* Glen law (eq. (glen)): mu = B0 * exp(-logA_e / n) * (II + eps)^((1-n)/(2n)),

@@ -15,6 +15,10 @@ of a periodic axis are identified (the slab problem of Sec. 4.3): nodes at
 logical x = nx are the nodes at x = 0, and columns on opposite boundaries are
 neighbours, with hanging faces across the boundary where their levels
 differ; ``period`` holds the physical translation between the boundaries.
+With ``base_frames=True`` every basal node gets a local frame whose third
+axis is the unit normal of the bed surface there (tangents: the x-direction
+tangent of the bed and normal x tangent), and the normal component is
+flagged in ``dmask``: u . n = 0 on a curved base (eq. (robin)) by rotation.
 
 Everything here is topology and node placement:
 
@@ -83,6 +87,8 @@ class ColumnMesh:
     pspace: str = "P"            # pressure space: "P" = P_{k-1}, "Q" = Q_{k-2} (a label only)
     periodic: tuple = (False, False)
     period: tuple = (0.0, 0.0, 0.0)  # physical translation between identified boundaries, 0 = none
+    frame_nodes: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))   # [n_frames]
+    frames: np.ndarray = field(default_factory=lambda: np.zeros((0, 3, 3)))         # [n_frames, 3, 3]
 
     @property
     def P(self) -> int:
@@ -161,7 +167,7 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
                 geometry: Optional[Callable[[np.ndarray], np.ndarray]] = None,
                 extent=(1.0, 1.0, 1.0),
                 base_normal_dirichlet: bool = False, pspace: str = "P", refine_from: int = 0,
-                periodic=(False, False)) -> ColumnMesh:
+                periodic=(False, False), base_frames: bool = False) -> ColumnMesh:
     """Build a column mesh.
 
     ``geometry`` maps logical positions [n, 3] (coarse-cell units, x in
@@ -339,13 +345,30 @@ def column_mesh(k: int, nx: int, ny: int, nz: int,
     dmask = np.zeros((3, keys.shape[0]), dtype=np.uint8)
     if base_normal_dirichlet:
         dmask[2, node_logical[:, 2] == 0.0] = 1
+    frame_nodes = np.zeros(0, np.int32)
+    frames = np.zeros((0, 3, 3))
+    if base_frames:
+        assert not base_normal_dirichlet
+        frame_nodes = np.nonzero(node_logical[:, 2] == 0.0)[0].astype(np.int32)
+        lg = node_logical[frame_nodes]
+        h = 1e-5                                     # central differences of the geometry map
+        ex, ey = np.array([h, 0.0, 0.0]), np.array([0.0, h, 0.0])
+        tx = (np.asarray(geometry(lg + ex)) - np.asarray(geometry(lg - ex))) / (2 * h)
+        ty = (np.asarray(geometry(lg + ey)) - np.asarray(geometry(lg - ey))) / (2 * h)
+        nrm = np.cross(tx, ty)
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        t1 = tx - np.sum(tx * nrm, axis=1, keepdims=True) * nrm
+        t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+        t2 = np.cross(nrm, t1)
+        frames = np.stack([t1, t2, nrm], axis=2)     # columns: local axes
+        dmask[2, frame_nodes] = 1
 
     return ColumnMesh(k=k, nx=nx, ny=ny, nz=nz, refined=refined,
                       elem_level=elem_level, elem_cell=elem_cell,
                       elem_nodes=elem_nodes.astype(np.int32), cmask=cmask,
                       node_logical=node_logical, coords=coords,
                       bface_elem=bface_elem, dmask=dmask, extent=tuple(extent), pspace=pspace,
-                      periodic=per, period=tuple(period))
+                      periodic=per, period=tuple(period), frame_nodes=frame_nodes, frames=frames)
 
 
 def random_refined_columns(nx: int, ny: int, fraction: float, rng: np.random.Generator) -> np.ndarray:

@@ -17,6 +17,10 @@ Definitions followed (Sec. 2 and 3 of the paper):
 * normal Dirichlet condition u.n = 0 on flat bases (eq. (robin)) as a
   component mask P: state and residual use P u, residual rows of masked
   components are u itself, Jacobian J_c = P K P + (I - P);
+* on a curved base the same condition by nodal frames: a node with frame Q
+  holds u_hat, u = Q u_hat, so with Q the block-diagonal change of variables
+  the operator is J_c = P Q^T K Q P + (I - P) and the residual
+  P Q^T r(Q P u_hat) + (I - P) u_hat, the mask acting on local components;
 * energy of the appendix (with the friction coefficient beta written into the
   boundary term): Pi(u) = int 2n/(n+1) B (II+eps)^((n+1)/(2n)) + 1/2 int beta |Tu|^2 - f(u).
 
@@ -66,6 +70,12 @@ class StokesOracle:
         self.beta = np.zeros(mesh.n_bface) if beta is None else np.asarray(beta, dtype=np.float64)
         self.body = np.asarray(body, dtype=np.float64)
         self.pmask = 1.0 - mesh.dmask.astype(np.float64)          # [3, n_nodes]
+        # nodal frames: Qn[n] with the local axes as columns (identity for nodes without one)
+        fnodes = getattr(mesh, "frame_nodes", None)
+        self.Qn = None
+        if fnodes is not None and len(fnodes):
+            self.Qn = np.tile(np.eye(3), (mesh.n_nodes, 1, 1))
+            self.Qn[np.asarray(fnodes)] = np.asarray(mesh.frames, dtype=np.float64).reshape(-1, 3, 3)
         E = self.elems.shape[0]
 
         self.R = build_restriction(mesh, ref, self.elems)          # [E*S, n_nodes]
@@ -101,18 +111,26 @@ class StokesOracle:
         self._K = None
 
     # ------------------------------------------------------------------ helpers
+    def to_cartesian(self, v):
+        """Q v: node vectors [3, n_nodes] from local to Cartesian components."""
+        return v if self.Qn is None else np.einsum("nij,jn->in", self.Qn, v)
+
+    def to_local(self, v):
+        """Q^T v: node vectors [3, n_nodes] from Cartesian to local components."""
+        return v if self.Qn is None else np.einsum("nji,jn->in", self.Qn, v)
+
     def gather(self, v_u):
-        """R_e (P v) for every element of the subset: [E, S, 3]."""
-        return (self.R @ (self.pmask * v_u).T).reshape(self.elems.shape[0], self.S, 3)
+        """R_e Q (P v) for every element of the subset: [E, S, 3]."""
+        return (self.R @ self.to_cartesian(self.pmask * v_u).T).reshape(self.elems.shape[0], self.S, 3)
 
     def _tangential(self, v):
         """T v = v - n (n.v) at face quadrature points."""
         return v - self.fn * np.einsum("fgc,fgc->fg", self.fn, v)[..., None]
 
     def scatter(self, r_e):
-        """sum_e R_e^T r_e for r_e [E, 3, S] -> [3, n_nodes]."""
+        """Q^T sum_e R_e^T r_e for r_e [E, 3, S] -> [3, n_nodes] (local components)."""
         out = np.stack([self.R.T @ r_e[:, c, :].reshape(-1) for c in range(3)])
-        return out
+        return self.to_local(out)
 
     # ------------------------------------------------------------------ state
     def set_state(self, u, p):
@@ -193,14 +211,22 @@ class StokesOracle:
         return A, Bm.reshape(E, self.ref.n_p, 3 * S)
 
     def _R3(self):
-        """Restriction on velocity dofs: rows (e, c, s) -> global c*n_nodes + node."""
+        """Restriction on velocity dofs, R_e Q: rows (e, c, s) -> global c*n_nodes + node (local components)."""
         R = self.R.tocoo()
         E, S, N = self.elems.shape[0], self.S, self.mesh.n_nodes
         e, s = R.row // S, R.row % S
         rows = np.concatenate([e * 3 * S + c * S + s for c in range(3)])
         cols = np.concatenate([c * N + R.col for c in range(3)])
         vals = np.concatenate([R.data] * 3)
-        return sp.csr_matrix((vals, (rows, cols)), shape=(E * 3 * S, 3 * N))
+        R3 = sp.csr_matrix((vals, (rows, cols)), shape=(E * 3 * S, 3 * N))
+        if self.Qn is None:
+            return R3
+        # block-diagonal change of variables: Cartesian (c, n) <- local (d, n), weight Q_n[c, d]
+        n = np.arange(N)
+        qr = np.concatenate([c * N + n for c in range(3) for d in range(3)])
+        qc = np.concatenate([d * N + n for c in range(3) for d in range(3)])
+        qv = np.concatenate([self.Qn[:, c, d] for c in range(3) for d in range(3)])
+        return R3 @ sp.csr_matrix((qv, (qr, qc)), shape=(3 * N, 3 * N))
 
     def jacobian(self, chunk=128):
         """Assembled J_c = P K P + (I - P) of shape [n_dof, n_dof] (CSR), velocity dofs first."""

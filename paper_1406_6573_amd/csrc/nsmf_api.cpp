@@ -55,6 +55,9 @@ struct nsmf_ctx {
   DevBuf<double> tabs;                // TabSet<P> of the mesh's degree
   DevBuf<double> geo_el64, geo_qp64, face64;
   DevBuf<float> geo_el32, geo_qp32, face32;
+  DevBuf<int32_t> rot_of;             // element -> row of its bottom-slot frames, -1 (nodal frames)
+  DevBuf<double> rot64;
+  DevBuf<float> rot32;
   // params
   bool have_params = false;
   nsmf_params prm;
@@ -93,6 +96,7 @@ struct nsmf_ctx {
     m.en = en.p;
     m.cmask = cmask.p;
     m.bface_of = bface_of.p;
+    m.rot_of = rot_of.p;
     m.pos = pos.p;
     m.spos = spos.p;
     m.sslot = sslot.p;
@@ -102,11 +106,12 @@ struct nsmf_ctx {
     m.nblocks = nblocks;
     return m;
   }
-  GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p}; }
-  GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p}; }
+  GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p, rot64.p}; }
+  GeoView<float> geo32() const { return GeoView<float>{geo_el32.p, geo_qp32.p, face32.p, rot32.p}; }
   void free_mesh() {
     en.free(); cmask.free(); bface_of.free(); inc_ptr.free(); pos.free(); spos.free(); sslot.free(); dmask.free(); ev.free(); tabs.free();
     geo_el64.free(); geo_qp64.free(); face64.free(); geo_el32.free(); geo_qp32.free(); face32.free();
+    rot_of.free(); rot64.free(); rot32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
     line_ptr.free(); line_node.free(); lptr.free(); lslot.free(); lbuf.free(); lfac64.free(); lfac32.free();
@@ -188,6 +193,30 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   }
   for (int64_t e = 0; e < n_el; ++e)
     if (m->cmask[e] >> 21) return ctx->fail(NSMF_EMESH, "cmask has bits above 20");
+  // ---- nodal frames: orthonormal, each node once, named only by bottom slots (z = 0)
+  std::vector<int32_t> frame_row;
+  if (m->n_frames < 0 || (m->n_frames > 0 && (!m->frame_nodes || !m->frames)))
+    return ctx->fail(NSMF_EINVAL, "n_frames < 0 or NULL frame arrays");
+  if (m->n_frames > 0) {
+    frame_row.assign((size_t)N, -1);
+    for (int64_t f = 0; f < m->n_frames; ++f) {
+      const int32_t id = m->frame_nodes[f];
+      if (id < 0 || id >= N) return ctx->fail(NSMF_EMESH, "frame_nodes entry out of range");
+      if (frame_row[id] >= 0) return ctx->fail(NSMF_EMESH, "node listed twice in frame_nodes");
+      frame_row[id] = (int32_t)f;
+      const double *Q = m->frames + 9 * f;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const double d = Q[a] * Q[b] + Q[3 + a] * Q[3 + b] + Q[6 + a] * Q[6 + b];   // (Q^T Q)_ab
+          if (!(std::fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-12)) return ctx->fail(NSMF_EMESH, "frame not orthonormal");
+        }
+    }
+    for (int64_t i = 0; i < n_el * P3; ++i)
+      if (frame_row[words[i] & NODE_MASK] >= 0) {
+        if ((i % P3) / P2 != 0) return ctx->fail(NSMF_EMESH, "node with a frame in a slot above the bottom");
+        words[i] |= ROT_BIT;
+      }
+  }
   std::vector<int32_t> bof((size_t)n_el, -1);
   for (int64_t f = 0; f < NB; ++f) {
     const int32_t e = m->bface_elem[f];
@@ -327,6 +356,34 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->cmask.p, m->cmask, n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->bface_of.p, bof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->dmask.p, dm.data(), 3 * N, hipMemcpyHostToDevice, s), "copy");
+  if (m->n_frames > 0) {
+    // per element with a framed bottom slot: the frames of its P^2 bottom slots (identity where the
+    // slot's node has none), [row][9][P^2]
+    std::vector<int32_t> rof((size_t)n_el, -1);
+    int64_t nrow = 0;
+    for (int64_t e = 0; e < n_el; ++e)
+      for (int t = 0; t < P2; ++t)
+        if (words[e * P3 + t] & ROT_BIT) {
+          rof[e] = (int32_t)nrow++;
+          break;
+        }
+    std::vector<double> rh((size_t)nrow * 9 * P2);
+    for (int64_t e = 0; e < n_el; ++e) {
+      if (rof[e] < 0) continue;
+      for (int t = 0; t < P2; ++t) {
+        const int32_t f = frame_row[words[e * P3 + t] & NODE_MASK];
+        for (int q = 0; q < 9; ++q)
+          rh[((size_t)rof[e] * 9 + q) * P2 + t] = f >= 0 ? m->frames[9 * (size_t)f + q] : (q % 4 == 0 ? 1.0 : 0.0);
+      }
+    }
+    NSMF_TRY(ctx, ctx->rot_of.alloc(n_el), "hipMalloc");
+    NSMF_TRY(ctx, ctx->rot64.alloc(rh.size()), "hipMalloc");
+    NSMF_TRY(ctx, ctx->rot32.alloc(rh.size()), "hipMalloc");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->rot_of.p, rof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->rot64.p, rh.data(), rh.size() * 8, hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, launch_d2f(s, ctx->rot64.p, ctx->rot32.p, (int64_t)rh.size()), "convert");
+    NSMF_TRY(ctx, hipStreamSynchronize(s), "frames");
+  }
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->inc_ptr.p, iptr.data(), iptr.size() * 4, hipMemcpyHostToDevice, s), "copy");
   if (sorted_store) {
     NSMF_TRY(ctx, hipMemcpyAsync(ctx->spos.p, spos.data(), spos.size() * 4, hipMemcpyHostToDevice, s), "copy");

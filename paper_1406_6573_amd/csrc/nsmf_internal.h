@@ -13,6 +13,7 @@ enum GeoKind { GEO_AFFINE = 0, GEO_COLUMN = 1 };
 // Dirichlet mask of components x, y, z of that node.
 constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;
 constexpr int MASK_SHIFT = 28;
+constexpr uint32_t ROT_BIT = 1u << 31;   // the slot's node has its unknowns in a local frame
 
 // Largest number of simultaneous dot products of nsmf_vec_dots (Krylov basis size + 1).
 constexpr int MAX_DOTS = 64;
@@ -81,6 +82,7 @@ struct MeshView {
   const uint32_t *en;        // [n_el][P^3] node word (id | mask bits)
   const uint32_t *cmask;     // [n_el]
   const int32_t *bface_of;   // [n_el] basal face id or -1
+  const int32_t *rot_of;     // [n_el] row of the element's bottom-slot frames in GeoView::rot, or -1
   // entries of the element slots in the node-ordered element vector.  P = 4: pos[e][a] per slot.
   // P = 3, 5: per block, the entries of its slots in ascending order (spos, -1 = padding) with the
   // slot's index in the block's LDS staging order (sslot), [nblocks][store_slots]
@@ -95,6 +97,8 @@ template <typename T> struct GeoView {
   const T *el;     // AFFINE: [n_el][4] (1/J00, 1/J11, 1/J22, detJ); COLUMN: [n_el][2] (1/J00, 1/J11)
   const T *qp;     // COLUMN: [nblocks][4][P][NT] (dzeta/dx, dzeta/dy, dzeta/dz, w detJ)
   const T *face;   // [n_bface][4][P*P] (w |S|, n_x, n_y, n_z) at the face Gauss points
+  const T *rot;    // [n_rot][9][P*P] local frame Q (row-major) of the node in each bottom slot of the
+                   // elements with a framed node (MeshView::rot_of), or null
 };
 
 // Launchers (defined in nsmf_kernels.hip).  Return hipError_t of the launch.

@@ -647,6 +647,32 @@ __device__ __forceinline__ void gather(const uint32_t *en_e, const T *x, int64_t
   gather_words<T, P>(nw, x, N, act, use_mask, v);
 }
 
+// Nodal frames (u . n = 0 on a curved base, eq. (robin)): a node with a local frame Q holds
+// u_hat with u = Q u_hat.  Such nodes are basal and occur only in bottom slots (z = 0): of basal
+// elements, and as parents in hanging slots of the elements above them.  Their frames are stored
+// per element (row rot_of[e]) and bottom slot.  frame_in turns the gathered local values of the
+// bottom slot into Cartesian ones; frame_out applies Q^T to the slot's result.
+template <typename T, int P>
+__device__ __forceinline__ void frame_load(const T *__restrict__ rot, int row, int t, T (&Q)[9]) {
+  constexpr int P2 = P * P;
+#pragma unroll
+  for (int r = 0; r < 9; ++r) Q[r] = rot[((size_t)row * 9 + r) * P2 + t];
+}
+template <typename T, int P>
+__device__ __forceinline__ void frame_in(T (&v)[3][P], const T (&Q)[9]) {
+  const T a = v[0][0], b = v[1][0], c = v[2][0];
+  v[0][0] = Q[0] * a + Q[1] * b + Q[2] * c;
+  v[1][0] = Q[3] * a + Q[4] * b + Q[5] * c;
+  v[2][0] = Q[6] * a + Q[7] * b + Q[8] * c;
+}
+template <typename T, int P>
+__device__ __forceinline__ void frame_out(T (&y)[3][P], const T (&Q)[9]) {
+  const T a = y[0][0], b = y[1][0], c = y[2][0];
+  y[0][0] = Q[0] * a + Q[3] * b + Q[6] * c;
+  y[1][0] = Q[1] * a + Q[4] * b + Q[7] * c;
+  y[2][0] = Q[2] * a + Q[5] * b + Q[8] * c;
+}
+
 // Element-vector store in node order.  The result of element slot (e, a) for component c goes
 // to ev[c * n_inc + pos], pos being the slot's entry in its node's contiguous segment (built at
 // upload).  Where two vertically adjacent elements of the block share a z-face, the lower
@@ -751,6 +777,12 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
   }
   T v[3][P];
   gather_words<T, P>(nw, xu, N, act, true, v);
+  const bool rot = act && (nw[0] & ROT_BIT);
+  if (rot) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_in<T, P>(v, Q);
+  }
   // geometry and pressure coefficients are needed only after the forward sweeps; requesting them
   // here hides their latency behind the sweeps (per-point geometry of column-mapped elements)
   QpGeo<T, P, GEO> g;
@@ -860,6 +892,11 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
     }
   }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  if (rot) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_out<T, P>(y, Q);
+  }
   evec_store<T, P>(yu, m, lb, e, smem, els, t, act, y);
 }
 
@@ -886,6 +923,11 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
   T v[3][P];
   uint32_t nw[P];
   gather<T, P>(m.en + e * P3, u, N, t, act, true, v, nw);
+  if (act && (nw[0] & ROT_BIT)) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_in<T, P>(v, Q);
+  }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
   T gr[3][3][P];
@@ -1026,6 +1068,11 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
       for (int c = 0; c < 3; ++c) y[c][0] += out[c];
   }
   if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  if (act && (nw[0] & ROT_BIT)) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_out<T, P>(y, Q);
+  }
   evec_store<T, P>(ru, m, lb, e, smem, els, t, act, y);
 }
 
@@ -1054,14 +1101,17 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   const uint32_t cm = act ? m.cmask[e] : 0u;
   uint32_t nw[P];
   load_words<P>(m.en + e * P3, t, act, nw);
-  T y[3][P];
+  T y[3][P], yo[3][P];   // yo: off-diagonal entries (xy, xz, yz) of the slot's 3x3 block
   T part[NP];
 #pragma unroll
   for (int mm = 0; mm < NP; ++mm) part[mm] = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int z = 0; z < P; ++z) y[c][z] = 0;
+    for (int z = 0; z < P; ++z) y[c][z] = yo[c][z] = 0;
+  // elements with framed bottom slots: the whole 3x3 blocks, so that a node in a local frame Q
+  // gets q_c^T (sum_a R[a, n]^2 F_aa) q_c
+  const bool offd = act && gv.rot != nullptr && m.rot_of[e] >= 0;
   if (act) {
     const int i = t % P, j = t / P;          // slot (i, j, z) of the z-line
     double jx = 0, jy = 0, jz = 0, detJ = 0;
@@ -1112,6 +1162,11 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
           const double SG[3] = {S[0] * G[0] + S[3] * G[1] + S[4] * G[2], S[3] * G[0] + S[1] * G[1] + S[5] * G[2],
                                 S[4] * G[0] + S[5] * G[1] + S[2] * G[2]};
           for (int c = 0; c < 3; ++c) y[c][z] += 0.5 * mu * (g2 + G[c] * G[c]) - ka * SG[c] * SG[c];
+          if (offd) {
+            yo[0][z] += 0.5 * mu * G[0] * G[1] - ka * SG[0] * SG[1];
+            yo[1][z] += 0.5 * mu * G[0] * G[2] - ka * SG[0] * SG[2];
+            yo[2][z] += 0.5 * mu * G[1] * G[2] - ka * SG[1] * SG[2];
+          }
         }
       }
     }
@@ -1125,12 +1180,30 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
           const double nc = fg[(1 + c) * P2 + fq];
           y[c][0] += bw * (1.0 - nc * nc);
         }
+        if (offd) {
+          const double n0 = fg[P2 + fq], n1 = fg[2 * P2 + fq], n2 = fg[3 * P2 + fq];
+          yo[0][0] -= bw * n0 * n1;
+          yo[1][0] -= bw * n0 * n2;
+          yo[2][0] -= bw * n1 * n2;
+        }
       }
     }
   }
   // lumped -M(1/mu): thread t holds the points of x-line t, reduce over the element's threads
   pressure_reduce<T, P, NP>(part, w, t, act, act ? dp + e * NP : nullptr);
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb2, t, act);
+  const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
+  if (hang) hang_bwd<T, P>(y, cm, w, tb2, t, act);
+  if (hang && __syncthreads_or(offd)) hang_bwd<T, P>(yo, cm, w, tb2, t, act);
+  if (act && (nw[0] & ROT_BIT)) {
+    double Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    const double d00 = y[0][0], d11 = y[1][0], d22 = y[2][0], d01 = yo[0][0], d02 = yo[1][0], d12 = yo[2][0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double a = Q[c], b = Q[3 + c], g = Q[6 + c];   // column c of Q
+      y[c][0] = a * a * d00 + b * b * d11 + g * g * d22 + 2.0 * (a * b * d01 + a * g * d02 + b * g * d12);
+    }
+  }
   evec_store<T, P>(ev, m, lb, e, smem, els, t, act, y);
 }
 
@@ -1234,6 +1307,90 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
       for (int c = 0; c < 3; ++c) {
         const double nc = fg[(1 + c) * P2 + fq];
         rows[c][0][0] += bw * (1.0 - nc * nc);
+      }
+    }
+  }
+  // bottom slot in a local frame Q (basal node, u . n = 0): its rows couple the local component c
+  // with component c of the slots above, F[(c, 0), (c, zb)] = sum_c' Q[c'][c] A[(c', 0), (c, zb)],
+  // and its diagonal is q_c^T A[(., 0), (., 0)] q_c, from the cross-component entries
+  // A[(c', 0), (c, zb)] = sum over points of mu'/2 (delta_c'c grad phi_0 . grad phi_zb +
+  // d_c phi_0 d_c' phi_zb) - kappa (Sigma0 grad phi_0)_c' (Sigma0 grad phi_zb)_c (+ basal term)
+  if (lo == 0 && (m.en[e * P3 + t] & ROT_BIT)) {
+    double M[3][3][P];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int z = 0; z < P; ++z) M[a][c][z] = 0;
+    for (int tq = 0; tq < P2; ++tq) {
+      const int qy = tq % P, qz = tq / P, tidq = el * P2 + tq;
+      for (int qx = 0; qx < P; ++qx) {
+        const double mu = st[qp_at<P, NT, NSTATE>(lb, 0, tidq, qx)];
+        const double ka = st[qp_at<P, NT, NSTATE>(lb, 1, tidq, qx)];
+        double S[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
+        double a = 0, b = 0, cc = jz;
+        if (GEO != GEO_AFFINE) {
+          a = gv.qp[qp_at<P, NT, 4>(lb, 0, tidq, qx)];
+          b = gv.qp[qp_at<P, NT, 4>(lb, 1, tidq, qx)];
+          cc = gv.qp[qp_at<P, NT, 4>(lb, 2, tidq, qx)];
+        }
+        double G[P][3], SG[P][3];
+#pragma unroll
+        for (int z = 0; z < P; ++z) {
+          const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
+          const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
+          const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
+          if (GEO == GEO_AFFINE) {
+            G[z][0] = gr0 * jx; G[z][1] = gr1 * jy; G[z][2] = gr2 * jz;
+          } else {
+            G[z][0] = gr0 * jx + gr2 * a; G[z][1] = gr1 * jy + gr2 * b; G[z][2] = gr2 * cc;
+          }
+          SG[z][0] = S[0] * G[z][0] + S[3] * G[z][1] + S[4] * G[z][2];
+          SG[z][1] = S[3] * G[z][0] + S[1] * G[z][1] + S[5] * G[z][2];
+          SG[z][2] = S[4] * G[z][0] + S[5] * G[z][1] + S[2] * G[z][2];
+        }
+#pragma unroll
+        for (int zb = 0; zb < P; ++zb) {
+          const double g = G[0][0] * G[zb][0] + G[0][1] * G[zb][1] + G[0][2] * G[zb][2];
+#pragma unroll
+          for (int ap = 0; ap < 3; ++ap)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              M[ap][c][zb] += 0.5 * mu * ((ap == c ? g : 0.0) + G[0][c] * G[zb][ap]) - ka * SG[0][ap] * SG[zb][c];
+        }
+      }
+    }
+    if (fid >= 0) {
+      const double *fg = gv.face + (size_t)fid * NFACEGEO * P2;
+      for (int fq = 0; fq < P2; ++fq) {
+        const double phi = tb.B[fq % P][i] * tb.B[fq / P][j];
+        const double bw = beta[fid] * fg[fq] * phi * phi;
+        const double nv[3] = {fg[P2 + fq], fg[2 * P2 + fq], fg[3 * P2 + fq]};
+#pragma unroll
+        for (int ap = 0; ap < 3; ++ap)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) M[ap][c][0] += bw * ((ap == c ? 1.0 : 0.0) - nv[ap] * nv[c]);
+      }
+    }
+    double Q[9];
+    frame_load<double, P>(gv.rot, m.rot_of[e], t, Q);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double dg = 0;
+#pragma unroll
+      for (int ap = 0; ap < 3; ++ap)
+#pragma unroll
+        for (int bp = 0; bp < 3; ++bp) dg += Q[3 * ap + c] * Q[3 * bp + c] * M[ap][bp][0];
+      rows[c][0][0] = dg;
+#pragma unroll
+      for (int d = 1; d < P; ++d) {
+        double s = 0;
+#pragma unroll
+        for (int ap = 0; ap < 3; ++ap) s += Q[3 * ap + c] * M[ap][c][d];
+        rows[c][0][d] = s;
       }
     }
   }

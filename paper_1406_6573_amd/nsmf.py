@@ -39,7 +39,8 @@ class _Mesh(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("n_el", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
                 ("n_bface", ctypes.c_int64), ("elem_nodes", ctypes.c_void_p), ("cmask", ctypes.c_void_p),
                 ("coords", ctypes.c_void_p), ("bface_elem", ctypes.c_void_p), ("dmask", ctypes.c_void_p),
-                ("pspace", ctypes.c_int32), ("period", ctypes.c_double * 3)]
+                ("pspace", ctypes.c_int32), ("period", ctypes.c_double * 3), ("n_frames", ctypes.c_int64),
+                ("frame_nodes", ctypes.c_void_p), ("frames", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -141,17 +142,25 @@ class Engine:
     # -------------------------------------------------------------- API
     def upload_mesh(self, mesh):
         """Copy a mesh (any object with k, elem_nodes, cmask, coords, bface_elem, dmask arrays, an
-        optional pressure-space label pspace: "P" = P_{k-1} (default), "Q" = Q_{k-2}, and an optional
-        period (x, y, z) of periodic axes, 0 where not periodic)."""
+        optional pressure-space label pspace: "P" = P_{k-1} (default), "Q" = Q_{k-2}, an optional
+        period (x, y, z) of periodic axes, 0 where not periodic, and optional nodal frames:
+        frame_nodes [n] and frames [n, 3, 3] (local axes as columns, unknowns u = Q u_hat)."""
         en = np.ascontiguousarray(mesh.elem_nodes, dtype=np.int32)
         cm = np.ascontiguousarray(mesh.cmask, dtype=np.uint32)
         X = np.ascontiguousarray(mesh.coords, dtype=np.float64)
         bf = np.ascontiguousarray(mesh.bface_elem, dtype=np.int32)
         dm = None if mesh.dmask is None else np.ascontiguousarray(mesh.dmask, dtype=np.uint8)
+        fn = getattr(mesh, "frame_nodes", None)
+        fn = None if fn is None or len(fn) == 0 else np.ascontiguousarray(fn, dtype=np.int32)
+        fq = None if fn is None else np.ascontiguousarray(mesh.frames, dtype=np.float64).reshape(-1, 3, 3)
+        if fq is not None and fq.shape[0] != fn.shape[0]:
+            raise ValueError("frames must be [len(frame_nodes), 3, 3]")
         s = _Mesh(int(mesh.k), en.shape[0], X.shape[1], bf.shape[0], en.ctypes.data, cm.ctypes.data,
                   X.ctypes.data, bf.ctypes.data if bf.size else None, None if dm is None else dm.ctypes.data,
                   {"P": 0, "Q": 1}[getattr(mesh, "pspace", "P")],
-                  (ctypes.c_double * 3)(*[float(v) for v in getattr(mesh, "period", (0.0, 0.0, 0.0))]))
+                  (ctypes.c_double * 3)(*[float(v) for v in getattr(mesh, "period", (0.0, 0.0, 0.0))]),
+                  0 if fn is None else fn.shape[0], None if fn is None else fn.ctypes.data,
+                  None if fq is None else fq.ctypes.data)
         self._check(self.lib.nsmf_upload_mesh(self.h, ctypes.byref(s)))
         self.k = int(mesh.k)
         self.sizes = self.query()

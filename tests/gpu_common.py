@@ -14,13 +14,14 @@ def terrain_geometry(nx, ny, nz, L):
 
 
 def small_case(k, mapped=False, frac=0.3, mask=True, seed=0, nx=4, ny=3, nz=2, L=40.0, body=(0.0, 0.0, 0.0),
-               pspace="P", refine_from=0, periodic=(False, False)):
+               pspace="P", refine_from=0, periodic=(False, False), frames=False):
     """A seeded case with hanging faces and edges: mesh, parameters, state, directions."""
     rng = np.random.default_rng(1000 + 17 * k + seed)
     refined = random_refined_columns(nx, ny, frac, rng)
     geo = terrain_geometry(nx, ny, nz, L) if mapped else None
     mesh = column_mesh(k, nx, ny, nz, refined=refined, extent=(L, L * ny / nx, 1.0), geometry=geo,
-                       base_normal_dirichlet=mask, pspace=pspace, refine_from=refine_from, periodic=periodic)
+                       base_normal_dirichlet=mask and not frames, pspace=pspace, refine_from=refine_from,
+                       periodic=periodic, base_frames=frames)
     case = dict(mesh=mesh, n=3.0, eps=1e-10, B0=0.5, body=body,
                 logA=rng.normal(0, 0.5, mesh.n_el), beta=np.exp(rng.normal(0, 1, mesh.n_bface)))
     x, y, z = mesh.coords

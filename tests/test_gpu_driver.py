@@ -26,12 +26,22 @@ def setup(torch, case):
     return eng, t
 
 
-VARIANTS = {"": {}, "zface": dict(refine_from=1), "periodic": dict(periodic=(True, True), frac=0.4)}
+VARIANTS = {"": {}, "zface": dict(refine_from=1), "periodic": dict(periodic=(True, True), frac=0.4),
+            "frames": dict(frames=True, frac=0.4)}
+
+
+def node_frames(m):
+    """Per-node frame Q_n [n_nodes, 3, 3] (identity for nodes without one)."""
+    Qn = np.tile(np.eye(3), (m.n_nodes, 1, 1))
+    if len(m.frame_nodes):
+        Qn[m.frame_nodes] = m.frames
+    return Qn
 
 
 @pytest.mark.parametrize("k,mapped,pspace,variant", [(2, False, "P", ""), (3, True, "P", ""), (4, False, "P", ""),
                                                      (3, True, "Q", ""), (4, False, "Q", ""), (2, True, "P", "zface"),
-                                                     (4, False, "P", "zface"), (3, True, "P", "periodic")])
+                                                     (4, False, "P", "zface"), (3, True, "P", "periodic"),
+                                                     (2, True, "P", "frames"), (4, True, "Q", "frames")])
 def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, variant):
     """d_u = sum_e sum_a R_e[a, n]^2 F_e[aa] (exact diagonal of F on conforming parts), 1 on masked
     rows; d_p = -sum_q w detJ psi_m^2 / mu."""
@@ -45,9 +55,15 @@ def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, variant):
     o.set_state(case["u"], case["p"])
     A, _ = o.element_matrices()
     S = o.S
-    dA = np.stack([np.diagonal(A, axis1=1, axis2=2)[:, c * S:(c + 1) * S].reshape(-1) for c in range(3)])
-    R2 = o.R.multiply(o.R)
-    ref_u = np.stack([R2.T @ dA[c] for c in range(3)])
+    # 3x3 slot blocks A_e[(c, a), (d, a)], summed with squared restriction weights per node, then
+    # seen in the node's frame: d_c(n) = q_c(n)^T (sum_a R[a, n]^2 A_aa) q_c(n)
+    idx = np.arange(S)
+    blk = np.stack([np.stack([A[:, c * S + idx, d * S + idx].reshape(-1) for d in range(3)], -1)
+                    for c in range(3)], -2)                       # [E*S, 3, 3]
+    R2 = o.R.multiply(o.R).T.tocsr()
+    Bn = np.stack([np.stack([R2 @ blk[:, c, d] for d in range(3)], -1) for c in range(3)], -2)   # [N, 3, 3]
+    Qn = node_frames(m)
+    ref_u = np.einsum("nca,ncd,nda->an", Qn, Bn, Qn)
     msk = m.dmask.astype(bool)
     ref_u[msk] = 1.0
     ref_p = -np.einsum("eq,qm->em", o.W / o.mu, o.ref.Psi ** 2)
@@ -243,7 +259,7 @@ def dependent_slots(cm, P):
 
 
 @pytest.mark.parametrize("k,mapped,variant", [(2, True, "zface"), (3, False, "zface"), (4, True, "zface"),
-                                             (3, True, "periodic")])
+                                             (3, True, "periodic"), (2, True, "frames"), (4, True, "frames")])
 def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
     """Lateral and -z hanging faces: each line block is the sum, over the elements, of the oracle's
     element matrix A_e restricted to the independent slots of one element z-line (couplings through
@@ -258,6 +274,7 @@ def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
     o.set_state(case["u"], case["p"])
     A, _ = o.element_matrices()
     S = P ** 3
+    Qn = node_frames(m)
     up, down = {}, {}
     blocks = [dict() for _ in range(3)]
     for e in range(m.n_el):
@@ -268,11 +285,13 @@ def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
                 na, nb = int(m.elem_nodes[e, sa]), int(m.elem_nodes[e, sb])
                 assert up.get(na, nb) == nb and down.get(nb, na) == na
                 up[na], down[nb] = nb, na
-            for c in range(3):
-                for sa in run:
-                    for sb in run:
-                        key = (int(m.elem_nodes[e, sa]), int(m.elem_nodes[e, sb]))
-                        blocks[c][key] = blocks[c].get(key, 0.0) + A[e, c * S + sa, c * S + sb]
+            for sa in run:
+                for sb in run:
+                    key = (int(m.elem_nodes[e, sa]), int(m.elem_nodes[e, sb]))
+                    A3 = A[e][np.ix_([sa, S + sa, 2 * S + sa], [sb, S + sb, 2 * S + sb])]
+                    F = Qn[key[0]].T @ A3 @ Qn[key[1]]           # in the nodes' frames
+                    for c in range(3):
+                        blocks[c][key] = blocks[c].get(key, 0.0) + F[c, c]
     lines = []
     for n in range(N):
         if n in down:
@@ -306,7 +325,8 @@ def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
     eng.close()
 
 
-@pytest.mark.parametrize("precond,variant", [("jacobi", "zface"), ("line", "zface"), ("line", "periodic")])
+@pytest.mark.parametrize("precond,variant", [("jacobi", "zface"), ("line", "zface"), ("line", "periodic"),
+                                             ("line", "frames")])
 def test_newton_step_variants(torch_cuda, precond, variant):
     """One Newton step on a mapped mesh with -z hanging faces, or periodic in x and y: the reported
     linear reduction is the true one (oracle Jacobian) and the next residual equals the oracle

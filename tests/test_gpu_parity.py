@@ -154,6 +154,21 @@ def test_periodic(torch_cuda, k, mapped):
     check_case(torch_cuda, case, f"periodic k={k} mapped={mapped}")
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_nodal_frames(torch_cuda, k):
+    """Curved (terrain) base with u . n = 0 by nodal frames: basal nodes hold local components
+    (tangent, tangent, normal), the normal one masked; hanging faces reach framed parents."""
+    case = small_case(k, mapped=True, frac=0.4, frames=True, body=(0.0, 0.1, -1.0))
+    m = case["mesh"]
+    assert m.frame_nodes.shape[0] > 0 and not np.allclose(m.frames[:, :, 2], [0.0, 0.0, 1.0])
+    check_case(torch_cuda, case, f"nodal frames k={k}")
+
+
+def test_nodal_frames_zface_qspace(torch_cuda):
+    case = small_case(3, mapped=True, frac=0.4, frames=True, refine_from=1, pspace="Q")
+    check_case(torch_cuda, case, "nodal frames, z-face hanging, k=3 Q_(k-2) pressure")
+
+
 def test_zface_hanging_qspace(torch_cuda):
     case = small_case(3, mapped=True, frac=0.4, refine_from=1, pspace="Q")
     check_case(torch_cuda, case, "z-face hanging k=3 mapped Q_(k-2) pressure")

@@ -230,6 +230,76 @@ def test_periodic_equals_identified_assembly(k):
     assert np.max(np.abs(D.data), initial=0.0) < 1e-12 * np.abs(Kn.data).max()
 
 
+def _random_frames(rng, n):
+    q, _ = np.linalg.qr(rng.normal(size=(n, 3, 3)))
+    return q
+
+
+def _frames_block(mesh, Qn):
+    """Block-diagonal Q on velocity dofs (c*N + node) extended by the identity on pressures."""
+    N = mesh.n_nodes
+    Qb = sp.lil_matrix((3 * N, 3 * N))
+    for c in range(3):
+        for d in range(3):
+            Qb[c * N + np.arange(N), d * N + np.arange(N)] = Qn[:, c, d]
+    return sp.block_diag([Qb.tocsr(), sp.eye(mesh.n_el * mesh.n_p)], format="csr")
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_frames_change_variables(k):
+    """Random orthonormal frames on the basal nodes, no mask: the framed operator is Q^T K Q and the
+    framed residual Q^T r(Q u_hat) for the unframed K and r (catches Q and Q^T swapped in the
+    gather or in the scatter)."""
+    mesh = hanging_mesh(k, nx=3, ny=3, frac=0.35, geometry=terrain(3, 3, 2, 40.0))
+    rng = np.random.default_rng(9)
+    base = np.nonzero(mesh.node_logical[:, 2] == 0.0)[0]
+    Qn = np.tile(np.eye(3), (mesh.n_nodes, 1, 1))
+    Qn[base] = _random_frames(rng, base.shape[0])
+    logA, beta = rng.normal(0, 0.5, mesh.n_el), np.exp(rng.normal(0, 1, mesh.n_bface))
+    uh = rng.uniform(-1, 1, (3, mesh.n_nodes))
+    p = rng.uniform(-1, 1, (mesh.n_el, mesh.n_p))
+    o = StokesOracle(mesh, 3.0, 1e-10, 0.5, logA, beta, body=(0.0, 0.1, -1.0))
+    o.set_state(np.einsum("nij,jn->in", Qn, uh), p)
+    mesh.frame_nodes, mesh.frames = base.astype(np.int32), Qn[base]
+    of = StokesOracle(mesh, 3.0, 1e-10, 0.5, logA, beta, body=(0.0, 0.1, -1.0))
+    of.set_state(uh, p)
+    Qb = _frames_block(mesh, Qn)
+    K, Kf = o.jacobian(), of.jacobian()
+    assert abs(Kf - Qb.T @ K @ Qb).max() < 1e-12 * abs(K).max()
+    r = np.concatenate([a.ravel() for a in o.residual()])
+    rf = np.concatenate([a.ravel() for a in of.residual()])
+    assert np.allclose(rf, Qb.T @ r, rtol=0, atol=1e-12 * np.abs(r).max())
+
+
+def test_frames_on_flat_base_match_component_mask():
+    """Flat base, frames with the normal e_z and tangents turned in the plane by a per-node angle,
+    normal component masked: the framed operator is Q~^T J_mask Q~, J_mask the operator with the
+    z component of the basal nodes masked (u_z = 0)."""
+    rng = np.random.default_rng(10)
+    ref = random_refined_columns(3, 3, 0.35, rng)
+    m0 = column_mesh(3, 3, 3, 2, refined=ref, extent=(30.0, 30.0, 1.0), base_normal_dirichlet=True)
+    mf = column_mesh(3, 3, 3, 2, refined=ref, extent=(30.0, 30.0, 1.0), base_frames=True)
+    assert np.array_equal(m0.dmask, mf.dmask)
+    ang = rng.uniform(0, 2 * np.pi, mf.frame_nodes.shape[0])
+    c, s = np.cos(ang), np.sin(ang)
+    Qf = np.zeros((ang.shape[0], 3, 3))
+    Qf[:, 0, 0], Qf[:, 0, 1], Qf[:, 1, 0], Qf[:, 1, 1], Qf[:, 2, 2] = c, -s, s, c, 1.0
+    assert np.allclose(mf.frames[:, :, 2], [0, 0, 1])
+    mf.frames = Qf
+    Qn = np.tile(np.eye(3), (mf.n_nodes, 1, 1))
+    Qn[mf.frame_nodes] = Qf
+    logA, beta = rng.normal(0, 0.5, m0.n_el), np.exp(rng.normal(0, 1, m0.n_bface))
+    u = rng.uniform(-1, 1, (3, m0.n_nodes))
+    p = rng.uniform(-1, 1, (m0.n_el, m0.n_p))
+    o0 = StokesOracle(m0, 3.0, 1e-10, 0.5, logA, beta)
+    o0.set_state(u, p)
+    of = StokesOracle(mf, 3.0, 1e-10, 0.5, logA, beta)
+    of.set_state(np.einsum("nji,jn->in", Qn, u), p)
+    Qb = _frames_block(mf, Qn)
+    K0, Kf = o0.jacobian(), of.jacobian()
+    assert abs(Kf - Qb.T @ K0 @ Qb).max() < 1e-12 * abs(K0).max()
+
+
 # ---------------------------------------------------------------- P1 rigid modes, P2 kernel of B
 @pytest.mark.parametrize("k,pspace", [(2, "P"), (3, "P"), (4, "P"), (3, "Q"), (4, "Q")])
 @pytest.mark.parametrize("mapped", [False, True])
