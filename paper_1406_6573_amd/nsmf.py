@@ -109,6 +109,7 @@ class Engine:
         self.sync_stream()
         self.k = None
         self.state_version = 0
+        self.linearization = "newton"
 
     # -------------------------------------------------------------- plumbing
     def _check(self, rc: int, h=-1):
@@ -195,6 +196,7 @@ class Engine:
         if kind not in codes:
             raise ValueError("linearization must be 'newton' or 'picard'")
         self._check(self.lib.nsmf_set_linearization(self.h, codes[kind]))
+        self.linearization = kind
         self.state_version += 1
 
     def set_state(self, u, p):

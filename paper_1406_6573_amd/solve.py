@@ -55,7 +55,8 @@ class NewtonKrylov:
             raise ValueError("restart must be at most 63")
         if precond not in ("jacobi", "line"):
             raise ValueError("precond must be 'jacobi' or 'line'")
-        engine.set_linearization(linearization)
+        if engine.linearization != linearization:         # switching discards the engine's state
+            engine.set_linearization(linearization)
         self.linearization = linearization
         self.eng, self.m, self.precision, self.refine, self.precond = engine, restart, precision, refine, precond
         self.triangular = triangular
