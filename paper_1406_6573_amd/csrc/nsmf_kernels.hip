@@ -67,43 +67,48 @@ template <int P> __device__ __forceinline__ bool zline_hanging(uint32_t cm, int 
 // Child-interval interpolation of a line (half h of the parent interval) and its transpose.
 // The upper half is the mirror image of the lower one, so h = 1 reverses the line, applies the
 // lower-half matrix and reverses the result: the table is indexed statically and stays in scalar
-// registers.  The half is a template argument in the line kernels, so that every register index
-// is static (a runtime-selected index into a register array compiles to select chains).
-template <typename T, int P, int H> __device__ __forceinline__ void interp_line_h(const Tab<T, P> &tb, T *v) {
-  T o[P];
+// registers.  The reversal selects between values read at static indices (a conditional between
+// two array elements would select their address, a runtime index into a register array, which
+// compiles to select chains over the whole array).
+template <typename T, int P> __device__ __forceinline__ void mirror_if(bool h, T *v) {
+#pragma unroll
+  for (int m = 0; m < P / 2; ++m) {
+    const T a = v[m], b = v[P - 1 - m];
+    v[m] = h ? b : a;
+    v[P - 1 - m] = h ? a : b;
+  }
+}
+template <typename T, int P> __device__ __forceinline__ void interp_line(const Tab<T, P> &tb, int h, T *v) {
+  T r[P], o[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) r[m] = v[m];
+  mirror_if<T, P>(h != 0, r);
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     T a = 0;
 #pragma unroll
-    for (int m = 0; m < P; ++m) a += tb.I[i][m] * v[H ? P - 1 - m : m];
+    for (int m = 0; m < P; ++m) a += tb.I[i][m] * r[m];
     o[i] = a;
   }
+  mirror_if<T, P>(h != 0, o);
 #pragma unroll
-  for (int i = 0; i < P; ++i) v[H ? P - 1 - i : i] = o[i];
+  for (int i = 0; i < P; ++i) v[i] = o[i];
 }
-template <typename T, int P, int H> __device__ __forceinline__ void interp_line_t_h(const Tab<T, P> &tb, T *v) {
-  T o[P];
+template <typename T, int P> __device__ __forceinline__ void interp_line_t(const Tab<T, P> &tb, int h, T *v) {
+  T r[P], o[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) r[i] = v[i];
+  mirror_if<T, P>(h != 0, r);
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     T a = 0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) a += tb.I[i][m] * v[H ? P - 1 - i : i];
+    for (int i = 0; i < P; ++i) a += tb.I[i][m] * r[i];
     o[m] = a;
   }
+  mirror_if<T, P>(h != 0, o);
 #pragma unroll
-  for (int m = 0; m < P; ++m) v[H ? P - 1 - m : m] = o[m];
-}
-template <typename T, int P> __device__ __forceinline__ void interp_line(const Tab<T, P> &tb, int h, T *v) {
-  if (h)
-    interp_line_h<T, P, 1>(tb, v);
-  else
-    interp_line_h<T, P, 0>(tb, v);
-}
-template <typename T, int P> __device__ __forceinline__ void interp_line_t(const Tab<T, P> &tb, int h, T *v) {
-  if (h)
-    interp_line_t_h<T, P, 1>(tb, v);
-  else
-    interp_line_t_h<T, P, 0>(tb, v);
+  for (int m = 0; m < P; ++m) v[m] = o[m];
 }
 
 // LDS strides chosen against bank conflicts (32 banks of 4 bytes): the z-plane stride SZ
