@@ -103,6 +103,23 @@ def test_mesh_validation(torch_cuda):
         s = _Mesh(2, en.shape[0], X.shape[1], bf.shape[0], en.ctypes.data, cm.ctypes.data, X.ctypes.data,
                   bf.ctypes.data if bf.size else None, None, 0, (ctypes.c_double * 3)(*per))
         assert eng.lib.nsmf_upload_mesh(eng.h, ctypes.byref(s)) == code
+    # nodal frames: n_frames < 0 -> EINVAL; a node listed twice, a frame that is not orthonormal,
+    # or a framed node named by a slot above the bottom -> EMESH
+    def frames_code(n, nodes, frames):
+        nd = np.ascontiguousarray(nodes, dtype=np.int32)
+        fr = np.ascontiguousarray(frames, dtype=np.float64)
+        s = _Mesh(2, en.shape[0], X.shape[1], bf.shape[0], en.ctypes.data, cm.ctypes.data, X.ctypes.data,
+                  bf.ctypes.data if bf.size else None, None, 0, (ctypes.c_double * 3)(0.0, 0.0, 0.0), n,
+                  nd.ctypes.data, fr.ctypes.data)
+        return eng.lib.nsmf_upload_mesh(eng.h, ctypes.byref(s))
+    base = np.nonzero(good.node_logical[:, 2] == 0.0)[0][:2]
+    top = np.nonzero(good.node_logical[:, 2] > 0.0)[0][:1]
+    eye = np.tile(np.eye(3), (2, 1, 1))
+    assert frames_code(-1, base, eye) == -1
+    assert frames_code(2, [base[0], base[0]], eye) == -3
+    assert frames_code(1, base[:1], 2.0 * eye[:1]) == -3
+    assert frames_code(1, top, eye[:1]) == -3
+    assert frames_code(2, base, eye) == 0
     # linearization kind out of range
     assert eng.lib.nsmf_set_linearization(eng.h, 2) == -1
     # the context is still usable
