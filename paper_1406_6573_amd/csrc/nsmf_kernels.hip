@@ -770,10 +770,10 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
   const int64_t N = m.n_nodes;
   // connectivity first (the gather of x waits on it), then the linearisation data of the thread's
   // P points: requested here so that its latency overlaps the gather and the forward sweeps,
-  // except in FP64 with P = 3, 5, where the extra live registers would cost occupancy (it is
-  // loaded just before the quadrature-point step there; P = 4 stays within 256 VGPRs, two
-  // wavefronts per SIMD either way).  The block's slice is always allocated, also for threads
-  // without an element.
+  // for P = 4 and for FP32 with P = 5.  Elsewhere it is loaded just before the quadrature-point
+  // step: in FP64 with P = 3, 5 the extra live registers would cost occupancy, and with FP32 and
+  // P = 3 the early request measured 4% slower.  The block's slice is always allocated, also for
+  // threads without an element.
   uint32_t nw[P];
   load_words<P>(m.en + e * P3, t, act, nw);
   const uint32_t cm = act ? m.cmask[e] : 0u;
@@ -783,7 +783,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
   using ST = std::conditional_t<kS32, float, double>;
   constexpr int NF = kS32 ? NSTATE32 : NSTATE;
   const ST *__restrict__ st = reinterpret_cast<const ST *>(st_);
-  constexpr bool kEarlyState = sizeof(ST) == 4 || P == 4;
+  constexpr bool kEarlyState = P == 4 || (P == 5 && sizeof(ST) == 4);
   ST stv[NF][P];
   if constexpr (kEarlyState) {
 #pragma unroll
