@@ -103,7 +103,7 @@ def run_newton(args, w, dev, n_newton=5, restart=50):
         eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
         u, p = t(w.u), t(w.p)
         nk = NewtonKrylov(eng, restart=restart, precision=prec, refine=1, precond=args.precond,
-                          triangular=not args.block_diagonal)
+                          triangular=not args.block_diagonal, linearization=args.linearization)
         st = nk.solve(u, p, n_newton=n_newton, lin_tol=1e-8, verbose=True)
         out[prec] = dict(seconds=st.seconds, newton_residuals=st.newton_residuals,
                          linear_reductions=st.linear_reductions, krylov_iterations=st.krylov_iterations,
@@ -114,11 +114,13 @@ def run_newton(args, w, dev, n_newton=5, restart=50):
     a, b = np.array(out["fp64"]["newton_residuals"]), np.array(out["mixed"]["newton_residuals"])
     pc = {"jacobi": "point-Jacobi", "line": "vertical-line-block"}[args.precond] + " velocity block, " + \
         ("block-diagonal" if args.block_diagonal else "block upper-triangular")
-    rec = {"metric": f"Newton-Krylov solve: 5 Newton steps x FGMRES(50), {pc}, FP64 vs mixed",
+    steps = "Newton" if args.linearization == "newton" else "Picard"
+    rec = {"metric": f"Newton-Krylov solve: 5 {steps} steps x FGMRES(50), {pc}, FP64 vs mixed",
            "value": out["fp64"]["seconds"] / out["mixed"]["seconds"], "unit": "speedup mixed vs fp64",
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": f"config{args.config}", "n_dof": m.n_dof, "n_el": m.n_el, "k": m.k,
-                      "preconditioner": args.precond, "triangular": not args.block_diagonal},
+                      "preconditioner": args.precond, "triangular": not args.block_diagonal,
+                      "linearization": args.linearization},
            "residual_reduction_fp64": float(a[-1] / a[0]), "residual_reduction_mixed": float(b[-1] / b[0]),
            "max_rel_diff_newton_residuals": float(np.max(np.abs(a - b) / a)), "fp64": out["fp64"],
            "mixed": out["mixed"]}
@@ -141,6 +143,8 @@ def main():
                     help="velocity block of the Newton driver's preconditioner (with --newton)")
     ap.add_argument("--block-diagonal", action="store_true",
                     help="block-diagonal instead of block upper-triangular preconditioner (with --newton)")
+    ap.add_argument("--linearization", choices=["newton", "picard"], default="newton",
+                    help="operator of the nonlinear steps (with --newton)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (reference for HBM counters)")
     args = ap.parse_args()
