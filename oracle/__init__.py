@@ -8,12 +8,16 @@ and it shares no code, tables or helpers with the engine.
 What it computes, by definition (no sum factorisation, no blocking):
 
 * reference tables: tensor Gauss-Lobatto Lagrange basis on Gauss points,
-  the mapped P_{k-1} pressure basis (Sec. 3.2.1-3.2.2);
+  the mapped P_{k-1} and the Gauss-point Q_{k-2} pressure bases
+  (Sec. 3.2.1-3.2.2, Sec. 6);
 * element restrictions R_e by point location in a coarse neighbour and
-  evaluation of its Lagrange basis (Sec. 3.2.1, figure "hanging");
+  evaluation of its Lagrange basis (Sec. 3.2.1, figure "hanging"), with
+  periodic lateral axes matched modulo the period (Sec. 4.3);
 * dense element residuals and Jacobians by full tensor quadrature of
-  eq. (weak) and eq. (newton) with the tensor of eq. (rank4) (Sec. 2.2-2.3);
-* the basal Robin term (eq. (robin), eq. (weak));
+  eq. (weak) and eq. (newton) with the tensor of eq. (rank4), or the
+  Picard operator (Sec. 2.2-2.3);
+* the basal Robin term and u.n = 0 by a component mask or by nodal frames
+  (eq. (robin), eq. (weak));
 * global assembly A = sum_e R_e^T A_e R_e (Sec. 3.2.1) with scipy.sparse;
 * the residual VJP and the energy functional of the appendix.
 
