@@ -11,7 +11,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-ROWS = {2: (150, 40), 3: (40, 12), 4: (120, 40), 5: (200, 60)}
+ROWS = {2: (400, 100), 3: (60, 16), 4: (300, 80), 5: (600, 150)}
 # the workloads as stated (P_{k-1} pressure), and config 2 with the Q_{k-2} pair (Q3 x Q1, the pair of
 # the paper's large runs)
 CASES = [(2, "P"), (3, "P"), (4, "P"), (5, "P"), (2, "Q")]
