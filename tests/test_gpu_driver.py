@@ -27,7 +27,8 @@ def setup(torch, case):
 
 
 VARIANTS = {"": {}, "zface": dict(refine_from=1), "periodic": dict(periodic=(True, True), frac=0.4),
-            "frames": dict(frames=True, frac=0.4)}
+            "frames": dict(frames=True, frac=0.4),
+            "all": dict(frames=True, frac=0.4, periodic=(True, True), refine_from=1)}
 
 
 def node_frames(m):
@@ -41,7 +42,8 @@ def node_frames(m):
 @pytest.mark.parametrize("k,mapped,pspace,variant", [(2, False, "P", ""), (3, True, "P", ""), (4, False, "P", ""),
                                                      (3, True, "Q", ""), (4, False, "Q", ""), (2, True, "P", "zface"),
                                                      (4, False, "P", "zface"), (3, True, "P", "periodic"),
-                                                     (2, True, "P", "frames"), (4, True, "Q", "frames")])
+                                                     (2, True, "P", "frames"), (4, True, "Q", "frames"),
+                                                     (3, True, "P", "all")])
 def test_jacobi_diag_matches_oracle(torch_cuda, k, mapped, pspace, variant):
     """d_u = sum_e sum_a R_e[a, n]^2 F_e[aa] (exact diagonal of F on conforming parts), 1 on masked
     rows; d_p = -sum_q w detJ psi_m^2 / mu."""
@@ -259,7 +261,8 @@ def dependent_slots(cm, P):
 
 
 @pytest.mark.parametrize("k,mapped,variant", [(2, True, "zface"), (3, False, "zface"), (4, True, "zface"),
-                                             (3, True, "periodic"), (2, True, "frames"), (4, True, "frames")])
+                                             (3, True, "periodic"), (2, True, "frames"), (4, True, "frames"),
+                                             (3, True, "all")])
 def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
     """Lateral and -z hanging faces: each line block is the sum, over the elements, of the oracle's
     element matrix A_e restricted to the independent slots of one element z-line (couplings through
@@ -326,7 +329,7 @@ def test_line_blocks_hanging_runs(torch_cuda, k, mapped, variant):
 
 
 @pytest.mark.parametrize("precond,variant", [("jacobi", "zface"), ("line", "zface"), ("line", "periodic"),
-                                             ("line", "frames")])
+                                             ("line", "frames"), ("line", "all")])
 def test_newton_step_variants(torch_cuda, precond, variant):
     """One Newton step on a mapped mesh with -z hanging faces, or periodic in x and y: the reported
     linear reduction is the true one (oracle Jacobian) and the next residual equals the oracle

@@ -169,6 +169,15 @@ def test_nodal_frames_zface_qspace(torch_cuda):
     check_case(torch_cuda, case, "nodal frames, z-face hanging, k=3 Q_(k-2) pressure")
 
 
+@pytest.mark.parametrize("k,pspace", [(2, "P"), (3, "Q"), (4, "P")])
+def test_all_variants_together(torch_cuda, k, pspace):
+    """Periodic x and y, refined columns starting one layer up (-z hanging faces), hanging faces
+    across the periodic boundaries, and nodal frames on the terrain base, in one mesh."""
+    case = small_case(k, mapped=True, frac=0.4, periodic=(True, True), frames=True, refine_from=1, pspace=pspace,
+                      body=(0.0, 0.1, -1.0))
+    check_case(torch_cuda, case, f"all variants k={k} {pspace}")
+
+
 def test_zface_hanging_qspace(torch_cuda):
     case = small_case(3, mapped=True, frac=0.4, refine_from=1, pspace="Q")
     check_case(torch_cuda, case, "z-face hanging k=3 mapped Q_(k-2) pressure")
