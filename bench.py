@@ -127,6 +127,77 @@ def run_newton(args, w, dev, n_newton=5, restart=50):
     print(json.dumps(rec), flush=True)
 
 
+def run_solve(args, w, dev, target=1e-6, inner_tol=1e-3, max_cycles=10, restart=50):
+    """Linear solve J d = b at the workload's state to a relative FP64 residual of 1e-6: cycles of
+    FGMRES(50) on the FP64 residual r = b - J_64 d (restarted FGMRES in FP64; FP32 Krylov cycles with
+    FP64 outer refinement in mixed precision), b = J x for a seeded random x."""
+    import torch
+    from paper_1406_6573_amd import Engine
+    from paper_1406_6573_amd.solve import NewtonKrylov
+    m = w.mesh
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    eng = Engine(0)
+    eng.upload_mesh(m)
+    eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
+    eng.set_state(t(w.u), t(w.p))
+    N = m.n_nodes
+    xr = np.random.default_rng(5).uniform(-1, 1, m.n_dof)
+    xr[:3 * N][m.dmask.ravel().astype(bool)] = 0.0
+    yu, yp = eng.jacobian_apply(t(xr[:3 * N].reshape(3, N)), t(xr[3 * N:].reshape(m.n_el, m.n_p)), "fp64")
+    b = torch.cat([yu.reshape(-1), yp.reshape(-1)])
+    bn = float(b.norm())
+    out = {}
+    for prec in ("fp64", "mixed"):
+        nk = NewtonKrylov(eng, restart=restart, precision=prec, refine=1, precond=args.precond,
+                          triangular=not args.block_diagonal)
+        d = torch.zeros_like(b)
+        r = torch.empty_like(b)
+        b32 = torch.empty(nk.n, dtype=torch.float32, device=dev) if prec == "mixed" else None
+        hist, its = [1.0], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nk.setup_preconditioner()
+        r.copy_(b)
+        for _ in range(max_cycles):
+            # one FGMRES cycle on the FP64 residual: in FP64, or in FP32 on its rounding (refinement)
+            if prec == "fp64":
+                nk.d64.zero_()
+                k, _ = nk.fgmres(r, nk.d64, inner_tol)
+                d += nk.d64
+            else:
+                eng.vec_convert(r, b32)
+                nk.tmp.zero_()
+                k, _ = nk.fgmres(b32, nk.tmp, inner_tol)
+                eng.vec_convert(nk.tmp, nk.w64)
+                d += nk.w64
+            its += k
+            du, dp = nk.split(d)
+            ru, rp = eng.jacobian_apply(du.contiguous(), dp.contiguous(), "fp64")
+            torch.sub(b, torch.cat([ru.reshape(-1), rp.reshape(-1)]), out=r)
+            hist.append(float(r.norm()) / bn)
+            if hist[-1] <= target:
+                break
+        torch.cuda.synchronize()
+        out[prec] = dict(seconds=time.perf_counter() - t0, krylov_iterations=its, residual_history=hist)
+        print(f"[bench] solve {prec}: {its} iterations, residuals " + " ".join(f"{v:.2e}" for v in hist),
+              file=sys.stderr, flush=True)
+        del nk
+    eng.close()
+    pc = {"jacobi": "point-Jacobi", "line": "vertical-line-block"}[args.precond] + " velocity block, " + \
+        ("block-diagonal" if args.block_diagonal else "block upper-triangular")
+    rec = {"metric": f"Linear solve J d = b to relative residual {target:g}: FGMRES({restart}) cycles on the FP64 "
+                     f"residual, {pc}, FP64 vs mixed",
+           "value": out["fp64"]["seconds"] / out["mixed"]["seconds"], "unit": "speedup mixed vs fp64",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"config{args.config}", "n_dof": m.n_dof, "n_el": m.n_el, "k": m.k,
+                      "pressure": args.pspace, "preconditioner": args.precond,
+                      "triangular": not args.block_diagonal},
+           "reached_fp64": out["fp64"]["residual_history"][-1] <= target,
+           "reached_mixed": out["mixed"]["residual_history"][-1] <= target,
+           "fp64": out["fp64"], "mixed": out["mixed"]}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +216,8 @@ def main():
                     help="block-diagonal instead of block upper-triangular preconditioner (with --newton)")
     ap.add_argument("--linearization", choices=["newton", "picard"], default="newton",
                     help="operator of the nonlinear steps (with --newton)")
+    ap.add_argument("--solve", action="store_true",
+                    help="time a linear solve to 1e-6 at the workload's state, FP64 vs mixed, instead of the applies")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (reference for HBM counters)")
     args = ap.parse_args()
@@ -180,9 +253,9 @@ def main():
     sz = dict(eng.sizes)
     sz["k"] = m.k
     geo = eng.geometry_kind()
-    if args.newton:
+    if args.newton or args.solve:
         eng.close()
-        run_newton(args, w, dev)
+        (run_newton if args.newton else run_solve)(args, w, dev)
         return
     print(f"[bench] n_el={sz['n_el']} n_dof={sz['n_dof']} geometry={geo}", file=sys.stderr, flush=True)
 

@@ -169,11 +169,19 @@ class NewtonKrylov:
         return k, abs(g[k]) / bnorm
 
     def linear_solve(self, rhs64, tol):
-        """d64 = approx J^-1 rhs64 (FP64 in and out)."""
+        """d64 = approx J^-1 rhs64 (FP64 in and out) by ``refine`` cycles of FGMRES(m).  FP64: restarted
+        FGMRES, stopping once the residual is below tol relative to rhs64.  Mixed: each cycle solves
+        for the FP64 residual r = rhs - J_64 d in FP32 to tol relative to r (the outer iterative
+        refinement), all ``refine`` cycles."""
         eng = self.eng
         self.d64.zero_()
         if self.precision == "fp64":
-            its, red = self.fgmres(rhs64, self.d64, tol)
+            its, red = 0, 1.0
+            for _ in range(self.refine):
+                k, red = self.fgmres(rhs64, self.d64, tol)
+                its += k
+                if red <= tol:
+                    break
             return its, red
         its = 0
         for _ in range(self.refine):                       # FP64 outer refinement of the correction
