@@ -32,6 +32,25 @@ def test_gradcheck_residual(torch_cuda):
     eng.close()
 
 
+def test_gradcheck_residual_all_variants(torch_cuda):
+    """gradcheck on a mesh that is periodic in x and y, has -z hanging faces and nodal frames on
+    the terrain base (the residual's u-derivative goes through the framed and periodic slots)."""
+    torch = torch_cuda
+    from paper_1406_6573_amd import Engine
+    from paper_1406_6573_amd.autograd import stokes_residual
+    case = small_case(2, mapped=True, nx=3, ny=3, nz=2, frac=0.4, periodic=(True, True), frames=True,
+                      refine_from=1)
+    m = case["mesh"]
+    eng = Engine()
+    eng.upload_mesh(m)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda").requires_grad_(True)
+    u, p, logA, beta = t(case["u"]), t(case["p"]), t(case["logA"]), t(case["beta"])
+    print(f"[gpu] gradcheck all variants k=2 n_el={m.n_el} n_dof={m.n_dof}", flush=True)
+    fn = lambda u, p, a, b: stokes_residual(eng, u, p, a, b, body=(0.0, 0.0, -1.0))
+    assert torch.autograd.gradcheck(fn, (u, p, logA, beta), eps=1e-6, atol=1e-6, rtol=1e-5, fast_mode=True)
+    eng.close()
+
+
 def test_vjp_matches_oracle_through_autograd(torch_cuda):
     torch = torch_cuda
     from oracle import StokesOracle
