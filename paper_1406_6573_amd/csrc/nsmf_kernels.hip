@@ -11,11 +11,12 @@
 //   z-line  (i, j) = (t % P, t / P): points (i, j, 0..P-1)   -- gather / scatter layout
 //   y-line  (i, z) = (t % P, t / P): points (i, 0..P-1, z)
 //   x-line  (j, z) = (t % P, t / P): points (0..P-1, j, z)   -- quadrature-point layout
-// with point (x, y, z) stored at LDS offset x + P*y + P*P*z.
+// with point (x, y, z) stored at LDS offset x + P*y + SZ*z (SZ >= P*P, padded against bank
+// conflicts).
 //
-// Per-quadrature-point data are stored in the x-line layout of the kernel itself:
-// index ((block * F + field) * NT + thread) * P + i, so that each thread loads one field of
-// its P points with one wide load and a wavefront's load is one contiguous access.
+// Per-quadrature-point data are stored in the x-line layout of the kernel itself (qp_at):
+// thread-major for P = 4 (one wide load per field and thread), point-major for P = 3, 5 (each
+// scalar load one contiguous span across the wavefront).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
