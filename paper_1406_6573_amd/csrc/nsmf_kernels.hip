@@ -1097,7 +1097,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
 // beta w|S| phi_a^2 (1 - n_c^2); hanging slots reach their parent nodes through squared
 // interpolation weights (tb2), i.e. sum_e sum_a R_e[a,n]^2 F_e[a,a].  Pressure: the lumped
 // mass weighted by 1/mu with a minus sign, the Schur-complement approximation of Sec. 6.
-template <int P, int GEO, int PS>
+template <int P, int GEO, int PS, bool FR>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
        const Tab<double, P> *__restrict__ tb2p, const double *__restrict__ st,
@@ -1125,8 +1125,8 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
 #pragma unroll
     for (int z = 0; z < P; ++z) y[c][z] = yo[c][z] = 0;
   // elements with framed bottom slots: the whole 3x3 blocks, so that a node in a local frame Q
-  // gets q_c^T (sum_a R[a, n]^2 F_aa) q_c
-  const bool offd = act && gv.rot != nullptr && m.rot_of[e] >= 0;
+  // gets q_c^T (sum_a R[a, n]^2 F_aa) q_c (FR: the mesh has nodal frames)
+  const bool offd = FR && act && m.rot_of[e] >= 0;
   if (act) {
     const int i = t % P, j = t / P;          // slot (i, j, z) of the z-line
     double jx = 0, jy = 0, jz = 0, detJ = 0;
@@ -1208,8 +1208,10 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   pressure_reduce<T, P, NP>(part, w, t, act, act ? dp + e * NP : nullptr);
   const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
   if (hang) hang_bwd<T, P>(y, cm, w, tb2, t, act);
-  if (hang && __syncthreads_or(offd)) hang_bwd<T, P>(yo, cm, w, tb2, t, act);
-  if (act && (nw[0] & ROT_BIT)) {
+  if constexpr (FR) {
+    if (hang && __syncthreads_or(offd)) hang_bwd<T, P>(yo, cm, w, tb2, t, act);
+  }
+  if (FR && act && (nw[0] & ROT_BIT)) {
     double Q[9];
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
     const double d00 = y[0][0], d11 = y[1][0], d22 = y[2][0], d01 = yo[0][0], d02 = yo[1][0], d12 = yo[2][0];
@@ -1245,7 +1247,7 @@ template <int P> __device__ __forceinline__ bool zline_run(uint32_t cm, int i, i
 // za = zb = 0.  Each slot stores its row towards the slots below it: buf[(c n_inc + slot) P + d] =
 // F_e[zb, zb - d], d = 0..k (0 where zb - d < lo), for zb = lo..hi.  Dependent slots store nothing
 // (couplings through hanging constraints are left out of the preconditioner).
-template <int P, int GEO>
+template <int P, int GEO, bool FR>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ st,
         const double *__restrict__ beta, double *__restrict__ buf) {
@@ -1330,7 +1332,7 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
   // and its diagonal is q_c^T A[(., 0), (., 0)] q_c, from the cross-component entries
   // A[(c', 0), (c, zb)] = sum over points of mu'/2 (delta_c'c grad phi_0 . grad phi_zb +
   // d_c phi_0 d_c' phi_zb) - kappa (Sigma0 grad phi_0)_c' (Sigma0 grad phi_zb)_c (+ basal term)
-  if (lo == 0 && (m.en[e * P3 + t] & ROT_BIT)) {
+  if (FR && lo == 0 && (m.en[e * P3 + t] & ROT_BIT)) {
     double M[3][3][P];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -1855,8 +1857,12 @@ template <int P, int GEO, int PS>
 static hipError_t diag_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                           const double *st, const double *beta, double *ev, double *dp) {
   const TabSet<P> *ts = (const TabSet<P> *)tabs;
-  hipLaunchKernelGGL((k_diag<P, GEO, PS>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &ts->d, &ts->dsq, st, beta, ev,
-                     dp);
+  if (g.rot != nullptr)   // nodal frames: the 3x3 slot blocks are formed
+    hipLaunchKernelGGL((k_diag<P, GEO, PS, true>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &ts->d, &ts->dsq, st,
+                       beta, ev, dp);
+  else
+    hipLaunchKernelGGL((k_diag<P, GEO, PS, false>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &ts->d, &ts->dsq, st,
+                       beta, ev, dp);
   return hipGetLastError();
 }
 hipError_t launch_diag(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
@@ -1908,8 +1914,12 @@ static hipError_t lines_pg(hipStream_t s, const MeshView &m, const GeoView<doubl
                            const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
                            const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
                            double *buf, double *fac64, float *fac32) {
-  hipLaunchKernelGGL((k_lines<P, GEO>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
-                     &((const TabSet<P> *)tabs)->d, st, beta, buf);
+  if (g.rot != nullptr)   // nodal frames: rotated bottom rows
+    hipLaunchKernelGGL((k_lines<P, GEO, true>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
+                       &((const TabSet<P> *)tabs)->d, st, beta, buf);
+  else
+    hipLaunchKernelGGL((k_lines<P, GEO, false>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
+                       &((const TabSet<P> *)tabs)->d, st, beta, buf);
   hipLaunchKernelGGL(k_line_band, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, P, lptr, lslot,
                      (const double *)buf, fac64);
   if (n_lines > 0)
