@@ -751,7 +751,7 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
 
 // ================================================================= kernels
 // Jacobian apply (and VJP): y = J_c x at the stored linearisation point.
-template <typename T, int P, int GEO, bool VJP, int PS>
+template <typename T, int P, int GEO, bool VJP, int PS, bool FR>
 __global__ void __launch_bounds__(Launch<P>::NT)
 k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void *__restrict__ st_, const T *__restrict__ fst,
         const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
@@ -792,7 +792,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
   }
   T v[3][P];
   gather_words<T, P>(nw, xu, N, act, true, v);
-  const bool rot = act && (nw[0] & ROT_BIT);
+  const bool rot = FR && act && (nw[0] & ROT_BIT);   // FR: the mesh has nodal frames
   if (rot) {
     T Q[9];
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
@@ -1884,9 +1884,13 @@ static hipError_t apply_t(hipStream_t s, const MeshView &m, const void *gview, c
   const Tab<T, P> *tb;
   if constexpr (sizeof(T) == 8) tb = &ts->d;
   else tb = bf16 ? &ts->fb : &ts->f;
-  hipLaunchKernelGGL((k_apply<T, P, GEO, VJP, PS>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m,
-                     *(const GeoView<T> *)gview, tb, st, (const T *)fst, (const T *)beta, (const T *)xu,
-                     (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
+  const GeoView<T> &gv = *(const GeoView<T> *)gview;
+  if (gv.rot != nullptr)   // nodal frames: the framed-slot variant
+    hipLaunchKernelGGL((k_apply<T, P, GEO, VJP, PS, true>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, gv, tb, st,
+                       (const T *)fst, (const T *)beta, (const T *)xu, (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
+  else
+    hipLaunchKernelGGL((k_apply<T, P, GEO, VJP, PS, false>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, gv, tb, st,
+                       (const T *)fst, (const T *)beta, (const T *)xu, (const T *)xp, (T *)yu, (T *)yp, inv_n, gA, gB);
   return hipGetLastError();
 }
 hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t s, const MeshView &m, const void *gview,
