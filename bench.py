@@ -3,11 +3,13 @@
 A step is one application y = J_c x of the Newton-linearised Stokes operator
 (gather with hanging-node interpolation, sum-factorised gradients, the fused
 quadrature-point Newton-tensor step, pressure terms, transposed contractions,
-basal Robin term, scatter, Dirichlet rows) on the workload "slab 64x64x8, Q3 x P2,
-element aspect ratio 125, 20% of the columns refined 2:1" with inputs resident in
-HBM.  The headline value is the mixed-precision (FP32) apply; the FP64 apply, the
-FP32-vs-FP64 error, the linearisation (set_state), residual and VJP times are
-reported beside it.
+basal Robin term, scatter, Dirichlet rows) with inputs resident in HBM.  The
+default workload is the largest single-GPU one: "terrain-mapped slab 128x128x16,
+Q4 x P3, Fourier base and thickness" (56.6M DoF).  The headline value is the
+mixed-precision (FP32) apply; the FP64 apply, the FP32-vs-FP64 error, the
+BF16-operator trial, the linearisation (set_state), residual and VJP times are
+reported beside it, and the same figures for "slab 64x64x8, Q3 x P2, aspect 125,
+20% of the columns refined 2:1" under the key "slab_q3".
 
 Prints one JSON line.
 """
@@ -28,25 +30,26 @@ METRIC = "GDoF/s of Newton-Stokes Jacobian apply, mixed vs FP64 at stated rel. e
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(sz, geo_kind, word, nstate):
-    """Bytes one Jacobian apply must move with stored linearisation data: nstate values per
-    quadrature point (FP64: mu', kappa, Sigma0 = 8; FP32: mu', sqrt(kappa) Sigma0 = 7), x read and
-    y written once, per-element geometry (affine) or per-point geometry (column-mapped), basal face
-    data and beta."""
+def algorithmic_bytes(sz, geo_kind, word):
+    """Bytes one Jacobian apply must move in the stored-linearisation design: per quadrature point
+    the 8 values of the linearisation (mu', kappa, Sigma0) and, on column-mapped elements, 6
+    geometry values (the rows of J^-1 that vary and w detJ); x read and y written once; per-element
+    geometry on affine elements; the basal face data.  Connectivity, slot positions and partial sums
+    are not counted (they are not part of the method's data)."""
     k = sz["k"]
     nq = sz["n_el"] * (k + 1) ** 3
     nvec = 3 * sz["n_nodes"] + sz["n_el"] * sz["n_p"]
-    geo = 4 * sz["n_el"] if geo_kind == "affine" else 2 * sz["n_el"] + 4 * nq
+    geo = 4 * sz["n_el"] if geo_kind == "affine" else 6 * nq
     face = sz["n_bface"] * (1 + 4 * (k + 1) ** 2)
-    return word * (nstate * nq + 2 * nvec + geo + face)
+    return word * (8 * nq + 2 * nvec + geo + face)
 
 
 TRAFFIC_FILES = {2: "apply_slab64x64x8_q3_traffic.json", 3: "apply_terrain128x128x16_q4_traffic.json"}
 
 
-def measured_traffic(config_id):
-    """HBM bytes per FP32 apply from the committed counter summary of the workload, if it was taken
-    with the current kernel sources (otherwise None)."""
+def measured_traffic(config_id, prec="fp32_apply"):
+    """HBM bytes per apply (every kernel of one apply) from the committed counter summary of the
+    workload, if it was taken with the current kernel sources (otherwise None)."""
     import hashlib
     if config_id not in TRAFFIC_FILES:
         return None
@@ -59,17 +62,16 @@ def measured_traffic(config_id):
         h.update(open(os.path.join(ROOT, p), "rb").read())
     if h.hexdigest() != rec["source_sha256"]:
         return None
-    f = rec["fp32_apply"]
-    return 1e6 * (f["k_apply_read_MB"] + f["k_apply_write_MB"] + f["k_assemble_read_MB"] + f["k_assemble_write_MB"])
+    return 1e6 * sum(rec[prec].values())
 
 
 def cpu_baseline(seed=0):
     """The FP64 oracle as it stands: assemble the Jacobian and apply it once, on a reduced
-    sample of the same workload (20x20x2 columns, same element shape, 20% refined)."""
+    sample of the same workload (terrain 16x16x4, Q4 x P3, same construction)."""
     import threadpoolctl
     from meshgen import make_config
     from oracle import StokesOracle
-    w = make_config(2, seed=seed, nx=20, ny=20, nz=2)
+    w = make_config(3, seed=seed, nx=16, ny=16, nz=4)
     m = w.mesh
     t0 = time.perf_counter()
     o = StokesOracle(m, w.n, w.eps, w.B0, w.logA, w.beta)
@@ -77,15 +79,15 @@ def cpu_baseline(seed=0):
     xu, xp = w.directions[0]
     o.jacobian_apply(xu, xp)
     t1 = time.perf_counter()
-    reps = 10
+    reps = 5
     for _ in range(reps):
         o.jacobian_apply(xu, xp)
     t2 = time.perf_counter()
     threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] + [1])
     return {"value": m.n_dof / (t1 - t0) / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"slab 20x20x2 Q3xP2 (aspect 125, 20% refined), {m.n_el} elements, {m.n_dof} DoF: "
-                       f"dense-quadrature element matrices + CSR assembly + one SpMV = {t1 - t0:.2f} s; "
-                       f"SpMV alone with the assembled matrix {(t2 - t1) / reps * 1e3:.2f} ms "
+            "sample": (f"terrain 16x16x4 Q4xP3 (same construction as the 128x128x16 workload), {m.n_el} elements, "
+                       f"{m.n_dof} DoF: dense-quadrature element matrices + CSR assembly + one SpMV = "
+                       f"{t1 - t0:.2f} s; SpMV alone with the assembled matrix {(t2 - t1) / reps * 1e3:.2f} ms "
                        f"({m.n_dof / ((t2 - t1) / reps) / 1e9:.4f} GDoF/s)")}
 
 
@@ -198,13 +200,96 @@ def run_solve(args, w, dev, target=1e-6, inner_tol=1e-3, max_cycles=10, restart=
     print(json.dumps(rec), flush=True)
 
 
+WORKLOADS = {1: "unit box 8x8x2 {pair}", 2: "slab 64x64x8 {pair}, aspect 125, 20% columns refined 2:1",
+             3: "terrain slab 128x128x16 {pair}, Fourier base and thickness", 4: "slab 96x96x12 {pair}, 20% refined",
+             5: "dome 256x256x8 {pair}, margin refined"}
+
+
+def measure_applies(config_id, pspace, steps, warmup, dev, with_aux=True):
+    """Build the workload, then time `steps` Jacobian applies in FP64, FP32 and FP32 with bfloat16
+    operators (after `warmup` untimed ones each), with inputs resident in HBM.  Returns a dict."""
+    import torch
+    from meshgen import make_config
+    from paper_1406_6573_amd import Engine
+
+    print(f"[bench] building workload config{config_id}", file=sys.stderr, flush=True)
+    w = make_config(config_id, n_dirs=1, pspace=pspace)
+    m = w.mesh
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    eng = Engine(0)
+    eng.upload_mesh(m)
+    eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
+    u, p = t(w.u), t(w.p)
+    xu, xp = w.directions[0]
+    x64u, x64p = t(xu), t(xp)
+    x32u, x32p = x64u.float(), x64p.float()
+    y64 = (torch.empty_like(x64u), torch.empty_like(x64p))
+    y32 = (torch.empty_like(x32u), torch.empty_like(x32p))
+    sz = dict(eng.sizes)
+    sz["k"] = m.k
+    geo = eng.geometry_kind()
+    print(f"[bench] n_el={sz['n_el']} n_dof={sz['n_dof']} geometry={geo}", file=sys.stderr, flush=True)
+
+    def timed(fn, n, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e3
+
+    eng.set_state(u, p)
+    res = {}
+    if with_aux:
+        res["set_state_ms"] = timed(lambda: eng.set_state(u, p), 5, 1)
+        res["residual_ms"] = timed(lambda: eng.residual(), 10, 2)
+        res["vjp_fp64_ms"] = timed(lambda: eng.residual_vjp(x64u, x64p), 10, 2)
+    out = {}
+    for prec, (xa, xb, yy) in (("fp64", (x64u, x64p, y64)), ("fp32", (x32u, x32p, y32)),
+                              ("bf16ops", (x32u, x32p, y32))):
+        fn = lambda: eng.jacobian_apply(xa, xb, prec, out=yy)
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        eng.set_kernel_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        kms, nk = eng.kernel_time()
+        eng.set_kernel_timing(False)
+        out[prec] = dict(ms=ms, kernel_ms=kms / max(nk, 1))
+        print(f"[bench] config{config_id} {prec}: {ms:.4f} ms/apply, device time {kms / max(nk, 1):.4f} ms",
+              file=sys.stderr, flush=True)
+    # accuracy of the mixed paths against the FP64 apply (which matches the FP64 oracle to ~1e-13)
+    r64u, r64p = eng.jacobian_apply(x64u, x64p, "fp64")
+    ref = torch.cat([r64u.reshape(-1), r64p.reshape(-1)])
+    errs = {}
+    for prec in ("fp32", "bf16ops"):
+        a, b = eng.jacobian_apply(x32u, x32p, prec)
+        got = torch.cat([a.reshape(-1), b.reshape(-1)]).double()
+        errs[prec] = float((got - ref).norm() / ref.norm())
+    eng.close()
+    del eng, u, p, x64u, x64p, x32u, x32p, y64, y32, r64u, r64p, ref
+    torch.cuda.empty_cache()
+    n_dof = sz["n_dof"]
+    res.update(sz=sz, geo=geo, k=m.k, out=out, errs=errs,
+               gdofs={k: n_dof / (v["ms"] * 1e-3) / 1e9 for k, v in out.items()},
+               bytes32=algorithmic_bytes(sz, geo, 4), bytes64=algorithmic_bytes(sz, geo, 8))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the second (slab Q3) workload")
     ap.add_argument("--pspace", choices=["P", "Q"], default="P",
                     help="pressure space: P = P_{k-1} (the workloads as stated), Q = Q_{k-2} (Gauss-point Lagrange)")
     ap.add_argument("--newton", action="store_true",
@@ -228,108 +313,61 @@ def main():
 
     import torch
     from meshgen import make_config
-    from paper_1406_6573_amd import Engine
 
+    dev = torch.device("cuda", 0)
     if args.calibration_copy_mib > 0:
-        src = torch.ones(args.calibration_copy_mib * 2 ** 18, dtype=torch.float32, device="cuda:0")
+        src = torch.ones(args.calibration_copy_mib * 2 ** 18, dtype=torch.float32, device=dev)
         dst = src.clone()
         torch.cuda.synchronize()
         print(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done ({float(dst[0])})", file=sys.stderr)
         del src, dst
-    print(f"[bench] building workload config{args.config}", file=sys.stderr, flush=True)
-    w = make_config(args.config, n_dirs=1, pspace=args.pspace)
-    m = w.mesh
-    dev = torch.device("cuda", 0)
-    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    eng = Engine(0)
-    eng.upload_mesh(m)
-    eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
-    u, p = t(w.u), t(w.p)
-    xu, xp = w.directions[0]
-    x64u, x64p = t(xu), t(xp)
-    x32u, x32p = x64u.float(), x64p.float()
-    y64 = (torch.empty_like(x64u), torch.empty_like(x64p))
-    y32 = (torch.empty_like(x32u), torch.empty_like(x32p))
-    sz = dict(eng.sizes)
-    sz["k"] = m.k
-    geo = eng.geometry_kind()
     if args.newton or args.solve:
-        eng.close()
+        print(f"[bench] building workload config{args.config}", file=sys.stderr, flush=True)
+        w = make_config(args.config, n_dirs=1, pspace=args.pspace)
         (run_newton if args.newton else run_solve)(args, w, dev)
         return
-    print(f"[bench] n_el={sz['n_el']} n_dof={sz['n_dof']} geometry={geo}", file=sys.stderr, flush=True)
 
-    def timed(fn, steps, warm):
-        for _ in range(warm):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps * 1e3
-
-    ms_state = timed(lambda: eng.set_state(u, p), 5, 1)
-    ms_res = timed(lambda: eng.residual(), 10, 2)
-    ms_vjp = timed(lambda: eng.residual_vjp(x64u, x64p), 10, 2)
-    out = {}
-    for prec, (xa, xb, yy) in (("fp64", (x64u, x64p, y64)), ("fp32", (x32u, x32p, y32)),
-                              ("bf16ops", (x32u, x32p, y32))):
-        fn = lambda: eng.jacobian_apply(xa, xb, prec, out=yy)
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        eng.set_kernel_timing(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / args.steps * 1e3
-        kms, nk = eng.kernel_time()
-        eng.set_kernel_timing(False)
-        out[prec] = dict(ms=ms, kernel_ms=kms / max(nk, 1))
-        print(f"[bench] {prec}: {ms:.4f} ms/apply, device time {kms / max(nk, 1):.4f} ms", file=sys.stderr,
-              flush=True)
-    # accuracy of the mixed paths against the FP64 apply (which matches the FP64 oracle to ~1e-14)
-    r64u, r64p = eng.jacobian_apply(x64u, x64p, "fp64")
-    ref = torch.cat([r64u.reshape(-1), r64p.reshape(-1)])
-    errs = {}
-    for prec in ("fp32", "bf16ops"):
-        a, b = eng.jacobian_apply(x32u, x32p, prec)
-        got = torch.cat([a.reshape(-1), b.reshape(-1)]).double()
-        errs[prec] = float((got - ref).norm() / ref.norm())
-    n_dof = sz["n_dof"]
-    gdofs = {k: n_dof / (v["ms"] * 1e-3) / 1e9 for k, v in out.items()}
-    b32 = algorithmic_bytes(sz, geo, 4, 7)
-    b64 = algorithmic_bytes(sz, geo, 8, 8)
-    ach32 = b32 / (out["fp32"]["kernel_ms"] * 1e-3) / 1e9
-    ach64 = b64 / (out["fp64"]["kernel_ms"] * 1e-3) / 1e9
-    pair = f"Q{m.k}xP{m.k - 1}" if args.pspace == "P" else f"Q{m.k}xQ{m.k - 2}"
+    r = measure_applies(args.config, args.pspace, args.steps, args.warmup, dev)
+    sz, geo, k, out, errs, gdofs = r["sz"], r["geo"], r["k"], r["out"], r["errs"], r["gdofs"]
+    ach32 = r["bytes32"] / (out["fp32"]["kernel_ms"] * 1e-3) / 1e9
+    ach64 = r["bytes64"] / (out["fp64"]["kernel_ms"] * 1e-3) / 1e9
+    pair = f"Q{k}xP{k - 1}" if args.pspace == "P" else f"Q{k}xQ{k - 2}"
+    traffic = measured_traffic(args.config) if args.pspace == "P" else None
     rec = {
         "metric": METRIC, "value": gdofs["fp32"], "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": out["fp32"]["ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"config{args.config}: " + {2: "slab 64x64x8 {pair}, aspect 125, 20% columns refined 2:1",
-                                                            3: "terrain slab 128x128x16 {pair}",
-                                                            4: "slab 96x96x12 {pair}, 20% refined",
-                                                            5: "dome 256x256x8 {pair}, margin refined",
-                                                            1: "unit box 8x8x2 {pair}"}[args.config].format(pair=pair),
-                   "k": m.k, "n_el": sz["n_el"], "n_dof": n_dof, "geometry": geo, "pressure": pair.split("x")[1]},
+        "config": {"workload": f"config{args.config}: " + WORKLOADS[args.config].format(pair=pair),
+                   "k": k, "n_el": sz["n_el"], "n_dof": sz["n_dof"], "geometry": geo, "pressure": pair.split("x")[1]},
         "rel_err_vs_fp64": errs["fp32"],
         "fp64": {"value": gdofs["fp64"], "ms_per_step": out["fp64"]["ms"],
                  "roofline_frac": ach64 / HBM_PEAK_GBS},
         "speedup_mixed_vs_fp64": out["fp64"]["ms"] / out["fp32"]["ms"],
         "bf16ops_trial": {"value": gdofs["bf16ops"], "rel_err_vs_fp64": errs["bf16ops"]},
-        "set_state_ms": ms_state, "residual_ms": ms_res, "vjp_fp64_ms": ms_vjp,
+        "set_state_ms": r["set_state_ms"], "residual_ms": r["residual_ms"], "vjp_fp64_ms": r["vjp_fp64_ms"],
         "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach32 / HBM_PEAK_GBS, "traffic": measured_traffic(args.config) if args.pspace == "P" else None,
-                     "kernel": f"apply = k_apply<float,{sz['k'] + 1},{geo}> + k_assemble<float>", "kernel_ms": out["fp32"]["kernel_ms"],
-                     "algorithmic_bytes": b32},
+                     "frac": ach32 / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic / 1e9,
+                     "traffic_unit": "GB per apply",
+                     "kernel": f"one FP32 apply (all its kernels), Q{k} {geo}",
+                     "kernel_ms": out["fp32"]["kernel_ms"], "algorithmic_bytes": r["bytes32"]},
     }
+    if not args.no_extra and args.config != 2:
+        r2 = measure_applies(2, args.pspace, args.steps, args.warmup, dev, with_aux=False)
+        pair2 = "Q3xP2" if args.pspace == "P" else "Q3xQ1"
+        rec["slab_q3"] = {
+            "workload": "config2: " + WORKLOADS[2].format(pair=pair2), "n_dof": r2["sz"]["n_dof"],
+            "fp32": {"value": r2["gdofs"]["fp32"], "ms_per_step": r2["out"]["fp32"]["ms"],
+                     "roofline_frac": r2["bytes32"] / (r2["out"]["fp32"]["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "fp64": {"value": r2["gdofs"]["fp64"], "ms_per_step": r2["out"]["fp64"]["ms"],
+                     "roofline_frac": r2["bytes64"] / (r2["out"]["fp64"]["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "bf16ops_trial": {"value": r2["gdofs"]["bf16ops"], "rel_err_vs_fp64": r2["errs"]["bf16ops"]},
+            "rel_err_vs_fp64": r2["errs"]["fp32"],
+            "traffic_GB_per_apply": (lambda v: None if v is None else v / 1e9)(measured_traffic(2)),
+        }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a reduced sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()
-    eng.close()
     print(json.dumps(rec), flush=True)
 
 

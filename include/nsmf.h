@@ -172,10 +172,19 @@ int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p);
  * x and y must not overlap. */
 int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p);
 
-/* Vector-Jacobian product of the residual at the state for cotangent w = (w_u, w_p):
- * g_u, g_p = J_c^T w (= J_c w, the operator is symmetric); g_logA[e] = d<w, r>/dlogA_e;
- * g_beta[f] = d<w, r>/dbeta_f.  w and g_u/g_p are double for NSMF_FP64, float otherwise;
- * g_logA [n_el] and g_beta [n_bface] are always double.  Any g_* may be NULL. */
+/* Vector-Jacobian product of the residual at the state for cotangent w = (w_u, w_p).
+ * Sec. 2.3: the adjoint (transposed) linearisation of eq. (weak) uses the same fourth-order
+ * tensor of eq. (rank4) as the Newton step, and A(u) is symmetric (Sec. 4.1), so
+ *   g_u, g_p = J_c^T w = J_c w;
+ * the parameter derivatives differentiate eq. (weak) through the rate factor of eq. (glen)
+ * (B_e = B0 exp(-logA_e / n), so d mu / d logA_e = -mu / n) and through the basal term of
+ * eq. (robin):
+ *   g_logA[e] = d<w, r>/dlogA_e = -(1/n) sum over the element's points of w detJ mu D(u):D(w_u);
+ *   g_beta[f] = d<w, r>/dbeta_f = int_f (T u).(T w_u), T = I - n n^T.
+ * w and g_u/g_p are DEVICE double for NSMF_FP64, float otherwise; g_logA [n_el] and
+ * g_beta [n_bface] are always DEVICE double (FP64 accumulation).  Any g_* may be NULL.
+ * Errors: NSMF_EINVAL (prec out of range, w NULL), NSMF_ESTATE (no state, or the Picard
+ * linearisation is selected), NSMF_EHIP. */
 int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
                       double *g_logA, double *g_beta);
 
@@ -210,7 +219,7 @@ int nsmf_line_apply(nsmf_ctx *ctx, int prec, const void *x_u, void *y_u);
  * accumulate in FP64 with a fixed reduction order (deterministic).
  *   nsmf_vec_dots:  h[i] = sum_r V[i*ldv + r] w[r], i < k <= 64 (h: DEVICE doubles [k])
  *   nsmf_vec_gemv:  w[r] += alpha sum_i V[i*ldv + r] h[i] (h: DEVICE doubles [k])
- *   nsmf_vec_axpby: y = a x + b y
+ *   nsmf_vec_axpby: y = a x + b y (b == 0: y is written without being read, BLAS convention)
  *   nsmf_vec_mul:   z = d .* x (d: DEVICE doubles [n])
  *   nsmf_vec_convert: out = in, double -> float (to_fp32 != 0) or float -> double */
 int nsmf_vec_dots(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w, double *h);

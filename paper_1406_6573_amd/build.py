@@ -19,7 +19,6 @@ SOURCES = ["nsmf_tables.cpp", "nsmf_api.cpp", "nsmf_kernels.hip", "nsmf_blas.hip
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
-    "-munsafe-fp-atomics",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -51,11 +51,11 @@ __global__ void k_gemv(int64_t n, int k, const T *__restrict__ V, int64_t ldv, c
   w[r] = (T)((double)w[r] + alpha * s);
 }
 
-// y = a x + b y
+// y = a x + b y; with b == 0 the old y is not read (BLAS convention), so y may hold any bits
 template <typename T>
 __global__ void k_axpby(int64_t n, double a, const T *__restrict__ x, double b, T *__restrict__ y) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) y[r] = (T)(a * (double)x[r] + b * (double)y[r]);
+  if (r < n) y[r] = (T)(b == 0.0 ? a * (double)x[r] : a * (double)x[r] + b * (double)y[r]);
 }
 
 // z = d * x (elementwise), d in FP64

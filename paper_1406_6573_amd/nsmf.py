@@ -118,9 +118,13 @@ class Engine:
             raise NsmfError(rc, msg.decode() if msg else "")
 
     def sync_stream(self):
-        """Enqueue subsequent work on torch's current stream of the engine's device."""
+        """Bind the context to torch's current stream of the engine's device.  Every method that
+        enqueues device work calls this first, so the work always follows the caller's current
+        stream (a changed stream is passed to the library before the call)."""
         s = self.torch.cuda.current_stream(self.dev).cuda_stream
-        self._check(self.lib.nsmf_set_stream(self.h, ctypes.c_void_p(s)))
+        if s != getattr(self, "_stream", None):
+            self._check(self.lib.nsmf_set_stream(self.h, ctypes.c_void_p(s)))
+            self._stream = s
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -139,6 +143,22 @@ class Engine:
         if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous {dtype} of shape {tuple(shape)}")
         return t
+
+    def _flat(self, t, n, dtype, name):
+        """A contiguous device vector of dtype with at least n entries (Krylov vector kernels)."""
+        if not (t.is_cuda and t.device.index == self.device):
+            raise ValueError(f"{name} must be a CUDA tensor on device {self.device}")
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor with at least {n} entries")
+        return t
+
+    def _basis(self, V, k, n, dtype, name="V"):
+        """Row-major basis [rows, >= n] with at least k rows, unit stride along a row."""
+        if not (V.is_cuda and V.device.index == self.device):
+            raise ValueError(f"{name} must be a CUDA tensor on device {self.device}")
+        if V.dtype != dtype or V.dim() != 2 or V.stride(1) != 1 or V.shape[0] < k or V.shape[1] < n:
+            raise ValueError(f"{name} must be a {dtype} [rows >= {k}, cols >= {n}] tensor with unit row stride")
+        return V
 
     # -------------------------------------------------------------- API
     def upload_mesh(self, mesh):
@@ -162,6 +182,7 @@ class Engine:
                   (ctypes.c_double * 3)(*[float(v) for v in getattr(mesh, "period", (0.0, 0.0, 0.0))]),
                   0 if fn is None else fn.shape[0], None if fn is None else fn.ctypes.data,
                   None if fq is None else fq.ctypes.data)
+        self.sync_stream()
         self._check(self.lib.nsmf_upload_mesh(self.h, ctypes.byref(s)))
         self.k = int(mesh.k)
         self.sizes = self.query()
@@ -186,6 +207,7 @@ class Engine:
         if beta is not None:
             beta = self._vec(beta, (sz["n_bface"],), torch.float64, "beta")
         prm = _Params(float(n), float(eps), float(B0), (ctypes.c_double * 3)(*[float(b) for b in body]))
+        self.sync_stream()
         self._check(self.lib.nsmf_set_params(self.h, ctypes.byref(prm), _ptr(logA), _ptr(beta)))
         self.state_version += 1
 
@@ -204,6 +226,7 @@ class Engine:
         sz = self.sizes
         u = self._vec(u, (3, sz["n_nodes"]), torch.float64, "u")
         p = self._vec(p, (sz["n_el"], sz["n_p"]), torch.float64, "p")
+        self.sync_stream()
         self._check(self.lib.nsmf_set_state(self.h, _ptr(u), _ptr(p)))
         self.state_version += 1
 
@@ -215,6 +238,7 @@ class Engine:
         if out is None:
             out = (torch.empty((3, sz["n_nodes"]), dtype=torch.float64, device=self.dev),
                    torch.empty((sz["n_el"], sz["n_p"]), dtype=torch.float64, device=self.dev))
+        self.sync_stream()
         self._check(self.lib.nsmf_residual(self.h, _ptr(f_u), _ptr(out[0]), _ptr(out[1])))
         return out
 
@@ -229,6 +253,7 @@ class Engine:
         x_p = self._vec(x_p, (sz["n_el"], sz["n_p"]), dt, "x_p")
         if out is None:
             out = (self.torch.empty_like(x_u), self.torch.empty_like(x_p))
+        self.sync_stream()
         self._check(self.lib.nsmf_jacobian_apply(self.h, prec, _ptr(x_u), _ptr(x_p), _ptr(out[0]), _ptr(out[1])))
         return out
 
@@ -243,6 +268,7 @@ class Engine:
         g_p = torch.empty_like(w_p) if "p" in want else None
         g_A = torch.empty(sz["n_el"], dtype=torch.float64, device=self.dev) if "logA" in want else None
         g_b = torch.empty(sz["n_bface"], dtype=torch.float64, device=self.dev) if "beta" in want else None
+        self.sync_stream()
         self._check(self.lib.nsmf_residual_vjp(self.h, prec, _ptr(w_u), _ptr(w_p), _ptr(g_u), _ptr(g_p),
                                                _ptr(g_A), _ptr(g_b)))
         return g_u, g_p, g_A, g_b
@@ -256,12 +282,14 @@ class Engine:
             out = (torch.empty((3, sz["n_nodes"]), dtype=torch.float64, device=self.dev),
                    torch.empty((sz["n_el"], sz["n_p"]), dtype=torch.float64, device=self.dev))
         d_u, d_p = out
+        self.sync_stream()
         self._check(self.lib.nsmf_jacobi_diag(self.h, 1 if invert else 0, _ptr(d_u), _ptr(d_p)))
         return d_u, d_p
 
     def line_setup(self):
         """Factor the vertical-line blocks of the velocity block at the state; returns the number of lines."""
         n = ctypes.c_int64(0)
+        self.sync_stream()
         self._check(self.lib.nsmf_line_setup(self.h, ctypes.byref(n)))
         return int(n.value)
 
@@ -269,7 +297,8 @@ class Engine:
         """y_u = (line blocks)^{-1} x_u for x_u [3, n_nodes] (float64 or float32, contiguous)."""
         sz = self.sizes
         x_u = self._vec(x_u, (3, sz["n_nodes"]), x_u.dtype, "x_u")
-        y_u = self.torch.empty_like(x_u) if out is None else out
+        y_u = self.torch.empty_like(x_u) if out is None else self._vec(out, (3, sz["n_nodes"]), x_u.dtype, "out")
+        self.sync_stream()
         self._check(self.lib.nsmf_line_apply(self.h, self._prec_of(x_u), _ptr(x_u), _ptr(y_u)))
         return y_u
 
@@ -284,36 +313,60 @@ class Engine:
         raise ValueError("vectors must be float64 or float32")
 
     def vec_dots(self, V, k, w, h):
-        """h[:k] = V[:k] @ w  (V: [rows, n] contiguous, h: float64 device [>= k])."""
+        """h[:k] = V[:k] @ w  (V: [rows >= k, >= n] with unit row stride, h: float64 device [>= k])."""
         prec = self._prec_of(w)
-        self._check(self.lib.nsmf_vec_dots(self.h, prec, w.numel(), int(k), _ptr(V), V.stride(0), _ptr(w), _ptr(h)))
+        n = w.numel()
+        self._flat(w, n, w.dtype, "w")
+        self._basis(V, k, n, w.dtype)
+        self._flat(h, k, self.torch.float64, "h")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_dots(self.h, prec, n, int(k), _ptr(V), V.stride(0), _ptr(w), _ptr(h)))
 
     def vec_gemv(self, V, k, h, alpha, w):
         """w += alpha * V[:k].T @ h[:k]."""
         prec = self._prec_of(w)
-        self._check(self.lib.nsmf_vec_gemv(self.h, prec, w.numel(), int(k), _ptr(V), V.stride(0), _ptr(h),
+        n = w.numel()
+        self._flat(w, n, w.dtype, "w")
+        self._basis(V, k, n, w.dtype)
+        self._flat(h, k, self.torch.float64, "h")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_gemv(self.h, prec, n, int(k), _ptr(V), V.stride(0), _ptr(h),
                                            float(alpha), _ptr(w)))
 
     def vec_axpby(self, a, x, b, y):
-        """y = a x + b y."""
-        self._check(self.lib.nsmf_vec_axpby(self.h, self._prec_of(y), y.numel(), float(a), _ptr(x), float(b),
-                                            _ptr(y)))
+        """y = a x + b y (b == 0: y is overwritten without being read)."""
+        n = y.numel()
+        self._flat(y, n, y.dtype, "y")
+        self._flat(x, n, y.dtype, "x")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_axpby(self.h, self._prec_of(y), n, float(a), _ptr(x), float(b), _ptr(y)))
 
     def vec_mul(self, d, x, z):
         """z = d * x (d float64)."""
-        self._check(self.lib.nsmf_vec_mul(self.h, self._prec_of(z), z.numel(), _ptr(d), _ptr(x), _ptr(z)))
+        n = z.numel()
+        self._flat(z, n, z.dtype, "z")
+        self._flat(x, n, z.dtype, "x")
+        self._flat(d, n, self.torch.float64, "d")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_mul(self.h, self._prec_of(z), n, _ptr(d), _ptr(x), _ptr(z)))
 
     def vec_convert(self, x, out):
         """out = x converted between float64 and float32."""
-        import torch
+        torch = self.torch
         to32 = 1 if out.dtype == torch.float32 else 0
-        self._check(self.lib.nsmf_vec_convert(self.h, x.numel(), to32, _ptr(x), _ptr(out)))
+        n = x.numel()
+        self._flat(x, n, torch.float64 if to32 else torch.float32, "x")
+        self._flat(out, n, torch.float32 if to32 else torch.float64, "out")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_convert(self.h, n, to32, _ptr(x), _ptr(out)))
 
     def set_kernel_timing(self, enable: bool):
+        self.sync_stream()
         self._check(self.lib.nsmf_set_kernel_timing(self.h, 1 if enable else 0))
 
     def kernel_time(self):
         ms = ctypes.c_double()
         n = ctypes.c_int64()
+        self.sync_stream()
         self._check(self.lib.nsmf_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value

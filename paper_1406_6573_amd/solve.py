@@ -45,6 +45,10 @@ class SolveStats:
     linear_reductions: list = field(default_factory=list)
     krylov_iterations: list = field(default_factory=list)
     step_lengths: list = field(default_factory=list)
+    # per step: True when the accepted step met the sufficient-decrease test of the line search
+    sufficient_decrease: list = field(default_factory=list)
+    # set when no trial step lowered ||r||: the iterate was kept and the iteration stopped
+    stalled: bool = False
     seconds: float = 0.0
 
 
@@ -225,8 +229,10 @@ class NewtonKrylov:
             its, red = self.linear_solve(r, lin_tol)
             st.krylov_iterations.append(its)
             st.linear_reductions.append(red)
-            alpha = 1.0
-            for _ in range(max_backtrack + 1):               # backtracking on ||r||
+            alpha, ok = 1.0, False
+            for b in range(max_backtrack + 1):               # backtracking on ||r||
+                if b:
+                    alpha *= 0.5
                 eng.vec_axpby(1.0, x, 0.0, trial)
                 eng.vec_axpby(alpha, self.d64, 1.0, trial)
                 tu, tp = self.split(trial)
@@ -234,12 +240,22 @@ class NewtonKrylov:
                 self.residual_vec(r)
                 rt = self.norm(r)
                 if rt <= (1.0 - 1e-4 * alpha) * rn:
+                    ok = True
                     break
-                alpha *= 0.5
+            if not ok and not rt < rn:                        # no trial lowered ||r||: keep x and stop
+                xu, xp = self.split(x)
+                eng.set_state(xu, xp)
+                self.residual_vec(r)
+                st.stalled = True
+                if verbose:
+                    print(f"[newton {self.precision}] step {it + 1}: no step length down to {alpha} lowers "
+                          f"|r| = {rn:.6e}; stopping", flush=True)
+                break
             eng.vec_axpby(1.0, trial, 0.0, x)
             rn = rt
             st.newton_residuals.append(rn)
             st.step_lengths.append(alpha)
+            st.sufficient_decrease.append(ok)
             if verbose:
                 print(f"[newton {self.precision}] step {it + 1}: |r| = {rn:.6e}, krylov {its}, "
                       f"linear reduction {red:.2e}, alpha {alpha}", flush=True)

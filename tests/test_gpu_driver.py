@@ -106,10 +106,61 @@ def test_vector_kernels(torch_cuda):
         z = torch.empty_like(w)
         eng.vec_mul(d, w, z)
         assert torch.allclose(z.double(), d * w.double(), rtol=1e-6)
+        # b = 0: y is written without being read (BLAS convention), so NaN or Inf bits in an
+        # uninitialised y cannot leak into the result
+        y = torch.full_like(w, float("nan"))
+        y[::2] = float("inf")
+        eng.vec_axpby(-3.0, w, 0.0, y)
+        assert torch.equal(y, (-3.0 * w.double()).to(dt))
     x = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
     x32 = torch.empty(n, dtype=torch.float32, device="cuda")
     eng.vec_convert(x, x32)
     assert torch.equal(x32, x.float())
+    # mismatched tensors are refused in the binding before any device work
+    V = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    w = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h = torch.zeros(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        eng.vec_dots(V, 4, w, h)                                   # fewer rows than k
+    with pytest.raises(ValueError):
+        eng.vec_dots(V[:, : n - 1], 2, w, h)                       # rows shorter than w
+    with pytest.raises(ValueError):
+        eng.vec_gemv(V, 2, h.float(), 1.0, w)                      # h not float64
+    with pytest.raises(ValueError):
+        eng.vec_gemv(V, 2, h[:1], 1.0, w)                          # h shorter than k
+    with pytest.raises(ValueError):
+        eng.vec_axpby(1.0, w[:-1], 1.0, w)                         # x shorter than y
+    with pytest.raises(ValueError):
+        eng.vec_axpby(1.0, w.float(), 1.0, w)                      # dtype mismatch
+    with pytest.raises(ValueError):
+        eng.vec_mul(w.float(), w, w)                               # d not float64
+    with pytest.raises(ValueError):
+        eng.vec_convert(w, torch.empty(n - 1, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        eng.vec_axpby(1.0, w.cpu(), 1.0, w)                        # host tensor
+    eng.close()
+
+
+def test_calls_follow_the_current_stream(torch_cuda):
+    """Each call enqueues its work on torch's current stream at the time of the call: applies issued
+    on two different side streams, each followed by that stream's own synchronisation, give the same
+    results as on the default stream."""
+    torch = torch_cuda
+    eng, t = setup(torch, small_case(3))
+    xu, xp = (t(a) for a in small_case(3)["dirs"][0])
+    ref = [v.clone() for v in eng.jacobian_apply(xu, xp)]
+    torch.cuda.synchronize()
+    for _ in range(2):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            yu, yp = eng.jacobian_apply(xu, xp)
+            assert eng._stream == s.cuda_stream
+        s.synchronize()                    # only the side stream: its work must be the apply
+        assert torch.equal(yu, ref[0]) and torch.equal(yp, ref[1])
+    yu, yp = eng.jacobian_apply(xu, xp)
+    assert eng._stream == torch.cuda.current_stream().cuda_stream
+    torch.cuda.current_stream().synchronize()
+    assert torch.equal(yu, ref[0]) and torch.equal(yp, ref[1])
     eng.close()
 
 

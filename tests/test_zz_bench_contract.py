@@ -26,7 +26,7 @@ def test_multi_gpu_request_is_refused():
 
 @pytest.mark.gpu
 def test_bench_json_line():
-    r = run_bench("--steps", "3", "--warmup", "1", "--no-cpu-baseline")
+    r = run_bench("--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--no-extra")
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.strip().splitlines() if l.strip()]
     assert len(lines) == 1, r.stdout
