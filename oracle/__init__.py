@@ -19,7 +19,10 @@ What it computes, by definition (no sum factorisation, no blocking):
 * the basal Robin term and u.n = 0 by a component mask or by nodal frames
   (eq. (robin), eq. (weak));
 * global assembly A = sum_e R_e^T A_e R_e (Sec. 3.2.1) with scipy.sparse;
-* the residual VJP and the energy functional of the appendix.
+* the residual VJP and the energy functional of the appendix;
+* a solved state by Newton's method with direct sparse solves, and the adjoint
+  gradient of a functional of the solved state with respect to logA and beta
+  (Sec. 2.3), by a direct solve with the transposed Jacobian.
 
 Every function carries "parity unpinned" in its docstring where no
 independent pin exists; the pins live in ``tests/test_oracle_*.py``.
@@ -27,5 +30,6 @@ independent pin exists; the pins live in ``tests/test_oracle_*.py``.
 from .reference import ReferenceElement
 from .restriction import build_restriction
 from .stokes import StokesOracle
+from .adjoint import adjoint_gradient, newton_solve
 
-__all__ = ["ReferenceElement", "build_restriction", "StokesOracle"]
+__all__ = ["ReferenceElement", "build_restriction", "StokesOracle", "adjoint_gradient", "newton_solve"]

@@ -13,12 +13,23 @@ def terrain_geometry(nx, ny, nz, L):
     return geo
 
 
+def inclined_geometry(nx, ny, nz, L, a, b):
+    """Planar inclined base z = a x + b y under a thickness varying linearly in x and y."""
+    def geo(lg):
+        x, y = lg[:, 0] * L / nx, lg[:, 1] * L / ny
+        return np.stack([x, y, a * x + b * y + lg[:, 2] / nz * (1.0 + 0.004 * x - 0.003 * y)], 1)
+    return geo
+
+
 def small_case(k, mapped=False, frac=0.3, mask=True, seed=0, nx=4, ny=3, nz=2, L=40.0, body=(0.0, 0.0, 0.0),
-               pspace="P", refine_from=0, periodic=(False, False), frames=False):
-    """A seeded case with hanging faces and edges: mesh, parameters, state, directions."""
+               pspace="P", refine_from=0, periodic=(False, False), frames=False, incline=None):
+    """A seeded case with hanging faces and edges: mesh, parameters, state, directions.  incline = (a, b)
+    puts the mesh over the planar base z = a x + b y (column-mapped)."""
     rng = np.random.default_rng(1000 + 17 * k + seed)
     refined = random_refined_columns(nx, ny, frac, rng)
     geo = terrain_geometry(nx, ny, nz, L) if mapped else None
+    if incline is not None:
+        geo = inclined_geometry(nx, ny, nz, L, *incline)
     mesh = column_mesh(k, nx, ny, nz, refined=refined, extent=(L, L * ny / nx, 1.0), geometry=geo,
                        base_normal_dirichlet=mask and not frames, pspace=pspace, refine_from=refine_from,
                        periodic=periodic, base_frames=frames)

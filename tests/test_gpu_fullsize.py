@@ -1,17 +1,26 @@
 """Parity at the workloads' full sizes, on sampled outputs.
 
-The oracle assembles only the elements incident to a random sample of velocity rows and pressure
-elements (the rows are then exact), at the full mesh sizes and in the engine's production launch
-configuration; properties that hold at any size (FP32 vs FP64 over all rows, symmetry) cover the
-rest.  For the VJP workload, parameter gradients are also checked by central finite differences
-(h = 1e-6) of the engine's own residual.
+The oracle assembles only the elements of a few windows of whole columns (all layers) at the
+full mesh sizes; the rows of the nodes whose incident elements all lie in a window are then exact
+(every element whose restriction touches a node names it in its connectivity, hanging slots
+included), and so are the pressure rows of every window element.  The windows are chosen so that
+at least 2,000 velocity rows and 500 pressure rows are compared per workload, one of them placed on
+refined columns (hanging faces) where the workload has any.  The engine runs in the production
+launch configuration; FP64 rows must match to 1e-12 relative to (|K||x|)_i, FP32 rows to
+64 * 2^-24 and the BF16-operator rows to 16 * 2^-9 (the per-entry bounds of the small parity tests).
+Properties that hold at any size (FP32 vs FP64 over all rows) cover the rest.  For the VJP workload,
+parameter gradients are also checked by central finite differences (h = 1e-6) of the engine's own
+residual.
 """
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
-ROWS = {2: (400, 100), 3: (60, 16), 4: (300, 80), 5: (600, 150)}
+U32 = 2.0 ** -24
+MIN_VEL_ROWS, MIN_PRES_ROWS = 2000, 500
+# window side (coarse columns) per workload, and the number of windows
+WINDOWS = {2: (3, 3), 3: (3, 2), 4: (3, 3), 5: (3, 4)}
 # the workloads as stated (P_{k-1} pressure), and config 2 with the Q_{k-2} pair (Q3 x Q1, the pair of
 # the paper's large runs)
 CASES = [(2, "P"), (3, "P"), (4, "P"), (5, "P"), (2, "Q")]
@@ -25,13 +34,34 @@ def torch_cuda():
     return torch
 
 
-def sampled(mesh, rng, n_vel, n_pres):
-    nodes = rng.choice(mesh.n_nodes, n_vel, replace=False)
-    comps = rng.integers(0, 3, n_vel)
-    pel = rng.choice(mesh.n_el, n_pres, replace=False)
-    touch = np.isin(mesh.elem_nodes, nodes).any(axis=1)
-    elems = np.union1d(np.nonzero(touch)[0], pel)
-    return nodes, comps, pel, elems
+def coarse_columns(mesh):
+    """Coarse column (i, j) of every element (fine elements of refined columns map to their parent)."""
+    fine = mesh.elem_level == 1
+    ci = np.where(fine, mesh.elem_cell[:, 0] // 2, mesh.elem_cell[:, 0])
+    cj = np.where(fine, mesh.elem_cell[:, 1] // 2, mesh.elem_cell[:, 1])
+    return ci, cj
+
+
+def window_sample(mesh, rng, side, count):
+    """Elements of `count` windows of side x side coarse columns (one centred on a refined column when
+    there are any), the exactly computable velocity rows (nodes named only by window elements) and the
+    window elements (their pressure rows)."""
+    ci, cj = coarse_columns(mesh)
+    refined = np.argwhere(mesh.refined)
+    corners = []
+    if refined.shape[0]:
+        i, j = refined[rng.integers(refined.shape[0])]
+        corners.append((int(np.clip(i - side // 2, 0, mesh.nx - side)), int(np.clip(j - side // 2, 0, mesh.ny - side))))
+    while len(corners) < count:
+        corners.append((int(rng.integers(0, mesh.nx - side + 1)), int(rng.integers(0, mesh.ny - side + 1))))
+    inw = np.zeros(mesh.n_el, dtype=bool)
+    for (i0, j0) in corners:
+        inw |= (ci >= i0) & (ci < i0 + side) & (cj >= j0) & (cj < j0 + side)
+    elems = np.nonzero(inw)[0]
+    named_in = np.unique(mesh.elem_nodes[inw])
+    named_out = np.unique(mesh.elem_nodes[~inw])
+    nodes = np.setdiff1d(named_in, named_out, assume_unique=True)
+    return elems, nodes, corners
 
 
 @pytest.mark.parametrize("cfg,pspace", CASES)
@@ -61,15 +91,22 @@ def test_fullsize_sampled_parity(torch_cuda, cfg, pspace):
     e32 = float((full32 - full64).norm() / full64.norm())
     print(f"  fp32 vs fp64 over all {full64.numel()} rows: rel {e32:.2e}", flush=True)
     assert e32 < 1e-5
-    # sampled rows against the oracle
+    ybu, ybp = eng.jacobian_apply(t(xu).float(), t(xp).float(), "bf16ops")
+    # window rows against the oracle
     rng = np.random.default_rng(100 + cfg)
-    nodes, comps, pel, elems = sampled(m, rng, *ROWS[cfg])
+    side, count = WINDOWS[cfg]
+    elems, nodes, corners = window_sample(m, rng, side, count)
+    pel = elems
+    N = m.n_nodes
+    vrows = np.concatenate([c * N + nodes for c in range(3)])
+    prow = (pel[:, None] * m.n_p + np.arange(m.n_p)[None, :]).ravel()
+    print(f"  windows at {corners}: {len(elems)} elements, {vrows.size} velocity rows, {prow.size} pressure rows",
+          flush=True)
+    assert vrows.size >= MIN_VEL_ROWS and prow.size >= MIN_PRES_ROWS
+    if m.refined.any():
+        assert (m.cmask[elems] >> 3).any()          # hanging faces among the sampled elements
     o = StokesOracle(m, w.n, w.eps, w.B0, w.logA, w.beta, body=w.body, elems=elems)
     o.set_state(w.u, w.p)
-    print(f"  oracle on {len(elems)} incident elements", flush=True)
-    N = m.n_nodes
-    vrows = comps * N + nodes
-    prow = (pel[:, None] * m.n_p + np.arange(m.n_p)[None, :]).ravel()
     oru, orp = o.residual()
     K = o.jacobian()
     x = np.concatenate([xu.ravel(), xp.ravel()])
@@ -78,6 +115,14 @@ def test_fullsize_sampled_parity(torch_cuda, cfg, pspace):
     gy = np.concatenate([yu.cpu().numpy().ravel(), yp.cpu().numpy().ravel()])
     rows = np.concatenate([vrows, 3 * N + prow])
     e_j = np.max(np.abs(gy[rows] - oy[rows]) / sc[rows])
+    # mixed paths on the same rows, per entry against the FP64 oracle
+    g32 = np.concatenate([y32u.double().cpu().numpy().ravel(), y32p.double().cpu().numpy().ravel()])
+    gbf = np.concatenate([ybu.double().cpu().numpy().ravel(), ybp.double().cpu().numpy().ravel()])
+    e_32 = np.max(np.abs(g32[rows] - oy[rows]) / sc[rows])
+    e_bf = np.max(np.abs(gbf[rows] - oy[rows]) / sc[rows])
+    print(f"  window rows: FP32 scaled {e_32:.2e} (bound {64 * U32:.2e}), BF16 operators scaled {e_bf:.2e} "
+          f"(bound {16 * 2.0 ** -9:.2e})", flush=True)
+    assert e_32 < 64 * U32 and e_bf < 16 * 2.0 ** -9
     gr = np.concatenate([ru.cpu().numpy().ravel(), rp.cpu().numpy().ravel()])
     orr = np.concatenate([oru.ravel(), orp.ravel()])
     rmag = np.max(np.abs(orr[rows]))
@@ -95,7 +140,7 @@ def test_fullsize_sampled_parity(torch_cuda, cfg, pspace):
     Dw = 0.5 * (Gw + np.swapaxes(Gw, 2, 3))
     scale_A = np.sum(np.abs(o.W[pos] * o.mu[pos] * np.einsum("eqij,eqij->eq", o.D0[pos], Dw)), axis=1) / w.n
     e_a = np.max(np.abs(g_A.cpu().numpy()[pel] - og_A[pel]) / np.maximum(scale_A, 1e-300))
-    print(f"  sampled rows: J scaled {e_j:.2e}, residual {e_r:.2e}, VJP u,p scaled {e_v:.2e}, logA {e_a:.2e}",
+    print(f"  window rows: J scaled {e_j:.2e}, residual {e_r:.2e}, VJP u,p scaled {e_v:.2e}, logA {e_a:.2e}",
           flush=True)
     assert e_j < 1e-12 and e_r < 1e-12 and e_v < 1e-12 and e_a < 1e-12
     if m.n_bface and len(o.fid):

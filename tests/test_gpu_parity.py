@@ -164,6 +164,18 @@ def test_nodal_frames(torch_cuda, k):
     check_case(torch_cuda, case, f"nodal frames k={k}")
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_nodal_frames_inclined_base(torch_cuda, k):
+    """Planar inclined base z = 0.02 x - 0.015 y with hanging columns and u . n = 0 by nodal frames: the
+    mesh of the oracle's closed-form pin of the face measure and normal (the frames' normal is the
+    constant plane normal), through the full check."""
+    case = small_case(k, frac=0.4, frames=True, incline=(0.02, -0.015), body=(0.0, 0.1, -1.0))
+    m = case["mesh"]
+    nrm = np.array([-0.02, 0.015, 1.0]) / np.sqrt(1.0 + 0.02 ** 2 + 0.015 ** 2)
+    assert m.frame_nodes.shape[0] > 0 and np.allclose(m.frames[:, :, 2], nrm, atol=1e-9)
+    check_case(torch_cuda, case, f"nodal frames, inclined plane, k={k}")
+
+
 def test_nodal_frames_zface_qspace(torch_cuda):
     case = small_case(3, mapped=True, frac=0.4, frames=True, refine_from=1, pspace="Q")
     check_case(torch_cuda, case, "nodal frames, z-face hanging, k=3 Q_(k-2) pressure")

@@ -570,6 +570,83 @@ def test_mapped_volume_closed_form():
     assert abs(o.W.sum() - vol) < 1e-11 * vol
 
 
+def basal_blocks(o):
+    """sum over the basal elements of e_d^T A_e e_c (3x3) and the magnitude of the summands: the stress
+    part of A_e annihilates constant fields, so for beta = 1 only int_base (T e_c).(T e_d) remains."""
+    A, _ = o.element_matrices()
+    S = o.S
+    tot, mag = np.zeros((3, 3)), 0.0
+    for el in o.fl:
+        Ae = A[el].reshape(3, S, 3, S)
+        tot += Ae.sum(axis=(1, 3))
+        mag += np.abs(Ae).sum()
+    return tot, mag
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_basal_term_inclined_plane_closed_form(k):
+    """Column-mapped mesh over a planar inclined base z = a x + b y (with hanging columns), beta = 1:
+    the face measure integrates to the tilted area Lx Ly sqrt(1 + a^2 + b^2), the face normal is
+    (-a, -b, 1)/sqrt(1 + a^2 + b^2) at every face point, and sum over the basal blocks of
+    <e_d, M e_c> = area (delta_cd - n_c n_d) (eq. (robin), eq. (weak)).  A projected measure |cr_z|
+    or the reference normal e_z instead of the mapped one fails it."""
+    a, b, Lx, Ly, nx, ny, nz = 0.3, -0.2, 12.0, 9.0, 4, 3, 2
+
+    def geo(lg):
+        x, y = lg[:, 0] * Lx / nx, lg[:, 1] * Ly / ny
+        H = 1.0 + 0.02 * x - 0.01 * y
+        return np.stack([x, y, a * x + b * y + lg[:, 2] / nz * H], 1)
+
+    mesh = hanging_mesh(k, seed=3, nx=nx, ny=ny, nz=nz, frac=0.35, geometry=geo)
+    assert (mesh.cmask >> 3).any()                     # hanging faces present
+    o = StokesOracle(mesh, beta=np.ones(mesh.n_bface))
+    o.set_state(np.zeros((3, mesh.n_nodes)), np.zeros((mesh.n_el, mesh.n_p)))
+    s = np.sqrt(1.0 + a * a + b * b)
+    area = Lx * Ly * s
+    nrm = np.array([-a, -b, 1.0]) / s
+    assert abs(o.Wf.sum() - area) < 1e-12 * area
+    assert np.max(np.abs(o.fn - nrm)) < 1e-13
+    tot, mag = basal_blocks(o)
+    expect = area * (np.eye(3) - np.outer(nrm, nrm))
+    assert np.max(np.abs(tot - expect)) < 1e-13 * mag
+
+
+def test_basal_term_twisted_base_quadrature():
+    """Curved (doubly ruled) base z = c (x - x0)(y - y0), exactly reproduced by the Q_k map: the
+    basal blocks sum to int_base (I - n n^T) dS with the mapped normal n = (-z_x, -z_y, 1)/s and
+    dS = s dx dy, s = sqrt(1 + z_x^2 + z_y^2), here evaluated by adaptive 2D quadrature of the
+    closed-form integrand (scipy), independent of the oracle's face quadrature; agreement to the
+    (k+1)^2-point Gauss error on the smooth integrand."""
+    from scipy.integrate import dblquad
+    c, Lx, Ly, nx, ny, nz, k = 0.004, 20.0, 16.0, 4, 4, 2, 4
+    x0, y0 = 7.0, 5.0
+
+    def geo(lg):
+        x, y = lg[:, 0] * Lx / nx, lg[:, 1] * Ly / ny
+        return np.stack([x, y, c * (x - x0) * (y - y0) + lg[:, 2] / nz * 1.5], 1)
+
+    mesh = hanging_mesh(k, seed=5, nx=nx, ny=ny, nz=nz, frac=0.3, geometry=geo)
+    o = StokesOracle(mesh, beta=np.ones(mesh.n_bface))
+    o.set_state(np.zeros((3, mesh.n_nodes)), np.zeros((mesh.n_el, mesh.n_p)))
+
+    def integrand(i, j):
+        def f(y, x):
+            g = np.array([-c * (y - y0), -c * (x - x0), 1.0])
+            sc = np.linalg.norm(g)
+            n = g / sc
+            return ((1.0 if i == j else 0.0) - n[i] * n[j]) * sc
+        return f
+
+    expect = np.zeros((3, 3))
+    for i in range(3):
+        for j in range(i, 3):
+            expect[i, j] = expect[j, i] = dblquad(integrand(i, j), 0.0, Lx, 0.0, Ly, epsabs=1e-13, epsrel=1e-13)[0]
+    tot, mag = basal_blocks(o)
+    assert np.max(np.abs(tot - expect)) < 1e-9 * abs(expect).max()
+    # the normal varies over the base: a constant (reference) normal would miss the x-y coupling
+    assert abs(expect[0, 1]) > 1e-4 * abs(expect).max()
+
+
 # ---------------------------------------------------------------- P11 VJP closed forms / complex step
 def test_vjp_parameter_gradients_complex_step():
     mesh = hanging_mesh(2, seed=9, nx=3, ny=3, mask=True)
@@ -625,3 +702,46 @@ def test_dirichlet_rows():
     x2[m] += 5.0
     y2, _ = o.jacobian_apply(x2, np.zeros_like(p))
     assert np.allclose(y2[~m], y[~m], atol=1e-13 * np.abs(y).max())
+
+
+# ---------------------------------------------------------------- adjoint gradient (Sec. 2.3)
+def test_adjoint_gradient_matches_resolved_finite_differences():
+    """Phi(u) = 1/2 |u - u_obs|^2 at the solved state: the oracle's adjoint gradient (direct solve with
+    J_c^T, then the parameter VJP) equals central differences (h = 1e-6) of Phi at states re-solved by
+    Newton's method, for entries of logA and beta.  A wrong sign, a missing transpose of a
+    nonsymmetric part or an unsolved state would break it."""
+    from oracle import adjoint_gradient, newton_solve
+    rng = np.random.default_rng(21)
+    L, nx, nz = 20.0, 2, 1
+
+    def geo(lg):
+        x, y = lg[:, 0] * L / nx, lg[:, 1] * L / nx
+        return np.stack([x, y, 0.05 * np.sin(2 * np.pi * x / L) + lg[:, 2] / nz * (1.0 + 0.1 * np.cos(2 * np.pi * y / L))], 1)
+
+    mesh = hanging_mesh(2, seed=2, nx=nx, ny=nx, nz=nz, frac=0.5, mask=True, geometry=geo)
+    logA = rng.normal(0, 0.5, mesh.n_el)
+    beta = np.exp(rng.normal(0, 1, mesh.n_bface))
+    body = (0.0, 0.0, -1.0)
+    u0 = 0.1 * rng.uniform(-1, 1, (3, mesh.n_nodes))
+    p0 = np.zeros((mesh.n_el, mesh.n_p))
+    u_obs = rng.uniform(-1, 1, (3, mesh.n_nodes))
+
+    def solve(la, be):
+        o = StokesOracle(mesh, 3.0, 1e-10, 0.5, la, be, body=body)
+        u, p, hist = newton_solve(o, u0, p0, tol=1e-14)
+        assert hist[-1] <= 1e-12 * hist[0]
+        return o, u, p
+
+    o, u, p = solve(logA, beta)
+    gA, gB, _, _ = adjoint_gradient(o, u - u_obs)
+    phi = lambda v: 0.5 * np.sum((v - u_obs) ** 2)
+    h = 1e-6
+    for kind, idx in (("logA", 0), ("logA", mesh.n_el - 1), ("beta", 0), ("beta", mesh.n_bface - 1)):
+        vals = []
+        for sgn in (1.0, -1.0):
+            la, be = logA.copy(), beta.copy()
+            (la if kind == "logA" else be)[idx] += sgn * h
+            vals.append(phi(solve(la, be)[1]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        ad = (gA if kind == "logA" else gB)[idx]
+        assert abs(fd - ad) < 1e-6 * abs(ad) + 1e-10 * phi(u), (kind, idx, fd, ad)
