@@ -44,7 +44,7 @@ struct nsmf_ctx {
   // mesh
   bool have_mesh = false;
   int k = 0, P = 0, n_p = 0, ps = PS_P, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0;
-  int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_inc = 0;
+  int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_inc = 0, n_ent = 0;
   HostTables tab;
   DevBuf<uint32_t> en, cmask;
   DevBuf<int32_t> bface_of, inc_ptr;   // node -> first entry of its segment of the element vector
@@ -101,6 +101,7 @@ struct nsmf_ctx {
     m.spos = spos.p;
     m.sslot = sslot.p;
     m.n_inc = n_inc;
+    m.n_ent = n_ent;
     m.n_el = n_el;
     m.n_nodes = n_nodes;
     m.nblocks = nblocks;
@@ -350,8 +351,9 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   if (!sorted_store) NSMF_TRY(ctx, ctx->pos.alloc(ipos.size()), "hipMalloc");
   NSMF_TRY(ctx, ctx->spos.alloc(spos.size()), "hipMalloc");
   NSMF_TRY(ctx, ctx->sslot.alloc(sslot.size()), "hipMalloc");
-  NSMF_TRY(ctx, ctx->ev.alloc((size_t)3 * n_inc), "hipMalloc");
   ctx->n_inc = n_inc;
+  ctx->n_ent = iptr[N];
+  NSMF_TRY(ctx, ctx->ev.alloc((size_t)3 * ctx->n_ent), "hipMalloc");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->en.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->cmask.p, m->cmask, n_el * 4, hipMemcpyHostToDevice, s), "copy");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->bface_of.p, bof.data(), n_el * 4, hipMemcpyHostToDevice, s), "copy");
@@ -517,7 +519,7 @@ int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p) {
            launch_residual(ctx->P, ctx->geo, ctx->ps, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->fst64.p,
                            ctx->beta64.p, ctx->p.p, ctx->prm.body, ctx->ev.p, r_p),
            "residual kernel");
-  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p,
+  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_ent, ctx->dmask.p,
                                 ctx->u.p, f_u, r_u),
            "assembly");
   return NSMF_OK;
@@ -549,7 +551,7 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
                         y_u ? (void *)ctx->ev.p : nullptr, y_p, 1.0 / ctx->prm.n, g_logA, g_beta),
            "apply kernel");
   if (y_u)
-    NSMF_TRY(ctx, launch_assemble(s, prec, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p,
+    NSMF_TRY(ctx, launch_assemble(s, prec, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_ent, ctx->dmask.p,
                                   x_u, nullptr, y_u),
              "assembly");
   if (ctx->timing) {
@@ -576,7 +578,7 @@ int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p) {
            launch_diag(ctx->P, ctx->geo, ctx->ps, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->beta64.p,
                        ctx->ev.p, d_p),
            "diagonal kernel");
-  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_inc, ctx->dmask.p, nullptr,
+  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_ent, ctx->dmask.p, nullptr,
                                 nullptr, d_u),
            "assembly");
   if (invert) {

@@ -89,7 +89,8 @@ struct MeshView {
   const int32_t *pos;
   const int32_t *spos;
   const uint16_t *sslot;
-  int64_t n_el, n_nodes, n_inc;
+  int64_t n_el, n_nodes, n_inc;   // n_inc = n_el P^3 element slots
+  int64_t n_ent;                  // stored entries of the element vector per component (its plane stride)
   int nblocks;
 };
 
@@ -147,7 +148,7 @@ inline bool zline_run_host(uint32_t cm, int P, int i, int j, int &lo, int &hi) {
   hi = (((f >> 5) & 1u) || edge(0, j, P - 1) || edge(1, i, P - 1)) ? P - 2 : P - 1;
   return true;
 }
-hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
+hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_ent,
                            const uint8_t *dm, const void *xm, const void *f, void *y);
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);
 hipError_t launch_f2d(hipStream_t s, const float *in, double *out, int64_t n);

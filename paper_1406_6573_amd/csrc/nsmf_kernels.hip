@@ -719,7 +719,7 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
     for (int z = 0; z < P; ++z) {
       if (pos[z] < 0) continue;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ev[c * m.n_inc + pos[z]] = (z == P - 1 && take_up) ? v[c][z] + up[c] : v[c][z];
+      for (int c = 0; c < 3; ++c) ev[c * m.n_ent + pos[z]] = (z == P - 1 && take_up) ? v[c][z] + up[c] : v[c][z];
     }
   } else {
     static_assert(3 * EP3 <= E * Ws<T, P>::ES, "staging area exceeds the block workspace");
@@ -743,7 +743,7 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
         const int below = sl - (P - 1) * E * P2 + P2;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          ev[c * m.n_inc + pos] = (code & 0x8000) ? stage[c * EP3 + sl] + stage[c * EP3 + below] : stage[c * EP3 + sl];
+          ev[c * m.n_ent + pos] = (code & 0x8000) ? stage[c * EP3 + sl] + stage[c * EP3 + below] : stage[c * EP3 + sl];
       }
     }
   }
@@ -1710,7 +1710,7 @@ constexpr int ASM_TILE = 4 * ASM_NT;
 // thread sums its own node's segment from LDS in increasing slot order.
 template <typename T>
 __global__ void __launch_bounds__(ASM_NT)
-k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_inc,
+k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_ent,
            const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f, T *__restrict__ y) {
   __shared__ T tile[3][ASM_TILE];
   const int64_t n0 = (int64_t)blockIdx.x * ASM_NT;
@@ -1731,8 +1731,8 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
       const int j = (int)threadIdx.x + u * ASM_NT;
       const bool in = j < cn;
       a[0][u] = in ? ev[c0 + j] : T(0);
-      a[1][u] = in ? ev[n_inc + c0 + j] : T(0);
-      a[2][u] = in ? ev[2 * n_inc + c0 + j] : T(0);
+      a[1][u] = in ? ev[n_ent + c0 + j] : T(0);
+      a[2][u] = in ? ev[2 * n_ent + c0 + j] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
@@ -1771,13 +1771,13 @@ __global__ void k_d2f(const double *in, float *out, int64_t n) {
 
 static inline int grid1(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 
-hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_inc,
+hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_ent,
                            const uint8_t *dm, const void *xm, const void *f, void *y) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const double *)ev, n_inc,
+    hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const double *)ev, n_ent,
                        dm, (const double *)xm, (const double *)f, (double *)y);
   else
-    hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev, n_inc, dm,
+    hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev, n_ent, dm,
                        (const float *)xm, (const float *)f, (float *)y);
   return hipGetLastError();
 }
