@@ -602,31 +602,30 @@ def test_adjoint_gradient_matches_finite_differences(torch_cuda):
 
 
 def test_adjoint_gradient_matches_oracle(torch_cuda):
-    """The engine's adjoint gradient (FGMRES solve with J_c, then the residual VJP) against the oracle's
-    (direct sparse solve with J_c^T, then the oracle's VJP) at the same solved state, for
-    Phi(u) = 1/2 |u - u_obs|^2, over every entry of dPhi/dlogA and dPhi/dbeta."""
+    """The engine's adjoint gradient (restarted FGMRES solve with J_c, then the residual VJP) against the
+    oracle's (direct sparse solve with J_c^T, then the oracle's VJP) at the same state -- solved by the
+    oracle's Newton iteration with direct solves -- for Phi(u) = 1/2 |u - u_obs|^2, over every entry of
+    dPhi/dlogA and dPhi/dbeta."""
     torch = torch_cuda
-    from oracle import StokesOracle, adjoint_gradient as oracle_adjoint
+    from oracle import StokesOracle, adjoint_gradient as oracle_adjoint, newton_solve
     from paper_1406_6573_amd import Engine
     from paper_1406_6573_amd.solve import NewtonKrylov, adjoint_gradient
     case = small_case(3, mapped=True, nx=3, ny=2, nz=2, frac=0.4, L=30.0, body=(0.0, 0.0, -1.0))
     m = case["mesh"]
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=case["body"])
+    uh, ph, hist = newton_solve(o, case["u"], case["p"], tol=1e-13)
+    assert hist[-1] <= 1e-12 * hist[0]
+    rng = np.random.default_rng(11)
+    u_obs = rng.uniform(-1, 1, (3, m.n_nodes))
+    oA, oB, _, _ = oracle_adjoint(o, uh - u_obs)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     eng = Engine()
     eng.upload_mesh(m)
     eng.set_params(case["n"], case["eps"], case["B0"], case["body"], t(case["logA"]), t(case["beta"]))
-    nk = NewtonKrylov(eng, restart=60, precision="fp64", precond="line", triangular=True)
-    u, p = t(case["u"]), t(case["p"])
-    st = nk.solve(u, p, n_newton=12, lin_tol=1e-13)
-    assert st.newton_residuals[-1] < 1e-10 * st.newton_residuals[0] + 1e-12
-    rng = np.random.default_rng(11)
-    u_obs = t(rng.uniform(-1, 1, (3, m.n_nodes)))
-    gA, gB, its, red = adjoint_gradient(nk, u, p, u - u_obs)
+    nk = NewtonKrylov(eng, restart=60, precision="fp64", precond="line", triangular=True, refine=20)
+    u, p = t(uh), t(ph)
+    gA, gB, its, red = adjoint_gradient(nk, u, p, u - t(u_obs), tol=1e-12)
     assert red < 1e-10
-    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=case["body"])
-    uh, ph = u.cpu().numpy(), p.cpu().numpy()
-    o.set_state(uh, ph)
-    oA, oB, _, _ = oracle_adjoint(o, uh - u_obs.cpu().numpy())
     eA, eB = rel_err(gA.cpu().numpy(), oA), rel_err(gB.cpu().numpy(), oB)
     mA = np.max(np.abs(gA.cpu().numpy() - oA)) / np.max(np.abs(oA))
     mB = np.max(np.abs(gB.cpu().numpy() - oB)) / np.max(np.abs(oB))
