@@ -172,6 +172,22 @@ int nsmf_residual(nsmf_ctx *ctx, const double *f_u, double *r_u, double *r_p);
  * x and y must not overlap. */
 int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p);
 
+/* Allocation-free variant of nsmf_jacobian_apply, for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same result, same kernels: y = J_c x.  The per-node partial sums
+ * that nsmf_jacobian_apply keeps in the context's element vector are kept instead in a
+ * library-wide device array of 64 MiB (one copy per GPU, held until the process ends), whose
+ * device address nsmf_create resolves once per device; the call itself allocates nothing (no
+ * hipMalloc, hipFree, events or library allocation).  The mesh must fit: 3 * (stored entries) *
+ * (8 bytes for NSMF_FP64, 4 otherwise) <= 64 MiB, else NSMF_EINVAL with the sizes in
+ * nsmf_last_error (e.g. the slab 64x64x8 Q3 workload fits in FP32, not in FP64).  All calls on
+ * one GPU share the array and it keeps the last call's contents (nothing has to start at zero:
+ * every entry is written before it is read): calls that may overlap on one GPU -- contexts on
+ * different streams or threads -- race and must be serialised by the caller.  Not counted by
+ * nsmf_set_kernel_timing.  Errors: NSMF_EINVAL (NULL vector, prec out of range, mesh too large),
+ * NSMF_ESTATE (no state), NSMF_EHIP. */
+int nsmf_jacobian_apply_noalloc(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p);
+
 /* Vector-Jacobian product of the residual at the state for cotangent w = (w_u, w_p).
  * Sec. 2.3: the adjoint (transposed) linearisation of eq. (weak) uses the same fourth-order
  * tensor of eq. (rank4) as the Newton step, and A(u) is symmetric (Sec. 4.1), so

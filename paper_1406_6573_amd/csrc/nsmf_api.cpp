@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,33 @@ template <typename T> struct DevBuf {
   }
 };
 
+// Scratch of the allocation-free Jacobian apply (nsmf_jacobian_apply_noalloc): the element vector
+// (per-node partial sums) of one apply lives in this file-scope device array instead of the
+// context's allocation.  Every device that loads the library holds its own copy, at its own
+// address, until the process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in symbol): the device address is looked up once per device with
+// hipGetSymbolAddress in nsmf_create, with that device current, and kept in scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device (hip_device), looked up on the
+// first call for that device.
+hipError_t scratch_address(int hip_device, void **out) {
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (hip_device < 0 || hip_device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  if (scratch_ptr[hip_device] == nullptr) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[hip_device] = ptr;
+  }
+  *out = scratch_ptr[hip_device];
+  return hipSuccess;
+}
+
 int launch_threads(int P) { return P == 5 ? Launch<5>::NT : (P == 4 ? Launch<4>::NT : Launch<3>::NT); }
 int launch_elems(int P) { return P == 5 ? Launch<5>::E : (P == 4 ? Launch<4>::E : Launch<3>::E); }
 
@@ -40,6 +68,7 @@ int launch_elems(int P) { return P == 5 ? Launch<5>::E : (P == 4 ? Launch<4>::E 
 struct nsmf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  void *scratch = nullptr;   // this device's address of the allocation-free apply's scratch array
   std::string err = "";
   // mesh
   bool have_mesh = false;
@@ -141,8 +170,11 @@ int nsmf_create(nsmf_ctx **out, int hip_device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return NSMF_EINVAL;
   if (hipSetDevice(hip_device) != hipSuccess) return NSMF_EHIP;
+  void *scr = nullptr;
+  if (scratch_address(hip_device, &scr) != hipSuccess || scr == nullptr) return NSMF_EHIP;
   nsmf_ctx *c = new nsmf_ctx();
   c->device = hip_device;
+  c->scratch = scr;
   *out = c;
   return NSMF_OK;
 }
@@ -563,6 +595,36 @@ static int apply_common(nsmf_ctx *ctx, int prec, bool vjp, const void *x_u, cons
 
 int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p) {
   return apply_common(ctx, prec, false, x_u, x_p, y_u, y_p, nullptr, nullptr);
+}
+
+int nsmf_jacobian_apply_noalloc(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p) {
+  if (!ctx || !x_u || !x_p || !y_u || !y_p) return NSMF_EINVAL;
+  if (prec < 0 || prec > 2) return ctx->fail(NSMF_EINVAL, "precision must be 0, 1 or 2");
+  if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "Jacobian apply needs a state");
+  const size_t word = prec == 0 ? sizeof(double) : sizeof(float);
+  const size_t need = (size_t)3 * (size_t)ctx->n_ent * word;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return ctx->fail(NSMF_EINVAL, "allocation-free apply: the mesh needs " + std::to_string(need) +
+                                      " bytes of partial sums, the scratch array holds " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES));
+  if (ctx->scratch == nullptr) return ctx->fail(NSMF_EHIP, "scratch array address not resolved");
+  hipStream_t s = ctx->stream;
+  GeoView<double> g64 = ctx->geo64();
+  GeoView<float> g32 = ctx->geo32();
+  const void *gv = prec == 0 ? (const void *)&g64 : (const void *)&g32;
+  const void *st = prec == 0 ? (const void *)ctx->st64.p : (const void *)ctx->st32.p;
+  const void *fst = prec == 0 ? (const void *)ctx->fst64.p : (const void *)ctx->fst32.p;
+  const void *beta = prec == 0 ? (const void *)ctx->beta64.p : (const void *)ctx->beta32.p;
+  // every entry of the element vector is written by exactly one element slot before the assembly
+  // reads it, so the scratch needs no clearing
+  NSMF_TRY(ctx,
+           launch_apply(ctx->P, ctx->geo, ctx->ps, prec, false, s, ctx->mesh_view(), gv, ctx->tabs.p, st, fst, beta, x_u,
+                        x_p, ctx->scratch, y_p, 1.0 / ctx->prm.n, nullptr, nullptr),
+           "apply kernel");
+  NSMF_TRY(ctx, launch_assemble(s, prec, ctx->n_nodes, ctx->inc_ptr.p, ctx->scratch, ctx->n_ent, ctx->dmask.p, x_u,
+                                nullptr, y_u),
+           "assembly");
+  return NSMF_OK;
 }
 
 int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,

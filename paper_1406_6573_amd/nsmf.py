@@ -26,7 +26,8 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_set_state", "nsmf_residual", "nsmf_jacobian_apply", "nsmf_residual_vjp", "nsmf_query",
             "nsmf_geometry_kind", "nsmf_set_kernel_timing", "nsmf_kernel_time", "nsmf_last_error",
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
-            "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization"]
+            "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization",
+            "nsmf_jacobian_apply_noalloc"]
 
 
 class NsmfError(RuntimeError):
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_set_state.argtypes = [vp, vp, vp]
     lib.nsmf_residual.argtypes = [vp, vp, vp, vp]
     lib.nsmf_jacobian_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.nsmf_jacobian_apply_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     lib.nsmf_residual_vjp.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
     lib.nsmf_query.argtypes = [vp, i64p, i64p, i64p, i64p, i64p]
     lib.nsmf_geometry_kind.argtypes = [vp]
@@ -256,6 +258,20 @@ class Engine:
         self.sync_stream()
         self._check(self.lib.nsmf_jacobian_apply(self.h, prec, _ptr(x_u), _ptr(x_p), _ptr(out[0]), _ptr(out[1])))
         return out
+
+    def jacobian_apply_noalloc(self, x_u, x_p, out, prec="fp64"):
+        """y = J_c x through the allocation-free entry point: the partial sums live in the library's
+        per-GPU scratch array; the caller provides the outputs `out` = (y_u, y_p)."""
+        prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        dt = self._dtype(prec)
+        sz = self.sizes
+        x_u = self._vec(x_u, (3, sz["n_nodes"]), dt, "x_u")
+        x_p = self._vec(x_p, (sz["n_el"], sz["n_p"]), dt, "x_p")
+        y_u = self._vec(out[0], (3, sz["n_nodes"]), dt, "y_u")
+        y_p = self._vec(out[1], (sz["n_el"], sz["n_p"]), dt, "y_p")
+        self.sync_stream()
+        self._check(self.lib.nsmf_jacobian_apply_noalloc(self.h, prec, _ptr(x_u), _ptr(x_p), _ptr(y_u), _ptr(y_p)))
+        return y_u, y_p
 
     def residual_vjp(self, w_u, w_p, prec="fp64", want=("u", "p", "logA", "beta")):
         torch = self.torch
