@@ -105,7 +105,9 @@ def run_newton(args, w, dev, n_newton=5, restart=50):
         eng.set_params(w.n, w.eps, w.B0, w.body, t(w.logA), t(w.beta))
         u, p = t(w.u), t(w.p)
         nk = NewtonKrylov(eng, restart=restart, precision=prec, refine=1, precond=args.precond,
-                          triangular=not args.block_diagonal, linearization=args.linearization)
+                          triangular=not args.block_diagonal, linearization=args.linearization,
+                          coarse=(m, (args.coarse, args.coarse)) if args.coarse > 0 else None,
+                          coarse_mode=args.coarse_mode)
         st = nk.solve(u, p, n_newton=n_newton, lin_tol=1e-8, verbose=True)
         out[prec] = dict(seconds=st.seconds, newton_residuals=st.newton_residuals,
                          linear_reductions=st.linear_reductions, krylov_iterations=st.krylov_iterations,
@@ -114,15 +116,17 @@ def run_newton(args, w, dev, n_newton=5, restart=50):
         del nk
         torch.cuda.empty_cache()
     a, b = np.array(out["fp64"]["newton_residuals"]), np.array(out["mixed"]["newton_residuals"])
-    pc = {"jacobi": "point-Jacobi", "line": "vertical-line-block"}[args.precond] + " velocity block, " + \
-        ("block-diagonal" if args.block_diagonal else "block upper-triangular")
+    pc = {"jacobi": "point-Jacobi", "line": "vertical-line-block"}[args.precond] + \
+        (f" + F~ coarse correction ({args.coarse}x{args.coarse} lattice, {args.coarse_mode})" if args.coarse > 0 else "") + \
+        " velocity block, " + ("block-diagonal" if args.block_diagonal else "block upper-triangular")
     steps = "Newton" if args.linearization == "newton" else "Picard"
     rec = {"metric": f"Newton-Krylov solve: 5 {steps} steps x FGMRES(50), {pc}, FP64 vs mixed",
            "value": out["fp64"]["seconds"] / out["mixed"]["seconds"], "unit": "speedup mixed vs fp64",
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": f"config{args.config}", "n_dof": m.n_dof, "n_el": m.n_el, "k": m.k,
                       "preconditioner": args.precond, "triangular": not args.block_diagonal,
-                      "linearization": args.linearization},
+                      "linearization": args.linearization, "coarse_cells": args.coarse,
+                      "coarse_mode": args.coarse_mode},
            "residual_reduction_fp64": float(a[-1] / a[0]), "residual_reduction_mixed": float(b[-1] / b[0]),
            "max_rel_diff_newton_residuals": float(np.max(np.abs(a - b) / a)), "fp64": out["fp64"],
            "mixed": out["mixed"]}
@@ -151,7 +155,9 @@ def run_solve(args, w, dev, target=1e-6, inner_tol=1e-3, max_cycles=10, restart=
     out = {}
     for prec in ("fp64", "mixed"):
         nk = NewtonKrylov(eng, restart=restart, precision=prec, refine=1, precond=args.precond,
-                          triangular=not args.block_diagonal)
+                          triangular=not args.block_diagonal,
+                          coarse=(m, (args.coarse, args.coarse)) if args.coarse > 0 else None,
+                          coarse_mode=args.coarse_mode)
         d = torch.zeros_like(b)
         r = torch.empty_like(b)
         b32 = torch.empty(nk.n, dtype=torch.float32, device=dev) if prec == "mixed" else None
@@ -185,15 +191,17 @@ def run_solve(args, w, dev, target=1e-6, inner_tol=1e-3, max_cycles=10, restart=
               file=sys.stderr, flush=True)
         del nk
     eng.close()
-    pc = {"jacobi": "point-Jacobi", "line": "vertical-line-block"}[args.precond] + " velocity block, " + \
-        ("block-diagonal" if args.block_diagonal else "block upper-triangular")
+    pc = {"jacobi": "point-Jacobi", "line": "vertical-line-block"}[args.precond] + \
+        (f" + F~ coarse correction ({args.coarse}x{args.coarse} lattice, {args.coarse_mode})" if args.coarse > 0 else "") + \
+        " velocity block, " + ("block-diagonal" if args.block_diagonal else "block upper-triangular")
     rec = {"metric": f"Linear solve J d = b to relative residual {target:g}: FGMRES({restart}) cycles on the FP64 "
                      f"residual, {pc}, FP64 vs mixed",
            "value": out["fp64"]["seconds"] / out["mixed"]["seconds"], "unit": "speedup mixed vs fp64",
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": f"config{args.config}", "n_dof": m.n_dof, "n_el": m.n_el, "k": m.k,
                       "pressure": args.pspace, "preconditioner": args.precond,
-                      "triangular": not args.block_diagonal},
+                      "triangular": not args.block_diagonal, "coarse_cells": args.coarse,
+                      "coarse_mode": args.coarse_mode},
            "reached_fp64": out["fp64"]["residual_history"][-1] <= target,
            "reached_mixed": out["mixed"]["residual_history"][-1] <= target,
            "fp64": out["fp64"], "mixed": out["mixed"]}
@@ -301,6 +309,11 @@ def main():
                     help="block-diagonal instead of block upper-triangular preconditioner (with --newton)")
     ap.add_argument("--linearization", choices=["newton", "picard"], default="newton",
                     help="operator of the nonlinear steps (with --newton)")
+    ap.add_argument("--coarse", type=int, default=0,
+                    help="with --newton/--solve: add the F~-based horizontal coarse correction on a lattice of this "
+                         "many cells per direction (0: none)")
+    ap.add_argument("--coarse-mode", choices=["mult", "add"], default="mult",
+                    help="coarse correction combined with the line blocks multiplicatively or additively")
     ap.add_argument("--solve", action="store_true",
                     help="time a linear solve to 1e-6 at the workload's state, FP64 vs mixed, instead of the applies")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,

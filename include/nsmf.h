@@ -213,6 +213,38 @@ int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p,
  * preconditioner's action).  Requires a state. */
 int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p);
 
+/* Low-order approximation of the velocity block on the Gauss-Lobatto sub-grid (Sec. 5, "Construction
+ * of low-order approximation F~"), the matrix the paper builds its velocity preconditioner from:
+ *   y_u = J~_c x_u,  J~_c = P Q^T F~ Q P + (I - P),  F~ = sum_e R_e^T F~_e R_e,
+ * where F~_e treats the element's (k+1)^3 nodes as corners of k^3 trilinear sub-cells and integrates
+ * the bilinear form of F (the tensor of eq. (rank4), or the Picard operator; the basal term of
+ * eq. (robin)) on them with the 2-point Gauss-Lobatto rule per direction (the paper's F~_GL: the
+ * quadrature points are the element's nodes, and the basal term is lumped on the base nodes).  The
+ * coefficients mu, (n-1)/(2n) mu/(II+eps) and D(u) are taken at each node from the high-order state
+ * differentiated inside the element (computed on the first call after nsmf_set_state); R_e is the
+ * high-order restriction (figure "interp" (a) at nonconforming faces).  FP64; x_u, y_u [3][n_nodes]
+ * DEVICE doubles, not overlapping; Q, P as for the Jacobian.  Requires a state.
+ * Errors: NSMF_EINVAL, NSMF_ESTATE, NSMF_EHIP. */
+int nsmf_lowo_apply(nsmf_ctx *ctx, const double *x_u, double *y_u);
+
+/* Horizontal coarse space of a two-level velocity preconditioner (a plain stand-in for the coarse
+ * levels of the paper's AMG on F~, Sec. 4.2 and Sec. 5; the vertical-line blocks act as the smoother).
+ * A coarse function is, per velocity component, the bilinear hat of one point of a coarse lattice in
+ * (x, y) times one of three profiles in the node's relative height zeta: 1 - zeta, zeta,
+ * 4 zeta (1 - zeta).  Coarse vectors are DEVICE doubles [3][n_cpts][3] (component, lattice point,
+ * profile).  nsmf_coarse_setup copies, per node, the 4 lattice points of its coarse cell node_cpt
+ * [n_nodes][4], their bilinear weights node_w [n_nodes][4] and zeta node_zeta [n_nodes] in [0, 1]
+ * (host arrays; the caller defines the lattice); it synchronises.
+ *   nsmf_coarse_prolong:  x_u = P_mask (P_c xc), masked components 0 (x_u double for prec 0, float for 1);
+ *   nsmf_coarse_restrict: rc = P_c^T P_mask r_u (FP64 accumulation in a fixed order; r_u double or float).
+ * With A_c = P_c^T J~_c P_c (e.g. probed with nsmf_lowo_apply) the coarse correction is
+ * P_c A_c^-1 P_c^T.  Errors: NSMF_EINVAL (sizes, indices, zeta), NSMF_ESTATE (no mesh / no coarse space),
+ * NSMF_EUNSUP (mesh with nodal frames), NSMF_EHIP. */
+int nsmf_coarse_setup(nsmf_ctx *ctx, int64_t n_cpts, const int32_t *node_cpt, const double *node_w,
+                      const double *node_zeta);
+int nsmf_coarse_prolong(nsmf_ctx *ctx, int prec, const double *xc, void *x_u);
+int nsmf_coarse_restrict(nsmf_ctx *ctx, int prec, const void *r_u, double *rc);
+
 /* Vertical-line block preconditioner for the velocity block (a plain fallback beside the
  * block-diagonal preconditioner of Sec. 4.2, whose AMG for F is not part of this engine).
  * The mesh's nodes form vertical lines: chains linked through the z-lines of the elements

@@ -20,6 +20,9 @@ What it computes, by definition (no sum factorisation, no blocking):
   (eq. (robin), eq. (weak));
 * global assembly A = sum_e R_e^T A_e R_e (Sec. 3.2.1) with scipy.sparse;
 * the residual VJP and the energy functional of the appendix;
+* the low-order approximation F~ of the velocity block on the Gauss-Lobatto
+  sub-grid (Sec. 5): trilinear sub-cells, 2-point Gauss-Lobatto quadrature,
+  nodal coefficients from the high-order state, assembled with R_e;
 * a solved state by Newton's method with direct sparse solves, and the adjoint
   gradient of a functional of the solved state with respect to logA and beta
   (Sec. 2.3), by a direct solve with the transposed Jacobian.
@@ -31,5 +34,7 @@ from .reference import ReferenceElement
 from .restriction import build_restriction
 from .stokes import StokesOracle
 from .adjoint import adjoint_gradient, newton_solve
+from .loworder import low_order_matrix
 
-__all__ = ["ReferenceElement", "build_restriction", "StokesOracle", "adjoint_gradient", "newton_solve"]
+__all__ = ["ReferenceElement", "build_restriction", "StokesOracle", "adjoint_gradient", "newton_solve",
+           "low_order_matrix"]

@@ -99,6 +99,18 @@ struct nsmf_ctx {
   DevBuf<float> st32, fst32;
   // Krylov vector kernels: partial sums of the multi-dot products
   DevBuf<double> dot_partial;
+  // low-order approximation F~: node coordinates (kept from upload), periodic translations, and the
+  // nodal data of the current state (computed on first use after set_state)
+  DevBuf<double> xyz, lo;
+  double period[3] = {0.0, 0.0, 0.0};
+  bool have_lo = false;
+  bool has_frames = false;
+  // horizontal coarse space of the two-level velocity preconditioner: per node its coarse cell's corner
+  // points and bilinear weights and its relative height; per coarse point the list of its nodes
+  int64_t n_cpts = 0;
+  DevBuf<int32_t> c_cpt, c_node;
+  DevBuf<double> c_w, c_zeta, c_wt;
+  DevBuf<int64_t> c_ptr;
   // vertical node lines of the line-block preconditioner: chains of nodes linked through the
   // conforming z-lines of the elements (host arrays built at upload, copied at the first setup)
   bool lines_ok = false, have_lines = false;
@@ -144,6 +156,11 @@ struct nsmf_ctx {
     rot_of.free(); rot64.free(); rot32.free();
     logA.free(); beta64.free(); beta32.free();
     st64.free(); fst64.free(); u.free(); p.free(); st32.free(); fst32.free(); dot_partial.free();
+    xyz.free(); lo.free();
+    have_lo = false;
+    has_frames = false;
+    c_cpt.free(); c_node.free(); c_w.free(); c_zeta.free(); c_wt.free(); c_ptr.free();
+    n_cpts = 0;
     line_ptr.free(); line_node.free(); lptr.free(); lslot.free(); lbuf.free(); lfac64.free(); lfac32.free();
     h_line_ptr.clear(); h_line_node.clear(); h_lptr.clear(); h_lslot.clear();
     lines_ok = have_lines = false;
@@ -430,8 +447,9 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->tabs.alloc(tabset.size()), "hipMalloc");
   NSMF_TRY(ctx, hipMemcpyAsync(ctx->tabs.p, tabset.data(), tabset.size() * 8, hipMemcpyHostToDevice, s), "copy");
 
-  DevBuf<double> X;
+  DevBuf<double> &X = ctx->xyz;   // kept for the low-order approximation F~
   DevBuf<unsigned> flags;
+  for (int d = 0; d < 3; ++d) ctx->period[d] = m->period[d];
   NSMF_TRY(ctx, X.alloc(3 * N), "hipMalloc");
   NSMF_TRY(ctx, flags.alloc(1), "hipMalloc");
   NSMF_TRY(ctx, hipMemcpyAsync(X.p, m->coords, 3 * N * 8, hipMemcpyHostToDevice, s), "copy");
@@ -474,7 +492,6 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   if (ctx->geo == GEO_COLUMN) NSMF_TRY(ctx, launch_d2f(s, ctx->geo_qp64.p, ctx->geo_qp32.p, 4 * nqp), "convert");
   NSMF_TRY(ctx, launch_d2f(s, ctx->face64.p, ctx->face32.p, (size_t)NB * 4 * P2), "convert");
   NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry");
-  X.free();
 
   // per-point state: FP64 mu', kappa, Sigma0 (8 values); FP32 mu', sqrt(kappa) Sigma0 (7 values)
   constexpr size_t NS64 = 8, NS32 = 7;
@@ -489,6 +506,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->logA.alloc(n_el), "hipMalloc");
   NSMF_TRY(ctx, ctx->beta64.alloc(NB > 0 ? NB : 1), "hipMalloc");
   NSMF_TRY(ctx, ctx->beta32.alloc(NB > 0 ? NB : 1), "hipMalloc");
+  ctx->has_frames = m->n_frames > 0;
   ctx->have_mesh = true;
   ctx->err = "";
   return NSMF_OK;
@@ -515,6 +533,7 @@ int nsmf_set_params(nsmf_ctx *ctx, const nsmf_params *prm, const double *logA, c
   ctx->have_params = true;
   ctx->have_state = false;
   ctx->have_lines = false;
+  ctx->have_lo = false;
   return NSMF_OK;
 }
 
@@ -524,6 +543,7 @@ int nsmf_set_linearization(nsmf_ctx *ctx, int kind) {
   ctx->lin = kind;
   ctx->have_state = false;
   ctx->have_lines = false;
+  ctx->have_lo = false;
   return NSMF_OK;
 }
 
@@ -540,6 +560,7 @@ int nsmf_set_state(nsmf_ctx *ctx, const double *u, const double *p) {
            "state kernel");
   ctx->have_state = true;
   ctx->have_lines = false;
+  ctx->have_lo = false;
   return NSMF_OK;
 }
 
@@ -630,6 +651,98 @@ int nsmf_jacobian_apply_noalloc(nsmf_ctx *ctx, int prec, const void *x_u, const 
 int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
                       double *g_logA, double *g_beta) {
   return apply_common(ctx, prec, true, w_u, w_p, g_u, g_p, g_logA, g_beta);
+}
+
+int nsmf_lowo_apply(nsmf_ctx *ctx, const double *x_u, double *y_u) {
+  if (!ctx || !x_u || !y_u) return NSMF_EINVAL;
+  if (!ctx->have_state) return ctx->fail(NSMF_ESTATE, "lowo_apply needs a state");
+  hipStream_t s = ctx->stream;
+  if (!ctx->have_lo) {
+    const size_t nlo = (size_t)NLOWO * ctx->nblocks * ctx->P * ctx->nt;
+    if (ctx->lo.n != nlo) NSMF_TRY(ctx, ctx->lo.alloc(nlo), "hipMalloc");
+    NSMF_TRY(ctx,
+             launch_lowo_coef(ctx->P, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->xyz.p, ctx->period, ctx->u.p,
+                              ctx->logA.p, ctx->prm.n, ctx->prm.eps, ctx->prm.B0, ctx->lin == NSMF_PICARD, ctx->lo.p),
+             "low-order coefficient kernel");
+    ctx->have_lo = true;
+  }
+  NSMF_TRY(ctx, launch_lowo(ctx->P, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->lo.p, ctx->beta64.p, x_u, ctx->ev.p),
+           "low-order kernel");
+  NSMF_TRY(ctx, launch_assemble(s, 0, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_ent, ctx->dmask.p, x_u, nullptr, y_u),
+           "assembly");
+  return NSMF_OK;
+}
+
+int nsmf_coarse_setup(nsmf_ctx *ctx, int64_t n_cpts, const int32_t *node_cpt, const double *node_w,
+                      const double *node_zeta) {
+  if (!ctx || !node_cpt || !node_w || !node_zeta) return NSMF_EINVAL;
+  if (!ctx->have_mesh) return ctx->fail(NSMF_ESTATE, "no mesh uploaded");
+  if (ctx->has_frames) return ctx->fail(NSMF_EUNSUP, "coarse space on a mesh with nodal frames");
+  const int64_t N = ctx->n_nodes;
+  if (n_cpts <= 0 || n_cpts > 0x7FFFFFFF / 16) return ctx->fail(NSMF_EINVAL, "n_cpts out of range");
+  std::vector<int64_t> cnt((size_t)n_cpts + 1, 0);
+  for (int64_t n = 0; n < N; ++n) {
+    if (!(node_zeta[n] >= 0.0 && node_zeta[n] <= 1.0)) return ctx->fail(NSMF_EINVAL, "node_zeta outside [0, 1]");
+    for (int j = 0; j < 4; ++j) {
+      const int32_t J = node_cpt[4 * n + j];
+      const double wv = node_w[4 * n + j];
+      if (J < 0 || J >= n_cpts) return ctx->fail(NSMF_EINVAL, "node_cpt entry out of range");
+      if (!std::isfinite(wv)) return ctx->fail(NSMF_EINVAL, "node_w entry not finite");
+      if (wv != 0.0) cnt[J + 1]++;
+    }
+  }
+  for (int64_t J = 0; J < n_cpts; ++J) cnt[J + 1] += cnt[J];
+  std::vector<int32_t> cnode((size_t)cnt[n_cpts]);
+  std::vector<double> cwt((size_t)cnt[n_cpts]);
+  {
+    std::vector<int64_t> next(cnt.begin(), cnt.end() - 1);
+    for (int64_t n = 0; n < N; ++n)
+      for (int j = 0; j < 4; ++j) {
+        const double wv = node_w[4 * n + j];
+        if (wv == 0.0) continue;
+        const int64_t k = next[node_cpt[4 * n + j]]++;
+        cnode[k] = (int32_t)n;
+        cwt[k] = wv;
+      }
+  }
+  hipStream_t s = ctx->stream;
+  NSMF_TRY(ctx, ctx->c_cpt.alloc(4 * N), "hipMalloc");
+  NSMF_TRY(ctx, ctx->c_w.alloc(4 * N), "hipMalloc");
+  NSMF_TRY(ctx, ctx->c_zeta.alloc(N), "hipMalloc");
+  NSMF_TRY(ctx, ctx->c_ptr.alloc(cnt.size()), "hipMalloc");
+  NSMF_TRY(ctx, ctx->c_node.alloc(cnode.size() > 0 ? cnode.size() : 1), "hipMalloc");
+  NSMF_TRY(ctx, ctx->c_wt.alloc(cwt.size() > 0 ? cwt.size() : 1), "hipMalloc");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->c_cpt.p, node_cpt, 4 * N * 4, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->c_w.p, node_w, 4 * N * 8, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->c_zeta.p, node_zeta, N * 8, hipMemcpyHostToDevice, s), "copy");
+  NSMF_TRY(ctx, hipMemcpyAsync(ctx->c_ptr.p, cnt.data(), cnt.size() * 8, hipMemcpyHostToDevice, s), "copy");
+  if (!cnode.empty()) {
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->c_node.p, cnode.data(), cnode.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->c_wt.p, cwt.data(), cwt.size() * 8, hipMemcpyHostToDevice, s), "copy");
+  }
+  NSMF_TRY(ctx, hipStreamSynchronize(s), "coarse setup");
+  ctx->n_cpts = n_cpts;
+  return NSMF_OK;
+}
+
+int nsmf_coarse_prolong(nsmf_ctx *ctx, int prec, const double *xc, void *x_u) {
+  if (!ctx || !xc || !x_u) return NSMF_EINVAL;
+  if (prec < 0 || prec > 1) return ctx->fail(NSMF_EINVAL, "precision must be 0 or 1");
+  if (ctx->n_cpts <= 0) return ctx->fail(NSMF_ESTATE, "no coarse space (nsmf_coarse_setup)");
+  NSMF_TRY(ctx, launch_prolong(ctx->stream, prec, ctx->n_nodes, ctx->n_cpts, ctx->c_cpt.p, ctx->c_w.p, ctx->c_zeta.p,
+                               ctx->dmask.p, xc, x_u),
+           "prolongation");
+  return NSMF_OK;
+}
+
+int nsmf_coarse_restrict(nsmf_ctx *ctx, int prec, const void *r_u, double *rc) {
+  if (!ctx || !r_u || !rc) return NSMF_EINVAL;
+  if (prec < 0 || prec > 1) return ctx->fail(NSMF_EINVAL, "precision must be 0 or 1");
+  if (ctx->n_cpts <= 0) return ctx->fail(NSMF_ESTATE, "no coarse space (nsmf_coarse_setup)");
+  NSMF_TRY(ctx, launch_restrict(ctx->stream, prec, ctx->n_nodes, ctx->n_cpts, ctx->c_ptr.p, ctx->c_node.p, ctx->c_wt.p,
+                                ctx->c_zeta.p, ctx->dmask.p, r_u, rc),
+           "restriction");
+  return NSMF_OK;
 }
 
 int nsmf_jacobi_diag(nsmf_ctx *ctx, int invert, double *d_u, double *d_p) {

@@ -129,4 +129,92 @@ hipError_t launch_f2d(hipStream_t s, const float *in, double *out, int64_t n) {
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------- horizontal coarse space
+// Coarse functions of the two-level velocity preconditioner: a bilinear hat of a coarse lattice point
+// in (x, y) times one of NCZ profiles in the node's relative height zeta (1 - zeta, zeta, 4 zeta (1 -
+// zeta)), per velocity component.  Coarse vectors are FP64 [3][n_cpts][NCZ].  Node n belongs to the
+// coarse cell whose corners are cpt[n][0..3] with bilinear weights w[n][0..3]; masked components are
+// zero (the coarse functions are prolongated into the Dirichlet-eliminated space).
+constexpr int NCZ = 3;
+__device__ __forceinline__ void zprof(double z, double (&l)[NCZ]) {
+  l[0] = 1.0 - z;
+  l[1] = z;
+  l[2] = 4.0 * z * (1.0 - z);
+}
+
+template <typename T>
+__global__ void k_prolong(int64_t N, int64_t nc, const int32_t *__restrict__ cpt, const double *__restrict__ cw,
+                          const double *__restrict__ zeta, const uint8_t *__restrict__ dm, const double *__restrict__ xc,
+                          T *__restrict__ x) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double l[NCZ];
+  zprof(zeta[n], l);
+  for (int c = 0; c < 3; ++c) {
+    double v = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      const double *p = xc + ((size_t)c * nc + cpt[4 * n + j]) * NCZ;
+      v += cw[4 * n + j] * (l[0] * p[0] + l[1] * p[1] + l[2] * p[2]);
+    }
+    x[(size_t)c * N + n] = dm[(size_t)c * N + n] ? T(0) : (T)v;
+  }
+}
+
+// rc[c][J][m] = sum over the nodes n of coarse point J (list cptr/cnode/cwt, fixed order) of
+// w_J(n) l_m(zeta_n) (P r)[c][n]: one block per coarse point, FP64 accumulation, fixed reduction order.
+constexpr int RST_NT = 256;
+template <typename T>
+__global__ void __launch_bounds__(RST_NT)
+k_restrict(int64_t N, int64_t nc, const int64_t *__restrict__ cptr, const int32_t *__restrict__ cnode,
+           const double *__restrict__ cwt, const double *__restrict__ zeta, const uint8_t *__restrict__ dm,
+           const T *__restrict__ r, double *__restrict__ rc) {
+  __shared__ double red[3 * NCZ][RST_NT];
+  const int64_t J = blockIdx.x;
+  double acc[3][NCZ] = {};
+  for (int64_t k = cptr[J] + threadIdx.x; k < cptr[J + 1]; k += RST_NT) {
+    const int32_t n = cnode[k];
+    double l[NCZ];
+    zprof(zeta[n], l);
+    const double wv = cwt[k];
+    for (int c = 0; c < 3; ++c) {
+      const double rv = dm[(size_t)c * N + n] ? 0.0 : (double)r[(size_t)c * N + n];
+      for (int m = 0; m < NCZ; ++m) acc[c][m] += wv * l[m] * rv;
+    }
+  }
+  for (int c = 0; c < 3; ++c)
+    for (int m = 0; m < NCZ; ++m) red[c * NCZ + m][threadIdx.x] = acc[c][m];
+  __syncthreads();
+  for (int h = RST_NT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int f = 0; f < 3 * NCZ; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3 * NCZ) {
+    const int c = threadIdx.x / NCZ, m = threadIdx.x % NCZ;
+    rc[((size_t)c * nc + J) * NCZ + m] = red[threadIdx.x][0];
+  }
+}
+
+hipError_t launch_prolong(hipStream_t s, int prec, int64_t N, int64_t nc, const int32_t *cpt, const double *cw,
+                          const double *zeta, const uint8_t *dm, const double *xc, void *x) {
+  if (N <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_prolong<double>, dim3(nblk(N)), dim3(BLAS_NT), 0, s, N, nc, cpt, cw, zeta, dm, xc, (double *)x);
+  else
+    hipLaunchKernelGGL(k_prolong<float>, dim3(nblk(N)), dim3(BLAS_NT), 0, s, N, nc, cpt, cw, zeta, dm, xc, (float *)x);
+  return hipGetLastError();
+}
+hipError_t launch_restrict(hipStream_t s, int prec, int64_t N, int64_t nc, const int64_t *cptr, const int32_t *cnode,
+                           const double *cwt, const double *zeta, const uint8_t *dm, const void *r, double *rc) {
+  if (nc <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_restrict<double>, dim3((unsigned)nc), dim3(RST_NT), 0, s, N, nc, cptr, cnode, cwt, zeta, dm,
+                       (const double *)r, rc);
+  else
+    hipLaunchKernelGGL(k_restrict<float>, dim3((unsigned)nc), dim3(RST_NT), 0, s, N, nc, cptr, cnode, cwt, zeta, dm,
+                       (const float *)r, rc);
+  return hipGetLastError();
+}
+
 }  // namespace nsmf

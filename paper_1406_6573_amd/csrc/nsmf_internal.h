@@ -48,6 +48,7 @@ template <typename T, int P> struct Tab {
                     // sqrt((2j+1)/2) P_j(g_q) (normalised Legendre, j < k); Q_{k-2} space,
                     // L[j][q] = lambda_j(g_q), the Lagrange basis on the k-1 Gauss points (j < k-1)
   T w[P];           // Gauss weights
+  T G[P][P];        // G[i][a] = l_a'(xi_i): derivative of the Lagrange basis at the Gauss-Lobatto nodes
 };
 
 // Pressure spaces (Sec. 3.2.2): P_{k-1} with normalised Legendre products, or Q_{k-2} with the
@@ -58,7 +59,7 @@ enum PSpace { PS_P = 0, PS_Q = 1 };
 struct HostTables {
   int P;
   double xi[5], g[5], w[5];
-  double B[5][5], D[5][5], I[2][5][5], L[4][5];
+  double B[5][5], D[5][5], I[2][5][5], L[4][5], G[5][5];
   int n_p;
 };
 void build_tables(int k, int pspace, HostTables *t);
@@ -119,6 +120,14 @@ hipError_t launch_residual(int P, int geo, int ps, hipStream_t s, const MeshView
 hipError_t launch_diag(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                        const double *st, const double *beta, double *ev, double *dp);
 hipError_t launch_fill(hipStream_t s, void *ptr, int64_t n_words32);
+// low-order approximation F~ on the Gauss-Lobatto sub-grid: nodal coefficients (once per state) and
+// the matrix-free action (element vector, assembled by launch_assemble)
+constexpr int NLOWO = 11;   // per element node: x_rel (3), mu, kappa', D0 (xx, yy, zz, xy, xz, yz)
+hipError_t launch_lowo_coef(int P, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                            const double *X, const double period[3], const double *u, const double *logA, double n,
+                            double eps, double B0, bool picard, double *lo);
+hipError_t launch_lowo(int P, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                       const double *lo, const double *beta, const double *x, double *ev);
 // vertical-line block preconditioner: element line blocks, node assembly, banded Cholesky
 hipError_t launch_lines(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                         const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
@@ -159,5 +168,10 @@ hipError_t launch_gemv(hipStream_t s, int prec, int64_t n, int k, const void *V,
                        double alpha, void *w);
 hipError_t launch_axpby(hipStream_t s, int prec, int64_t n, double a, const void *x, double b, void *y);
 hipError_t launch_mul(hipStream_t s, int prec, int64_t n, const double *d, const void *x, void *z);
+// horizontal coarse space of the two-level velocity preconditioner (NCZ vertical profiles)
+hipError_t launch_prolong(hipStream_t s, int prec, int64_t N, int64_t nc, const int32_t *cpt, const double *cw,
+                          const double *zeta, const uint8_t *dm, const double *xc, void *x);
+hipError_t launch_restrict(hipStream_t s, int prec, int64_t N, int64_t nc, const int64_t *cptr, const int32_t *cnode,
+                           const double *cwt, const double *zeta, const uint8_t *dm, const void *r, double *rc);
 
 }  // namespace nsmf

@@ -40,6 +40,13 @@ __device__ __forceinline__ int logical_block() {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Element of slot el of block lb (-1: none): blocks take runs of E consecutive elements.
+template <int E> __device__ __forceinline__ int64_t tile_elem(const MeshView &m, int lb, int el) {
+  if (el >= E) return -1;
+  const int64_t e = (int64_t)lb * E + el;
+  return e < m.n_el ? e : -1;
+}
+
 template <int P> __device__ __forceinline__ int side_of(int a) { return a == 0 ? 0 : (a == P - 1 ? 1 : -1); }
 
 template <int P> __device__ __forceinline__ bool edge_on(uint32_t cm, int dir, int a, int b) {
@@ -750,34 +757,30 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
 }
 
 // ================================================================= kernels
-// Jacobian apply (and VJP): y = J_c x at the stored linearisation point.
-template <typename T, int P, int GEO, bool VJP, int PS, bool FR>
-__global__ void __launch_bounds__(Launch<P>::NT)
-k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void *__restrict__ st_, const T *__restrict__ fst,
-        const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
-        T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
-  const Tab<T, P> &tb = *tbp;
-  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+// Jacobian apply (and VJP) of one element: y = J_e x_e at the stored linearisation point for the
+// element e of block lb, slot els, given the node words nw of the thread's z-line; writes the
+// element's pressure rows (and parameter gradients) and leaves the velocity rows, after R_e^T, in y.
+// All threads of the block call it (barriers inside); HANG = false compiles the hanging-node
+// interpolation out (meshes without hanging faces).
+template <typename T, int P, int GEO, bool VJP, int PS, bool FR, bool HANG>
+__device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &gv, const Tab<T, P> &tb,
+                                           const void *__restrict__ st_, const T *__restrict__ fst,
+                                           const T *__restrict__ beta, const T *__restrict__ xu,
+                                           const T *__restrict__ xp, T *__restrict__ yp, double inv_n,
+                                           double *__restrict__ g_logA, double *__restrict__ g_beta, T *smem,
+                                           double *red, int lb, int tid, int t, int els, int64_t e, bool act,
+                                           const uint32_t (&nw)[P], T (&y)[3][P]) {
+  constexpr int NT = Launch<P>::NT, P2 = P * P;
   constexpr int NP = n_pres<P, PS>();
-  __shared__ T smem[E * Ws<T, P>::ES];
-  __shared__ double red[E * P2];
-  const int lb = logical_block();
-  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
-  const int64_t e = (int64_t)lb * E + el;
-  const bool act = el < E && e < m.n_el;
-  const int els = el < E ? el : E - 1;
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   double *redl = red + els * P2;
   const int64_t N = m.n_nodes;
-  // connectivity first (the gather of x waits on it), then the linearisation data of the thread's
-  // P points: requested here so that its latency overlaps the gather and the forward sweeps,
-  // for P = 4 and for FP32 with P = 5.  Elsewhere it is loaded just before the quadrature-point
-  // step: in FP64 with P = 3, 5 the extra live registers would cost occupancy, and with FP32 and
-  // P = 3 the early request measured 4% slower.  The block's slice is always allocated, also for
-  // threads without an element.
-  uint32_t nw[P];
-  load_words<P>(m.en + e * P3, t, act, nw);
-  const uint32_t cm = act ? m.cmask[e] : 0u;
+  // the linearisation data of the thread's P points are requested right after the connectivity
+  // (the caller's) so that their latency overlaps the gather and the forward sweeps, for P = 4 and for
+  // FP32 with P = 5.  Elsewhere they are loaded just before the quadrature-point step: in FP64 with
+  // P = 3, 5 the extra live registers would cost occupancy, and with FP32 and P = 3 the early request
+  // measured 4% slower.  The tile's slice is always allocated, also for threads without an element.
+  const uint32_t cm = (HANG && act) ? m.cmask[e] : 0u;
   // FP32 apply: the 7-value FP32 state; FP64 and the VJP (which needs Sigma0 : D itself for the
   // logA gradient): the 8-value FP64 state
   constexpr bool kS32 = sizeof(T) == 4 && !VJP;
@@ -807,7 +810,8 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
 #pragma unroll
     for (int mm = 0; mm < NP; ++mm) xpl[mm] = xp[e * NP + mm];
   }
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  if constexpr (HANG)
+    if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
 
   T gr[3][3][P];
@@ -872,7 +876,6 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
     const double sA = elem_sum64<P>(gA, redl, t, act);
     if (act && t == 0 && g_logA != nullptr) g_logA[e] = -inv_n * sA;
   }
-  T y[3][P];
   const T zero[P] = {};
 #pragma unroll
   for (int c = 0; c < 3; ++c) grad_bwd<T, P, false>(gr[c][0], gr[c][1], gr[c][2], zero, y[c], w, tb, t, act);
@@ -906,14 +909,39 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
       if (fid >= 0 && t == 0 && g_beta != nullptr) g_beta[fid] = sb;
     }
   }
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  if constexpr (HANG)
+    if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
   if (rot) {
     T Q[9];
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
     frame_out<T, P>(y, Q);
   }
+}
+
+// Jacobian apply (and VJP): y = J_c x at the stored linearisation point, E consecutive elements per
+// block, results through the node-ordered element vector (assembled by k_assemble).
+template <typename T, int P, int GEO, bool VJP, int PS, bool FR>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void *__restrict__ st_, const T *__restrict__ fst,
+        const T *__restrict__ beta, const T *__restrict__ xu, const T *__restrict__ xp, T *__restrict__ yu,
+        T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
+  constexpr int E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  __shared__ T smem[E * Ws<T, P>::ES];
+  __shared__ double red[E * P2];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
+  const int els = el < E ? el : E - 1;
+  // connectivity first: the gather of x waits on it
+  uint32_t nw[P];
+  load_words<P>(m.en + e * P3, t, act, nw);
+  T y[3][P];
+  apply_elem<T, P, GEO, VJP, PS, FR, true>(m, gv, *tbp, st_, fst, beta, xu, xp, yp, inv_n, g_logA, g_beta, smem, red, lb,
+                                           tid, t, els, e, act, nw, y);
   evec_store<T, P>(yu, m, lb, e, smem, els, t, act, y);
 }
+
 
 // Linearisation point: per quadrature point mu' = w detJ mu, kappa, Sigma0 = mu' D(u)
 // (FP64, eq. (glen) and eq. (rank4)); per basal face point w|S| T u.  The Picard operator keeps
@@ -929,8 +957,8 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
   __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
-  const int64_t e = (int64_t)lb * E + el;
-  const bool act = el < E && e < m.n_el;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
@@ -1011,8 +1039,8 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
   __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
-  const int64_t e = (int64_t)lb * E + el;
-  const bool act = el < E && e < m.n_el;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
@@ -1109,8 +1137,8 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   __shared__ T smem[E * Ws<T, P>::ES];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
-  const int64_t e = (int64_t)lb * E + el;
-  const bool act = el < E && e < m.n_el;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const uint32_t cm = act ? m.cmask[e] : 0u;
@@ -1255,8 +1283,8 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
   constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
-  const int64_t e = (int64_t)lb * E + el;
-  if (el >= E || e >= m.n_el) return;      // no barriers in this kernel
+  const int64_t e = tile_elem<E>(m, lb, el);
+  if (e < 0) return;                        // no barriers in this kernel
   const int i = t % P, j = t / P;
   int lo, hi;
   if (!zline_run<P>(m.cmask[e], i, j, lo, hi)) return;
@@ -1577,8 +1605,8 @@ k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__r
   __shared__ T xmag[E];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
-  const int64_t e = (int64_t)lb * E + el;
-  const bool act = el < E && e < m.n_el;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
@@ -1696,6 +1724,340 @@ k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__r
     }
   }
   if (mode == 0 && fl) atomicOr(flags, fl);
+}
+
+// ---------------------------------------------------------------- low-order F~ on the Gauss-Lobatto sub-grid
+// Sec. 5, "Construction of low-order approximation F~": the element's (k+1)^3 nodes are the corners of
+// k^3 trilinear sub-cells, and F~_e is the matrix of the bilinear form of F (eq. (rank4), plus the basal
+// term of eq. (robin)) on that grid, with the 2-point Gauss-Lobatto rule per sub-cell direction (F~_GL):
+// its quadrature points are the sub-cell corners, i.e. the element's nodes, with weight |det J| / 8.
+// The coefficients (mu, kappa' = mu (n-1)/(2n)/(II+eps), D0) are taken at each node from the high-order
+// state differentiated inside the element.  Globally F~ = sum_e R_e^T F~_e R_e with the high-order
+// restriction (figure "interp" (a) at nonconforming faces).
+
+// Reference derivatives of a z-line field at the element's nodes: gz in registers, gx and gy through
+// LDS (buffers 0..2).  All threads of the block must call.
+template <int P>
+__device__ void node_grad(const double (&v)[P], double (&gx)[P], double (&gy)[P], double (&gz)[P], Ws<double, P> w,
+                          const Tab<double, P> &tb, int t, bool act) {
+  if (act) {
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      double a = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) a += tb.G[z][m] * v[m];
+      gz[z] = a;
+      w.b(0)[w.zl(t, z)] = v[z];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int j = t % P, z = t / P;   // x-line (., j, z) and y-line (j, ., z)
+    double lx[P], ly[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      lx[m] = w.b(0)[m + P * j + w.SZ * z];
+      ly[m] = w.b(0)[j + P * m + w.SZ * z];
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double a = 0, b = 0;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        a += tb.G[i][m] * lx[m];
+        b += tb.G[i][m] * ly[m];
+      }
+      w.b(1)[i + P * j + w.SZ * z] = a;
+      w.b(2)[j + P * i + w.SZ * z] = b;
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      gx[z] = w.b(1)[w.zl(t, z)];
+      gy[z] = w.b(2)[w.zl(t, z)];
+    }
+  }
+  __syncthreads();
+}
+
+// Nodal data of F~ at the state: per element node its coordinates relative to the element's first slot
+// (periodic images nearest to it, through R_e) and mu, kappa', D0 from grad u_h at the node.
+template <int P>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_lowo_coef(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ X,
+            double px, double py, const double *__restrict__ u, const double *__restrict__ logA, double n, double eps,
+            double B0, int picard, double *__restrict__ lo) {
+  using T = double;
+  const Tab<T, P> &tb = *tbp;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
+  __shared__ T smem[E * Ws<T, P>::ES];
+  __shared__ T ref0[E][3];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
+  const int64_t N = m.n_nodes;
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  T xv[3][P];
+  uint32_t nw[P];
+  gather<T, P>(m.en + e * P3, X, N, t, act, false, xv, nw);
+  if (act && t == 0)
+    for (int c = 0; c < 3; ++c) ref0[els][c] = xv[c][0];
+  __syncthreads();
+  if (act)
+    for (int c = 0; c < 3; ++c)
+      for (int z = 0; z < P; ++z) {
+        T d = xv[c][z] - ref0[els][c];
+        const T per = c == 0 ? px : (c == 1 ? py : 0.0);
+        if (per > 0.0) d -= per * rint(d / per);
+        xv[c][z] = d;
+      }
+  const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
+  if (hang) hang_fwd<T, P>(xv, cm, w, tb, t, act);
+  if (act)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < P; ++z) lo[qp_at<P, NT, NLOWO>(lb, c, tid, z)] = xv[c][z];
+  // inverse Jacobian of the high-order map at the nodes: Ji[r][i] = d xi_r / d x_i
+  T Ji[3][3][P];
+  {
+    T J[3][3][P];   // J[i][r] = d x_i / d xi_r
+#pragma unroll
+    for (int c = 0; c < 3; ++c) node_grad<P>(xv[c], J[c][0], J[c][1], J[c][2], w, tb, t, act);
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      const T a00 = J[0][0][z], a01 = J[0][1][z], a02 = J[0][2][z];
+      const T a10 = J[1][0][z], a11 = J[1][1][z], a12 = J[1][2][z];
+      const T a20 = J[2][0][z], a21 = J[2][1][z], a22 = J[2][2][z];
+      const T c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+      const T c10 = a12 * a20 - a10 * a22, c11 = a00 * a22 - a02 * a20, c12 = a02 * a10 - a00 * a12;
+      const T c20 = a10 * a21 - a11 * a20, c21 = a01 * a20 - a00 * a21, c22 = a00 * a11 - a01 * a10;
+      const T det = a00 * c00 + a01 * c10 + a02 * c20;
+      const T id = act ? 1.0 / det : 0.0;
+      Ji[0][0][z] = c00 * id; Ji[0][1][z] = c01 * id; Ji[0][2][z] = c02 * id;
+      Ji[1][0][z] = c10 * id; Ji[1][1][z] = c11 * id; Ji[1][2][z] = c12 * id;
+      Ji[2][0][z] = c20 * id; Ji[2][1][z] = c21 * id; Ji[2][2][z] = c22 * id;
+    }
+  }
+  T uv[3][P];
+  gather_words<T, P>(nw, u, N, act, true, uv);
+  if (act && (nw[0] & ROT_BIT)) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_in<T, P>(uv, Q);
+  }
+  if (hang) hang_fwd<T, P>(uv, cm, w, tb, t, act);
+  T G[3][3][P];   // G[c][i] = d u_c / d x_i at the nodes
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T gr[3][P];
+    node_grad<P>(uv[c], gr[0], gr[1], gr[2], w, tb, t, act);
+#pragma unroll
+    for (int z = 0; z < P; ++z)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) G[c][i][z] = gr[0][z] * Ji[0][i][z] + gr[1][z] * Ji[1][i][z] + gr[2][z] * Ji[2][i][z];
+  }
+  if (!act) return;
+  const double Be = B0 * exp(-logA[e] / n);
+  const double expo = (1.0 - n) / (2.0 * n), cf = picard ? 0.0 : (n - 1.0) / (2.0 * n);
+#pragma unroll
+  for (int z = 0; z < P; ++z) {
+    const T dxx = G[0][0][z], dyy = G[1][1][z], dzz = G[2][2][z];
+    const T dxy = 0.5 * (G[0][1][z] + G[1][0][z]), dxz = 0.5 * (G[0][2][z] + G[2][0][z]);
+    const T dyz = 0.5 * (G[1][2][z] + G[2][1][z]);
+    const T II = 0.5 * (dxx * dxx + dyy * dyy + dzz * dzz) + dxy * dxy + dxz * dxz + dyz * dyz;
+    const T mu = Be * pow(II + eps, expo);
+    const T vals[8] = {mu, cf * mu / (II + eps), dxx, dyy, dzz, dxy, dxz, dyz};
+#pragma unroll
+    for (int f = 0; f < 8; ++f) lo[qp_at<P, NT, NLOWO>(lb, 3 + f, tid, z)] = vals[f];
+  }
+}
+
+// y_e = F~_e x_e for the element's z-lines (thread t = x + P y holds nodes (x, y, 0..P-1)), then R_e^T
+// and the element-vector store.  Quadrature point (q, octant s): the sub-cell with corner q and edges
+// towards q + s_x e_x, q + s_y e_y, q + s_z e_z; with the edge vectors as columns of J, g_r = J^-T e_r is
+// the gradient of the basis function of the r-th edge neighbour, -(g_1 + g_2 + g_3) that of q, and
+// f_r = |det J|/8 tau g_r is added to neighbour r and subtracted from q.  Contributions to the x- and
+// y-neighbour z-lines pass through LDS (one writer per target entry, fixed summation order).
+template <int P> struct LoShape {
+  static constexpr int RS = 6 * P * P * P > Ws<double, P>::ES ? 6 * P * P * P : Ws<double, P>::ES;
+};
+template <int P>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_lowo(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, const double *__restrict__ lo,
+       const double *__restrict__ beta, const double *__restrict__ x, double *__restrict__ ev) {
+  using T = double;
+  const Tab<T, P> &tb = *tbp;
+  constexpr int NT = Launch<P>::NT, E = Launch<P>::E, P2 = P * P, P3 = P2 * P, RS = LoShape<P>::RS;
+  __shared__ T smem[E * RS];
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
+  const int els = el < E ? el : E - 1;
+  T *reg = smem + els * RS;            // element region: V[3][P3], X[3][P3]; later the contributions
+  Ws<T, P> w{reg};
+  const int64_t N = m.n_nodes;
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  const int xi = t % P, yi = t / P;
+  T v[3][P];
+  uint32_t nw[P];
+  gather<T, P>(m.en + e * P3, x, N, t, act, true, v, nw);
+  const bool rot = act && (nw[0] & ROT_BIT);
+  if (rot) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_in<T, P>(v, Q);
+  }
+  const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
+  if (hang) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int z = 0; z < P; ++z)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        reg[c * P3 + t + P2 * z] = v[c][z];
+        reg[(3 + c) * P3 + t + P2 * z] = lo[qp_at<P, NT, NLOWO>(lb, c, tid, z)];
+      }
+  __syncthreads();
+  T acc[3][P], cxp[3][P], cxm[3][P], cyp[3][P], cym[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < P; ++z) acc[c][z] = cxp[c][z] = cxm[c][z] = cyp[c][z] = cym[c][z] = 0;
+  if (act) {
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      const int q = t + P2 * z;
+      T co[8];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) co[f] = lo[qp_at<P, NT, NLOWO>(lb, 3 + f, tid, z)];
+      const T mu = co[0], ka = co[1];
+      const T s00 = co[2], s11 = co[3], s22 = co[4], s01 = co[5], s02 = co[6], s12 = co[7];
+#pragma unroll
+      for (int oct = 0; oct < 8; ++oct) {
+        const int sx = (oct & 1) ? 1 : -1, sy = (oct & 2) ? 1 : -1, sz = (oct & 4) ? 1 : -1;
+        if (xi + sx < 0 || xi + sx >= P || yi + sy < 0 || yi + sy >= P || z + sz < 0 || z + sz >= P) continue;
+        const int nb[3] = {q + sx, q + P * sy, q + P2 * sz};
+        T Jc[3][3], du[3][3];   // Jc[r][i]: edge r (column r of J), du[r][c]: value difference along edge r
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            Jc[r][i] = reg[(3 + i) * P3 + nb[r]] - reg[(3 + i) * P3 + q];
+            du[r][i] = reg[i * P3 + nb[r]] - reg[i * P3 + q];
+          }
+        // J[i][r] = Jc[r][i]; g_r = J^-T e_r = row r of J^-1 = cofactor column / det
+        const T a00 = Jc[0][0], a01 = Jc[1][0], a02 = Jc[2][0];
+        const T a10 = Jc[0][1], a11 = Jc[1][1], a12 = Jc[2][1];
+        const T a20 = Jc[0][2], a21 = Jc[1][2], a22 = Jc[2][2];
+        const T c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+        const T c10 = a12 * a20 - a10 * a22, c11 = a00 * a22 - a02 * a20, c12 = a02 * a10 - a00 * a12;
+        const T c20 = a10 * a21 - a11 * a20, c21 = a01 * a20 - a00 * a21, c22 = a00 * a11 - a01 * a10;
+        const T det = a00 * c00 + a01 * c10 + a02 * c20;
+        const T id = 1.0 / det;
+        const T g[3][3] = {{c00 * id, c01 * id, c02 * id}, {c10 * id, c11 * id, c12 * id}, {c20 * id, c21 * id, c22 * id}};
+        // G[c][i] = sum_r du[r][c] g[r][i]
+        T Gm[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) Gm[c][i] = du[0][c] * g[0][i] + du[1][c] * g[1][i] + du[2][c] * g[2][i];
+        const T dxx = Gm[0][0], dyy = Gm[1][1], dzz = Gm[2][2];
+        const T dxy = 0.5 * (Gm[0][1] + Gm[1][0]), dxz = 0.5 * (Gm[0][2] + Gm[2][0]), dyz = 0.5 * (Gm[1][2] + Gm[2][1]);
+        const T sd = s00 * dxx + s11 * dyy + s22 * dzz + 2.0 * (s01 * dxy + s02 * dxz + s12 * dyz);
+        const T wd = fabs(det) * 0.125;
+        const T tau[3][3] = {{wd * (mu * dxx - ka * sd * s00), wd * (mu * dxy - ka * sd * s01), wd * (mu * dxz - ka * sd * s02)},
+                             {wd * (mu * dxy - ka * sd * s01), wd * (mu * dyy - ka * sd * s11), wd * (mu * dyz - ka * sd * s12)},
+                             {wd * (mu * dxz - ka * sd * s02), wd * (mu * dyz - ka * sd * s12), wd * (mu * dzz - ka * sd * s22)}};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T f0 = tau[c][0] * g[0][0] + tau[c][1] * g[0][1] + tau[c][2] * g[0][2];
+          const T f1 = tau[c][0] * g[1][0] + tau[c][1] * g[1][1] + tau[c][2] * g[1][2];
+          const T f2 = tau[c][0] * g[2][0] + tau[c][1] * g[2][1] + tau[c][2] * g[2][2];
+          acc[c][z] -= f0 + f1 + f2;
+          if (sz > 0) { if (z + 1 < P) acc[c][z + 1] += f2; }
+          else { if (z >= 1) acc[c][z - 1] += f2; }
+          if (sx > 0) cxp[c][z] += f0; else cxm[c][z] += f0;
+          if (sy > 0) cyp[c][z] += f1; else cym[c][z] += f1;
+        }
+      }
+    }
+  }
+  // basal Robin term, lumped on the sub-faces at the bottom node: 1/4 |t1 x t2| beta (I - n n^T) v
+  const int fid = act ? m.bface_of[e] : -1;
+  if (fid >= 0) {
+    const T bt = beta[fid];
+#pragma unroll
+    for (int quad = 0; quad < 4; ++quad) {
+      const int sx = (quad & 1) ? 1 : -1, sy = (quad & 2) ? 1 : -1;
+      if (xi + sx < 0 || xi + sx >= P || yi + sy < 0 || yi + sy >= P) continue;
+      T t1[3], t2[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        t1[i] = reg[(3 + i) * P3 + t + sx] - reg[(3 + i) * P3 + t];
+        t2[i] = reg[(3 + i) * P3 + t + P * sy] - reg[(3 + i) * P3 + t];
+      }
+      const T cr[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2], t1[0] * t2[1] - t1[1] * t2[0]};
+      const T area = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      const T nv[3] = {cr[0] / area, cr[1] / area, cr[2] / area};
+      const T nu = nv[0] * v[0][0] + nv[1] * v[1][0] + nv[2] * v[2][0];
+      const T wb = 0.25 * area * bt;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c][0] += wb * (v[c][0] - nv[c] * nu);
+    }
+  }
+  // x-neighbour contributions: XP[target] from the source at target - e_x, XM[target] from target + e_x
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int z = 0; z < P; ++z)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (xi + 1 < P) reg[c * P3 + t + 1 + P2 * z] = cxp[c][z];
+        if (xi >= 1) reg[(3 + c) * P3 + t - 1 + P2 * z] = cxm[c][z];
+      }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int z = 0; z < P; ++z)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (xi >= 1) acc[c][z] += reg[c * P3 + t + P2 * z];
+        if (xi + 1 < P) acc[c][z] += reg[(3 + c) * P3 + t + P2 * z];
+      }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int z = 0; z < P; ++z)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (yi + 1 < P) reg[c * P3 + t + P + P2 * z] = cyp[c][z];
+        if (yi >= 1) reg[(3 + c) * P3 + t - P + P2 * z] = cym[c][z];
+      }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int z = 0; z < P; ++z)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (yi >= 1) acc[c][z] += reg[c * P3 + t + P2 * z];
+        if (yi + 1 < P) acc[c][z] += reg[(3 + c) * P3 + t + P2 * z];
+      }
+  __syncthreads();
+  if (hang) hang_bwd<T, P>(acc, cm, w, tb, t, act);
+  if (rot) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_out<T, P>(acc, Q);
+  }
+  evec_store<T, P>(ev, m, lb, e, smem, els, t, act, acc);
 }
 
 // ---------------------------------------------------------------- assembly  y = sum_e R_e^T y_e
@@ -1960,6 +2322,38 @@ hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const in
   }
   NSMF_LA(3) NSMF_LA(4) NSMF_LA(5)
 #undef NSMF_LA
+  return hipErrorInvalidValue;
+}
+
+
+template <int P>
+static hipError_t lowo_coef_p(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                              const double *X, const double *per, const double *u, const double *logA, double n,
+                              double eps, double B0, bool picard, double *lo) {
+  hipLaunchKernelGGL((k_lowo_coef<P>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g, &((const TabSet<P> *)tabs)->d, X,
+                     per[0], per[1], u, logA, n, eps, B0, (int)picard, lo);
+  return hipGetLastError();
+}
+hipError_t launch_lowo_coef(int P, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                            const double *X, const double period[3], const double *u, const double *logA, double n,
+                            double eps, double B0, bool picard, double *lo) {
+  switch (P) {
+    case 3: return lowo_coef_p<3>(s, m, g, tabs, X, period, u, logA, n, eps, B0, picard, lo);
+    case 4: return lowo_coef_p<4>(s, m, g, tabs, X, period, u, logA, n, eps, B0, picard, lo);
+    case 5: return lowo_coef_p<5>(s, m, g, tabs, X, period, u, logA, n, eps, B0, picard, lo);
+  }
+  return hipErrorInvalidValue;
+}
+hipError_t launch_lowo(int P, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
+                       const double *lo, const double *beta, const double *x, double *ev) {
+#define NSMF_LO(PP)                                                                                               \
+  if (P == PP) {                                                                                                  \
+    hipLaunchKernelGGL((k_lowo<PP>), dim3(m.nblocks), dim3(Launch<PP>::NT), 0, s, m, g,                          \
+                       &((const TabSet<PP> *)tabs)->d, lo, beta, x, ev);                                          \
+    return hipGetLastError();                                                                                     \
+  }
+  NSMF_LO(3) NSMF_LO(4) NSMF_LO(5)
+#undef NSMF_LO
   return hipErrorInvalidValue;
 }
 

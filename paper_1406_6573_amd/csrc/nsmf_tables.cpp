@@ -95,6 +95,8 @@ void build_tables(int k, int pspace, HostTables *t) {
       t->B[q][a] = lagrange(t->xi, P, a, t->g[q]);
       t->D[q][a] = lagrange_deriv(t->xi, P, a, t->g[q]);
     }
+  for (int i = 0; i < P; ++i)
+    for (int a = 0; a < P; ++a) t->G[i][a] = lagrange_deriv(t->xi, P, a, t->xi[i]);
   for (int h = 0; h < 2; ++h)
     for (int i = 0; i < P; ++i) {
       double xc = 0.5 * (t->xi[i] + (h ? 1.0 : -1.0));
@@ -160,6 +162,8 @@ Tab<T, P> make_tab(const HostTables &h, bool bf16_ops) {
   for (int j = 0; j < P - 1; ++j)
     for (int q = 0; q < P; ++q) t.L[j][q] = (T)h.L[j][q];
   for (int q = 0; q < P; ++q) t.w[q] = (T)h.w[q];
+  for (int i = 0; i < P; ++i)
+    for (int a = 0; a < P; ++a) t.G[i][a] = (T)h.G[i][a];
   return t;
 }
 

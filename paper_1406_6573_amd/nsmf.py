@@ -27,7 +27,8 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_geometry_kind", "nsmf_set_kernel_timing", "nsmf_kernel_time", "nsmf_last_error",
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
             "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization",
-            "nsmf_jacobian_apply_noalloc"]
+            "nsmf_jacobian_apply_noalloc", "nsmf_lowo_apply", "nsmf_coarse_setup", "nsmf_coarse_prolong",
+            "nsmf_coarse_restrict"]
 
 
 class NsmfError(RuntimeError):
@@ -82,6 +83,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_jacobi_diag.argtypes = [vp, ci, vp, vp]
     lib.nsmf_line_setup.argtypes = [vp, i64p]
     lib.nsmf_line_apply.argtypes = [vp, ci, vp, vp]
+    lib.nsmf_lowo_apply.argtypes = [vp, vp, vp]
+    lib.nsmf_coarse_setup.argtypes = [vp, i64, vp, vp, vp]
+    lib.nsmf_coarse_prolong.argtypes = [vp, ci, vp, vp]
+    lib.nsmf_coarse_restrict.argtypes = [vp, ci, vp, vp]
     lib.nsmf_set_linearization.argtypes = [vp, ci]
     lib.nsmf_vec_dots.argtypes = [vp, ci, i64, ci, vp, i64, vp, vp]
     lib.nsmf_vec_gemv.argtypes = [vp, ci, i64, ci, vp, i64, vp, dbl, vp]
@@ -301,6 +306,45 @@ class Engine:
         self.sync_stream()
         self._check(self.lib.nsmf_jacobi_diag(self.h, 1 if invert else 0, _ptr(d_u), _ptr(d_p)))
         return d_u, d_p
+
+    def lowo_apply(self, x_u, out=None):
+        """y_u = J~_c x_u with the low-order approximation of the velocity block on the Gauss-Lobatto
+        sub-grid at the state (FP64, [3, n_nodes])."""
+        sz = self.sizes
+        x_u = self._vec(x_u, (3, sz["n_nodes"]), self.torch.float64, "x_u")
+        y_u = self.torch.empty_like(x_u) if out is None else self._vec(out, (3, sz["n_nodes"]), self.torch.float64, "out")
+        self.sync_stream()
+        self._check(self.lib.nsmf_lowo_apply(self.h, _ptr(x_u), _ptr(y_u)))
+        return y_u
+
+    def coarse_setup(self, n_cpts, node_cpt, node_w, node_zeta):
+        """Horizontal coarse space: per node its coarse cell's 4 lattice points, bilinear weights and
+        relative height (host arrays).  Coarse vectors are float64 [3, n_cpts, 3]."""
+        sz = self.sizes
+        cpt = np.ascontiguousarray(node_cpt, dtype=np.int32).reshape(sz["n_nodes"], 4)
+        w = np.ascontiguousarray(node_w, dtype=np.float64).reshape(sz["n_nodes"], 4)
+        zeta = np.ascontiguousarray(node_zeta, dtype=np.float64).reshape(sz["n_nodes"])
+        self.sync_stream()
+        self._check(self.lib.nsmf_coarse_setup(self.h, int(n_cpts), cpt.ctypes.data, w.ctypes.data, zeta.ctypes.data))
+        self.n_cpts = int(n_cpts)
+
+    def coarse_prolong(self, xc, out):
+        """out [3, n_nodes] (float64 or float32) = masked prolongation of xc [3, n_cpts, 3] (float64)."""
+        sz = self.sizes
+        xc = self._vec(xc, (3, self.n_cpts, 3), self.torch.float64, "xc")
+        out = self._vec(out, (3, sz["n_nodes"]), out.dtype, "out")
+        self.sync_stream()
+        self._check(self.lib.nsmf_coarse_prolong(self.h, self._prec_of(out), _ptr(xc), _ptr(out)))
+        return out
+
+    def coarse_restrict(self, r_u, out):
+        """out [3, n_cpts, 3] (float64) = restriction of r_u [3, n_nodes] (float64 or float32)."""
+        sz = self.sizes
+        r_u = self._vec(r_u, (3, sz["n_nodes"]), r_u.dtype, "r_u")
+        out = self._vec(out, (3, self.n_cpts, 3), self.torch.float64, "out")
+        self.sync_stream()
+        self._check(self.lib.nsmf_coarse_restrict(self.h, self._prec_of(r_u), _ptr(r_u), _ptr(out)))
+        return out
 
     def line_setup(self):
         """Factor the vertical-line blocks of the velocity block at the state; returns the number of lines."""

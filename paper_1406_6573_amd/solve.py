@@ -39,6 +39,112 @@ import numpy as np
 import torch
 
 
+def column_coarse_space(mesh, cells):
+    """Host arrays of the horizontal coarse space on a column mesh: a lattice of cells[0] x cells[1]
+    coarse cells over the bounding box of the nodes' (x, y), each node's coarse cell corners (lattice
+    point i + (cells[0] + 1) j) with bilinear weights, and its relative height zeta (logical height over
+    the number of layers).  Returns (n_cpts, node_cpt [N, 4], node_w [N, 4], zeta [N], lattice shape)."""
+    ncx, ncy = int(cells[0]), int(cells[1])
+    # coarse cells made of whole columns: then no element straddles a lattice line, a hat function
+    # couples only with the hats of the neighbouring lattice points, and the probing colours stay exact
+    if mesh.nx % ncx or mesh.ny % ncy:
+        raise ValueError(f"coarse cells {cells} must divide the column counts ({mesh.nx}, {mesh.ny})")
+    x, y = np.asarray(mesh.coords[0]), np.asarray(mesh.coords[1])
+    zeta = np.clip(np.asarray(mesh.node_logical[:, 2], dtype=np.float64) / mesh.nz, 0.0, 1.0)
+    cols = []
+    for v, nc in ((x, ncx), (y, ncy)):
+        lo, hi = float(v.min()), float(v.max())
+        f = (v - lo) / max(hi - lo, 1e-300) * nc
+        i = np.clip(np.floor(f).astype(np.int64), 0, nc - 1)
+        cols.append((i, f - i))
+    (i, s), (j, t) = cols
+    npx = ncx + 1
+    cpt = np.stack([i + npx * j, i + 1 + npx * j, i + npx * (j + 1), i + 1 + npx * (j + 1)], 1).astype(np.int32)
+    w = np.stack([(1 - s) * (1 - t), s * (1 - t), (1 - s) * t, s * t], 1)
+    return npx * (ncy + 1), cpt, w, zeta, (npx, ncy + 1)
+
+
+class CoarseCorrection:
+    """Two-level part of the velocity preconditioner: coarse functions = bilinear hats of a horizontal
+    lattice times three vertical profiles (the engine's coarse space), Galerkin coarse matrix
+    A_c = P_c^T J~_c P_c with the low-order approximation J~_c of Sec. 5 (probed with the engine's
+    matrix-free F~ apply: lattice points whose indices agree modulo 3 have disjoint coupled supports, so
+    9 colours x 3 components x 3 profiles = 81 applies give every entry), and its dense inverse by
+    Cholesky.  apply(r) = P_c A_c^-1 P_c^T r."""
+
+    def __init__(self, engine, mesh, cells, krylov_dtype):
+        self.eng = engine
+        n_cpts, cpt, w, zeta, (npx, npy) = column_coarse_space(mesh, cells)
+        engine.coarse_setup(n_cpts, cpt, w, zeta)
+        self.n_cpts, self.npx, self.npy = n_cpts, npx, npy
+        self.nc = 9 * n_cpts
+        dev = engine.dev
+        self.kt = krylov_dtype
+        N = engine.sizes["n_nodes"]
+        self.xc = torch.zeros((3, n_cpts, 3), dtype=torch.float64, device=dev)
+        self.rc = torch.empty((3, n_cpts, 3), dtype=torch.float64, device=dev)
+        self.xu = torch.empty((3, N), dtype=torch.float64, device=dev)
+        self.yu = torch.empty((3, N), dtype=torch.float64, device=dev)
+        pi = torch.arange(n_cpts, device=dev) % npx
+        pj = torch.arange(n_cpts, device=dev) // npx
+        self.colours = []
+        for a in range(3):
+            for b in range(3):
+                members = (pi % 3 == a) & (pj % 3 == b)
+                # partner[J'] = the lattice point of colour (a, b) within distance 1 of J' (unique), or -1
+                di = (a - pi) % 3
+                di = torch.where(di == 2, -1, di)
+                dj = (b - pj) % 3
+                dj = torch.where(dj == 2, -1, dj)
+                qi, qj = pi + di, pj + dj
+                ok = (qi >= 0) & (qi < npx) & (qj >= 0) & (qj < npy)
+                partner = torch.where(ok, qi + npx * qj, torch.full_like(qi, -1))
+                self.colours.append((members, partner))
+        self.Ainv = None
+
+    def setup(self):
+        """Probe A_c at the engine's current state and factor it."""
+        eng, n, dev = self.eng, self.n_cpts, self.eng.dev
+        A = torch.zeros((self.nc, self.nc), dtype=torch.float64, device=dev)
+        rows_c = torch.arange(3, device=dev).view(3, 1, 1).expand(3, n, 3)
+        rows_m = torch.arange(3, device=dev).view(1, 1, 3).expand(3, n, 3)
+        for members, partner in self.colours:
+            pj = partner.view(1, n, 1).expand(3, n, 3)
+            valid = (pj >= 0).reshape(-1)
+            rows = torch.arange(self.nc, device=dev)[valid]
+            for c in range(3):
+                for m in range(3):
+                    self.xc.zero_()
+                    self.xc[c, members, m] = 1.0
+                    eng.coarse_prolong(self.xc, self.xu)
+                    eng.lowo_apply(self.xu, out=self.yu)
+                    eng.coarse_restrict(self.yu, self.rc)
+                    cols = ((c * n + pj) * 3 + m).reshape(-1)[valid]
+                    A[rows, cols] = self.rc.reshape(-1)[valid]
+        A = 0.5 * (A + A.T)
+        self.asym = None
+        L, info = torch.linalg.cholesky_ex(A)
+        if int(info) != 0:                      # singular coarse matrix (no basal friction nor mask)
+            shift = 1e-10 * float(torch.diagonal(A).abs().max())
+            L = torch.linalg.cholesky(A + shift * torch.eye(self.nc, dtype=A.dtype, device=dev))
+        self.Ainv = torch.cholesky_inverse(L)
+        self.Ainv32 = self.Ainv.float() if self.kt == torch.float32 else None
+        self.A = A
+
+    def apply(self, r_u, out):
+        """out = P_c A_c^-1 P_c^T r_u (r_u, out [3, n_nodes] in the Krylov precision)."""
+        eng = self.eng
+        eng.coarse_restrict(r_u, self.rc)
+        rc = self.rc.reshape(-1)
+        if self.Ainv32 is not None:
+            ec = (self.Ainv32 @ rc.float()).double()
+        else:
+            ec = self.Ainv @ rc
+        self.xc.copy_(ec.view(3, self.n_cpts, 3))
+        eng.coarse_prolong(self.xc, out)
+        return out
+
+
 @dataclass
 class SolveStats:
     newton_residuals: list = field(default_factory=list)
@@ -54,11 +160,17 @@ class SolveStats:
 
 class NewtonKrylov:
     def __init__(self, engine, restart: int = 50, precision: str = "fp64", refine: int = 1,
-                 precond: str = "jacobi", triangular: bool = False, linearization: str = "newton"):
+                 precond: str = "jacobi", triangular: bool = False, linearization: str = "newton",
+                 coarse=None, coarse_mode: str = "mult"):
+        """coarse = (mesh, (cells_x, cells_y)) adds the horizontal coarse correction built from the
+        low-order F~ to the velocity preconditioner (two-level with the line blocks as smoother,
+        multiplicative "coarse then smooth" or additive)."""
         if restart + 1 > 64:
             raise ValueError("restart must be at most 63")
         if precond not in ("jacobi", "line"):
             raise ValueError("precond must be 'jacobi' or 'line'")
+        if coarse_mode not in ("mult", "add"):
+            raise ValueError("coarse_mode must be 'mult' or 'add'")
         if engine.linearization != linearization:         # switching discards the engine's state
             engine.set_linearization(linearization)
         self.linearization = linearization
@@ -81,6 +193,12 @@ class NewtonKrylov:
         if triangular:
             self.zero_u = torch.zeros((3, self.N), dtype=kt, device=dev)
             self.bt = torch.empty(self.n, dtype=kt, device=dev)
+        self.coarse, self.coarse_mode = None, coarse_mode
+        if coarse is not None:
+            self.coarse = CoarseCorrection(engine, coarse[0], coarse[1], kt)
+            self.zc = torch.empty((3, self.N), dtype=kt, device=dev)
+            self.zero_p = torch.zeros((self.n_el, self.n_p), dtype=kt, device=dev)
+            self.fz = torch.empty(self.n, dtype=kt, device=dev)
 
     # ------------------------------------------------------------ views
     def split(self, x):
@@ -94,7 +212,7 @@ class NewtonKrylov:
     def precondition(self, v, z):
         """z = M^-1 v (vectors of the Krylov precision)."""
         eng = self.eng
-        if self.precond == "jacobi" and not self.triangular:
+        if self.precond == "jacobi" and not self.triangular and self.coarse is None:
             eng.vec_mul(self.minv, v, z)
             return
         vu, vp = self.split(v)
@@ -107,16 +225,28 @@ class NewtonKrylov:
             eng.jacobian_apply(self.zero_u, zp, prec, out=(bu, bp))
             eng.vec_axpby(1.0, vu.reshape(-1), -1.0, bu.reshape(-1))
             ru = bu
+        if self.coarse is not None:
+            zc = self.coarse.apply(ru, self.zc)                                  # coarse correction
+            if self.coarse_mode == "mult":                                      # smooth r - F z_c
+                fu, fp = self.split(self.fz)
+                prec = "fp64" if v.dtype == torch.float64 else "fp32"
+                eng.jacobian_apply(zc, self.zero_p, prec, out=(fu, fp))
+                eng.vec_axpby(1.0, ru.reshape(-1), -1.0, fu.reshape(-1))
+                ru = fu
         if self.precond == "line":
             eng.line_apply(ru, out=zu)
         else:
             eng.vec_mul(self.minv[:3 * self.N], ru.reshape(-1), zu.reshape(-1))
+        if self.coarse is not None:
+            eng.vec_axpby(1.0, self.zc.reshape(-1), 1.0, zu.reshape(-1))
 
     def setup_preconditioner(self):
         mu, mp = self.split(self.minv)
         self.eng.jacobi_diag(invert=True, out=(mu, mp))
         if self.precond == "line":
             self.eng.line_setup()
+        if self.coarse is not None:
+            self.coarse.setup()
 
     def norm(self, x):
         self.eng.vec_dots(x.view(1, -1), 1, x, self.h)

@@ -116,6 +116,18 @@ def test_hanging_small(torch_cuda, k, mapped):
     check_case(torch_cuda, case, f"hanging k={k} mapped={mapped}")
 
 
+@pytest.mark.parametrize("k,mapped,variant", [(2, False, ""), (3, True, ""), (4, True, ""), (4, False, "periodic"),
+                                               (3, True, "qspace")])
+def test_unrefined_columns(torch_cuda, k, mapped, variant):
+    """Meshes of unrefined columns (no hanging faces), 7 x 3 columns: the full check, with the basal mask
+    and random beta, periodic identification, and the Q_{k-2} pair."""
+    kw = dict(periodic=(True, True)) if variant == "periodic" else {}
+    if variant == "qspace":
+        kw["pspace"] = "Q"
+    case = small_case(k, mapped=mapped, frac=0.0, nx=7, ny=3, body=(0.0, 0.1, -1.0), **kw)
+    check_case(torch_cuda, case, f"unrefined columns k={k} mapped={mapped} {variant}")
+
+
 def test_config1_qspace(torch_cuda):
     """Config 1 with the Q_{k-2} pressure pair (Q2 x Q0)."""
     from meshgen import make_config
