@@ -269,12 +269,15 @@ int nsmf_line_apply(nsmf_ctx *ctx, int prec, const void *x_u, void *y_u);
  *   nsmf_vec_gemv:  w[r] += alpha sum_i V[i*ldv + r] h[i] (h: DEVICE doubles [k])
  *   nsmf_vec_axpby: y = a x + b y (b == 0: y is written without being read, BLAS convention)
  *   nsmf_vec_mul:   z = d .* x (d: DEVICE doubles [n])
+ *   nsmf_vec_normalize: x = x / sqrt(nrm2[0]), nrm2 a DEVICE double (e.g. from nsmf_vec_dots of x with
+ *                   itself); x = 0 when nrm2[0] <= 0.  Lets the Arnoldi step normalise without the host.
  *   nsmf_vec_convert: out = in, double -> float (to_fp32 != 0) or float -> double */
 int nsmf_vec_dots(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w, double *h);
 int nsmf_vec_gemv(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
                   double alpha, void *w);
 int nsmf_vec_axpby(nsmf_ctx *ctx, int prec, int64_t n, double a, const void *x, double b, void *y);
 int nsmf_vec_mul(nsmf_ctx *ctx, int prec, int64_t n, const double *d, const void *x, void *z);
+int nsmf_vec_normalize(nsmf_ctx *ctx, int prec, int64_t n, const double *nrm2, void *x);
 int nsmf_vec_convert(nsmf_ctx *ctx, int64_t n, int to_fp32, const void *in, void *out);
 
 /* Sizes of the uploaded mesh; any pointer may be NULL. */

@@ -842,6 +842,13 @@ int nsmf_vec_axpby(nsmf_ctx *ctx, int prec, int64_t n, double a, const void *x, 
   return NSMF_OK;
 }
 
+int nsmf_vec_normalize(nsmf_ctx *ctx, int prec, int64_t n, const double *nrm2, void *x) {
+  if (!ctx || !nrm2 || !x || n < 0) return NSMF_EINVAL;
+  if (prec < 0 || prec > 1) return ctx->fail(NSMF_EINVAL, "precision must be 0 or 1");
+  NSMF_TRY(ctx, launch_normalize(ctx->stream, prec, n, nrm2, x), "normalize");
+  return NSMF_OK;
+}
+
 int nsmf_vec_mul(nsmf_ctx *ctx, int prec, int64_t n, const double *d, const void *x, void *z) {
   int rc = vec_check(ctx, prec, n);
   if (rc) return rc;

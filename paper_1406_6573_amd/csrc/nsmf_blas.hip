@@ -58,6 +58,16 @@ __global__ void k_axpby(int64_t n, double a, const T *__restrict__ x, double b, 
   if (r < n) y[r] = (T)(b == 0.0 ? a * (double)x[r] : a * (double)x[r] + b * (double)y[r]);
 }
 
+// x = x / sqrt(nrm2[0]) with the squared norm read on the device (0 when nrm2[0] <= 0): the Arnoldi
+// normalisation without a round trip of the norm through the host
+template <typename T>
+__global__ void k_normalize(int64_t n, const double *__restrict__ nrm2, T *__restrict__ x) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double s = nrm2[0];
+  const double f = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  if (r < n) x[r] = (T)((double)x[r] * f);
+}
+
 // z = d * x (elementwise), d in FP64
 template <typename T>
 __global__ void k_mul(int64_t n, const double *__restrict__ d, const T *__restrict__ x, T *__restrict__ z) {
@@ -109,6 +119,14 @@ hipError_t launch_axpby(hipStream_t s, int prec, int64_t n, double a, const void
   return hipGetLastError();
 }
 
+hipError_t launch_normalize(hipStream_t s, int prec, int64_t n, const double *nrm2, void *x) {
+  if (n <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_normalize<double>, dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, nrm2, (double *)x);
+  else
+    hipLaunchKernelGGL(k_normalize<float>, dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, nrm2, (float *)x);
+  return hipGetLastError();
+}
 hipError_t launch_mul(hipStream_t s, int prec, int64_t n, const double *d, const void *x, void *z) {
   if (prec == 0)
     hipLaunchKernelGGL(k_mul<double>, dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, d, (const double *)x, (double *)z);

@@ -168,6 +168,7 @@ hipError_t launch_gemv(hipStream_t s, int prec, int64_t n, int k, const void *V,
                        double alpha, void *w);
 hipError_t launch_axpby(hipStream_t s, int prec, int64_t n, double a, const void *x, double b, void *y);
 hipError_t launch_mul(hipStream_t s, int prec, int64_t n, const double *d, const void *x, void *z);
+hipError_t launch_normalize(hipStream_t s, int prec, int64_t n, const double *nrm2, void *x);
 // horizontal coarse space of the two-level velocity preconditioner (NCZ vertical profiles)
 hipError_t launch_prolong(hipStream_t s, int prec, int64_t N, int64_t nc, const int32_t *cpt, const double *cw,
                           const double *zeta, const uint8_t *dm, const double *xc, void *x);

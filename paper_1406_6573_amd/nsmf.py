@@ -28,7 +28,7 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
             "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization",
             "nsmf_jacobian_apply_noalloc", "nsmf_lowo_apply", "nsmf_coarse_setup", "nsmf_coarse_prolong",
-            "nsmf_coarse_restrict"]
+            "nsmf_coarse_restrict", "nsmf_vec_normalize"]
 
 
 class NsmfError(RuntimeError):
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_vec_gemv.argtypes = [vp, ci, i64, ci, vp, i64, vp, dbl, vp]
     lib.nsmf_vec_axpby.argtypes = [vp, ci, i64, dbl, vp, dbl, vp]
     lib.nsmf_vec_mul.argtypes = [vp, ci, i64, vp, vp, vp]
+    lib.nsmf_vec_normalize.argtypes = [vp, ci, i64, vp, vp]
     lib.nsmf_vec_convert.argtypes = [vp, i64, ci, vp, vp]
     _lib = lib
     return lib
@@ -409,6 +410,14 @@ class Engine:
         self._flat(d, n, self.torch.float64, "d")
         self.sync_stream()
         self._check(self.lib.nsmf_vec_mul(self.h, self._prec_of(z), n, _ptr(d), _ptr(x), _ptr(z)))
+
+    def vec_normalize(self, nrm2, x):
+        """x = x / sqrt(nrm2[0]) with nrm2 a float64 device tensor (x = 0 when nrm2[0] <= 0)."""
+        n = x.numel()
+        self._flat(x, n, x.dtype, "x")
+        self._flat(nrm2, 1, self.torch.float64, "nrm2")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_normalize(self.h, self._prec_of(x), n, _ptr(nrm2), _ptr(x)))
 
     def vec_convert(self, x, out):
         """out = x converted between float64 and float32."""

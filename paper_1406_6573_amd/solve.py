@@ -32,6 +32,7 @@ aspect ratio.
 from __future__ import annotations
 
 import math
+import sys
 import time
 from dataclasses import dataclass, field
 
@@ -185,6 +186,11 @@ class NewtonKrylov:
         self.V = torch.empty((restart + 1, self.n), dtype=kt, device=dev)
         self.Z = torch.empty((restart, self.n), dtype=kt, device=dev)
         self.h = torch.empty(64, dtype=torch.float64, device=dev)
+        # Hessenberg columns of one cycle: two Gram-Schmidt passes and the squared norm per step, on the
+        # device and their pinned host copies
+        self.Hd = torch.zeros((restart, 3, 64), dtype=torch.float64, device=dev)
+        self.Hh = torch.zeros((restart, 3, 64), dtype=torch.float64, pin_memory=True)
+        self.events = [torch.cuda.Event() for _ in range(restart)]
         self.minv = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.w64 = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.r64 = torch.empty(self.n, dtype=torch.float64, device=dev)
@@ -255,7 +261,14 @@ class NewtonKrylov:
     # ------------------------------------------------------------ FGMRES
     def fgmres(self, b, x, tol):
         """Approximately solve J x = b (vectors of the Krylov precision), x += correction.
-        Returns (iterations, residual estimate / ||b||)."""
+        Returns (iterations, residual estimate / ||b||).
+
+        An Arnoldi step runs entirely on the device: both Gram-Schmidt passes (multi-dots into a device
+        Hessenberg column, basis combination), the norm and the normalisation by it.  The column is
+        copied to pinned host memory asynchronously, and the host applies the Givens rotations to
+        column j - 1 while step j is queued, so no step waits for the host.  When column j - 1 meets
+        the tolerance, the already computed column j is used as well (one step more than a
+        synchronous loop would take)."""
         eng, V, Z, m = self.eng, self.V, self.Z, self.m
         w = V[0]
         self.apply(x, w)
@@ -265,25 +278,21 @@ class NewtonKrylov:
         if beta == 0.0 or bnorm == 0.0:
             return 0, 0.0
         eng.vec_axpby(0.0, w, 1.0 / beta, w)
+        Hd, Hh = self.Hd, self.Hh
+        Hn = Hh.numpy()
         H = np.zeros((m + 1, m))
         cs, sn = np.zeros(m), np.zeros(m)
         g = np.zeros(m + 1)
         g[0] = beta
-        k = 0
-        for j in range(m):
-            self.precondition(V[j], Z[j])                  # z_j = M^-1 v_j
-            wj = V[j + 1]
-            self.apply(Z[j], wj)
+        events = self.events
+
+        def column(j):
+            """Givens-reduce column j; returns (converged, breakdown)."""
             hcol = np.zeros(j + 2)
-            for _ in range(2):                             # classical Gram-Schmidt, twice
-                eng.vec_dots(V, j + 1, wj, self.h)
-                eng.vec_gemv(V, j + 1, self.h, -1.0, wj)
-                hcol[:j + 1] += self.h[:j + 1].cpu().numpy()
-            hn = self.norm(wj)
+            hcol[:j + 1] = Hn[j, 0, :j + 1] + Hn[j, 1, :j + 1]
+            hn = math.sqrt(max(Hn[j, 2, 0], 0.0))
             hcol[j + 1] = hn
-            if hn > 0.0:
-                eng.vec_axpby(0.0, wj, 1.0 / hn, wj)
-            for i in range(j):                             # apply previous Givens rotations
+            for i in range(j):                             # previous Givens rotations
                 t = cs[i] * hcol[i] + sn[i] * hcol[i + 1]
                 hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1]
                 hcol[i] = t
@@ -293,9 +302,34 @@ class NewtonKrylov:
             g[j + 1] = -sn[j] * g[j]
             g[j] = cs[j] * g[j]
             H[:j + 2, j] = hcol
-            k = j + 1
-            if abs(g[j + 1]) <= tol * bnorm or hn == 0.0:
-                break
+            return abs(g[j + 1]) <= tol * bnorm, hn == 0.0
+
+        k = m
+        for j in range(m):
+            self.precondition(V[j], Z[j])                  # z_j = M^-1 v_j
+            wj = V[j + 1]
+            self.apply(Z[j], wj)
+            for ps in range(2):                            # classical Gram-Schmidt, twice
+                eng.vec_dots(V, j + 1, wj, Hd[j, ps])
+                eng.vec_gemv(V, j + 1, Hd[j, ps], -1.0, wj)
+            eng.vec_dots(wj.view(1, -1), 1, wj, Hd[j, 2])   # ||w||^2
+            eng.vec_normalize(Hd[j, 2], wj)
+            Hh[j].copy_(Hd[j], non_blocking=True)
+            events[j].record()
+            if j >= 1:
+                events[j - 1].synchronize()
+                conv, brk = column(j - 1)
+                if brk:                                    # v_j = 0: the space is invariant
+                    k = j
+                    break
+                if conv:
+                    events[j].synchronize()
+                    column(j)
+                    k = j + 1
+                    break
+        else:
+            events[m - 1].synchronize()
+            column(m - 1)
         y = np.linalg.solve(np.triu(H[:k, :k]), g[:k]) if k else np.zeros(0)
         if k:
             self.h[:k].copy_(torch.from_numpy(y))
@@ -379,7 +413,7 @@ class NewtonKrylov:
                 st.stalled = True
                 if verbose:
                     print(f"[newton {self.precision}] step {it + 1}: no step length down to {alpha} lowers "
-                          f"|r| = {rn:.6e}; stopping", flush=True)
+                          f"|r| = {rn:.6e}; stopping", file=sys.stderr, flush=True)
                 break
             eng.vec_axpby(1.0, trial, 0.0, x)
             rn = rt
@@ -388,7 +422,7 @@ class NewtonKrylov:
             st.sufficient_decrease.append(ok)
             if verbose:
                 print(f"[newton {self.precision}] step {it + 1}: |r| = {rn:.6e}, krylov {its}, "
-                      f"linear reduction {red:.2e}, alpha {alpha}", flush=True)
+                      f"linear reduction {red:.2e}, alpha {alpha}", file=sys.stderr, flush=True)
         u.copy_(self.split(x)[0])
         p.copy_(self.split(x)[1])
         torch.cuda.synchronize()

@@ -106,6 +106,15 @@ def test_vector_kernels(torch_cuda):
         z = torch.empty_like(w)
         eng.vec_mul(d, w, z)
         assert torch.allclose(z.double(), d * w.double(), rtol=1e-6)
+        # device-side normalisation by a squared norm held on the device (0 for a zero norm)
+        nrm2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        eng.vec_dots(w.view(1, -1), 1, w, nrm2)
+        y = w.clone()
+        eng.vec_normalize(nrm2, y)
+        assert torch.allclose(y.double(), w.double() / w.double().norm(), rtol=1e-6 if dt == torch.float32 else 1e-14)
+        nrm2.zero_()
+        eng.vec_normalize(nrm2, y)
+        assert torch.count_nonzero(y) == 0
         # b = 0: y is written without being read (BLAS convention), so NaN or Inf bits in an
         # uninitialised y cannot leak into the result
         y = torch.full_like(w, float("nan"))
