@@ -49,6 +49,12 @@ template <typename T, int P> struct Tab {
                     // L[j][q] = lambda_j(g_q), the Lagrange basis on the k-1 Gauss points (j < k-1)
   T w[P];           // Gauss weights
   T G[P][P];        // G[i][a] = l_a'(xi_i): derivative of the Lagrange basis at the Gauss-Lobatto nodes
+  // Even/odd folded forms of M = B, D, B^T, D^T (K = 0..3) for output rows q < (P+1)/2 and
+  // m < P/2: Ke[K][q][m] = (M[q][m] + M[q][P-1-m]) / 2, Ko[K][q][m] = (M[q][m] - M[q][P-1-m]) / 2,
+  // Kc[K][q] = M[q][P/2] (odd P; the centre column).
+  T Ke[4][(P + 1) / 2][P / 2];
+  T Ko[4][(P + 1) / 2][P / 2];
+  T Kc[4][(P + 1) / 2];
 };
 
 // Pressure spaces (Sec. 3.2.2): P_{k-1} with normalised Legendre products, or Q_{k-2} with the

@@ -119,12 +119,13 @@ template <typename T, int P> __device__ __forceinline__ void interp_line_t(const
   for (int m = 0; m < P; ++m) v[m] = o[m];
 }
 
-// LDS strides chosen against bank conflicts (32 banks of 4 bytes): the z-plane stride SZ
-// spreads the P lines of a y-line access over distinct banks, and the element stride puts the
-// elements sharing a half-wavefront on disjoint banks.
+// LDS strides chosen against bank conflicts: the z-plane stride SZ spreads the P lines of a
+// y-line access over distinct banks, and the element pad PADE shifts the elements that share a
+// wavefront onto disjoint banks.  The values minimise the summed conflict cost of the z-, y- and
+// x-line accesses of one block under 32- and 64-bank models of 4-byte banks.
 template <typename T, int P> struct LdsShape { static constexpr int SZ = P * P, PADE = 0; };
 template <typename T> struct LdsShape<T, 4> { static constexpr int SZ = 20, PADE = sizeof(T) == 8 ? 8 : 0; };
-template <typename T> struct LdsShape<T, 5> { static constexpr int SZ = 26, PADE = 0; };
+template <typename T> struct LdsShape<T, 5> { static constexpr int SZ = 25, PADE = sizeof(T) == 8 ? 12 : 8; };
 
 // Element workspace: NB buffers of P planes each; point (x, y, z) at x + P*y + SZ*z.
 template <typename T, int P> struct Ws {
@@ -256,6 +257,74 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- folded 1D products
+// Gauss points and Gauss-Lobatto nodes are symmetric about 0, so M[P-1-q][P-1-m] = s M[q][m] with
+// s = +1 for B and B^T and s = -1 for D and D^T.  With the input split into even and odd parts
+// about its centre, e_m = v_m + v_{P-1-m} and o_m = v_m - v_{P-1-m}, the output pair (q, P-1-q)
+// is E_q +- O_q (s = +1) or O_q +- E_q (s = -1), where E_q = sum_m Ke[q][m] e_m (+ Kc[q] v_c)
+// and O_q = sum_m Ko[q][m] o_m: about 2/3 of the multiply-adds of the plain P x P product.
+template <typename T, int P> struct Fold {
+  T e[P / 2], o[P / 2], c;
+};
+template <typename T, int P>
+__device__ __forceinline__ Fold<T, P> fold(const T (&v)[P]) {
+  Fold<T, P> f;
+#pragma unroll
+  for (int m = 0; m < P / 2; ++m) {
+    f.e[m] = v[m] + v[P - 1 - m];
+    f.o[m] = v[m] - v[P - 1 - m];
+  }
+  f.c = (P % 2) ? v[P / 2] : T(0);
+  return f;
+}
+// An output in folded form: out[q] = ev[q] + od[q], out[P-1-q] = ev[q] - od[q] (q < P/2), and
+// out[P/2] = ev[P/2] for odd P.
+template <typename T, int P> struct Acc {
+  T ev[(P + 1) / 2], od[P / 2];
+  __device__ __forceinline__ Acc() {
+#pragma unroll
+    for (int q = 0; q < (P + 1) / 2; ++q) ev[q] = 0;
+#pragma unroll
+    for (int q = 0; q < P / 2; ++q) od[q] = 0;
+  }
+  __device__ __forceinline__ void unfold(T (&out)[P]) const {
+#pragma unroll
+    for (int q = 0; q < P / 2; ++q) {
+      out[q] = ev[q] + od[q];
+      out[P - 1 - q] = ev[q] - od[q];
+    }
+    if (P % 2) out[P / 2] = ev[P / 2];
+  }
+};
+// a += M v for the folded table K (0 = B, 1 = D, 2 = B^T, 3 = D^T) of symmetry sign S
+template <int K, typename T, int P>
+__device__ __forceinline__ void acc_mv(Acc<T, P> &a, const Tab<T, P> &tb, const Fold<T, P> &f) {
+  constexpr int H = P / 2;
+  constexpr bool EVEN = K % 2 == 0;   // B, B^T: s = +1
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    T &te = EVEN ? a.ev[q] : a.od[q];   // receives E_q
+    T &to = EVEN ? a.od[q] : a.ev[q];   // receives O_q
+#pragma unroll
+    for (int m = 0; m < H; ++m) te += tb.Ke[K][q][m] * f.e[m];
+    if (P % 2) te += tb.Kc[K][q] * f.c;
+#pragma unroll
+    for (int m = 0; m < H; ++m) to += tb.Ko[K][q][m] * f.o[m];
+  }
+  if (P % 2) {
+    // centre row: only the even part survives for s = +1, only the odd part for s = -1
+    if (EVEN) {
+#pragma unroll
+      for (int m = 0; m < H; ++m) a.ev[H] += tb.Ke[K][H][m] * f.e[m];
+      a.ev[H] += tb.Kc[K][H] * f.c;
+    } else {
+#pragma unroll
+      for (int m = 0; m < H; ++m) a.ev[H] += tb.Ko[K][H][m] * f.o[m];
+    }
+  }
+}
+enum { KB = 0, KD = 1, KBT = 2, KDT = 3 };
+
 // ---------------------------------------------------------------- sum-factorised gradient
 // z-line nodal values -> reference gradient at the x-line's quadrature points:
 //   gx = (D x B x B) v, gy = (B x D x B) v, gz = (B x B x D) v  (x fastest in the Kronecker order).
@@ -263,18 +332,18 @@ __device__ void hang_bwd(T (&v)[3][P], uint32_t cm, Ws<T, P> w, const Tab<T, P> 
 template <typename T, int P>
 __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws<T, P> w, const Tab<T, P> &tb,
                          int t, bool act) {
-  constexpr int P2 = P * P;
   if (act) {
+    const Fold<T, P> f = fold<T, P>(v);
+    Acc<T, P> ab, ad;
+    acc_mv<KB>(ab, tb, f);
+    acc_mv<KD>(ad, tb, f);
+    T a[P], d[P];
+    ab.unfold(a);
+    ad.unfold(d);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      T a = 0, d = 0;
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        a += tb.B[q][m] * v[m];
-        d += tb.D[q][m] * v[m];
-      }
-      w.b(0)[w.zl(t, q)] = a;
-      w.b(1)[w.zl(t, q)] = d;
+      w.b(0)[w.zl(t, q)] = a[q];
+      w.b(1)[w.zl(t, q)] = d[q];
     }
   }
   __syncthreads();
@@ -286,18 +355,20 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
       a[m] = w.b(0)[i + P * m + w.SZ * z];
       b[m] = w.b(1)[i + P * m + w.SZ * z];
     }
+    const Fold<T, P> fa = fold<T, P>(a), fb = fold<T, P>(b);
+    Acc<T, P> a0, a1, a2;
+    acc_mv<KB>(a0, tb, fa);
+    acc_mv<KD>(a1, tb, fa);
+    acc_mv<KB>(a2, tb, fb);
+    T s0[P], s1[P], s2[P];
+    a0.unfold(s0);
+    a1.unfold(s1);
+    a2.unfold(s2);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        s0 += tb.B[q][m] * a[m];
-        s1 += tb.D[q][m] * a[m];
-        s2 += tb.B[q][m] * b[m];
-      }
-      w.b(2)[i + P * q + w.SZ * z] = s0;
-      w.b(3)[i + P * q + w.SZ * z] = s1;
-      w.b(4)[i + P * q + w.SZ * z] = s2;
+      w.b(2)[i + P * q + w.SZ * z] = s0[q];
+      w.b(3)[i + P * q + w.SZ * z] = s1[q];
+      w.b(4)[i + P * q + w.SZ * z] = s2[q];
     }
   }
   __syncthreads();
@@ -309,19 +380,13 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
       b[m] = w.b(3)[m + w.xl(t)];
       c[m] = w.b(4)[m + w.xl(t)];
     }
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      T x0 = 0, x1 = 0, x2 = 0;
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        x0 += tb.D[q][m] * a[m];
-        x1 += tb.B[q][m] * b[m];
-        x2 += tb.B[q][m] * c[m];
-      }
-      gx[q] = x0;
-      gy[q] = x1;
-      gz[q] = x2;
-    }
+    Acc<T, P> x0, x1, x2;
+    acc_mv<KD>(x0, tb, fold<T, P>(a));
+    acc_mv<KB>(x1, tb, fold<T, P>(b));
+    acc_mv<KB>(x2, tb, fold<T, P>(c));
+    x0.unfold(gx);
+    x1.unfold(gy);
+    x2.unfold(gz);
   }
 }
 
@@ -330,21 +395,21 @@ __device__ void grad_fwd(const T (&v)[P], T (&gx)[P], T (&gy)[P], T (&gz)[P], Ws
 template <typename T, int P, bool VALUE>
 __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], const T (&f0)[P], T (&out)[P],
                          Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
-  constexpr int P2 = P * P;
   if (act) {
+    Acc<T, P> h0, h1, h2;
+    acc_mv<KDT>(h0, tb, fold<T, P>(fx));
+    if (VALUE) acc_mv<KBT>(h0, tb, fold<T, P>(f0));
+    acc_mv<KBT>(h1, tb, fold<T, P>(fy));
+    acc_mv<KBT>(h2, tb, fold<T, P>(fz));
+    T o0[P], o1[P], o2[P];
+    h0.unfold(o0);
+    h1.unfold(o1);
+    h2.unfold(o2);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      T h0 = 0, h1 = 0, h2 = 0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        h0 += tb.D[q][i] * fx[q];
-        if (VALUE) h0 += tb.B[q][i] * f0[q];
-        h1 += tb.B[q][i] * fy[q];
-        h2 += tb.B[q][i] * fz[q];
-      }
-      w.b(0)[i + w.xl(t)] = h0;
-      w.b(1)[i + w.xl(t)] = h1;
-      w.b(2)[i + w.xl(t)] = h2;
+      w.b(0)[i + w.xl(t)] = o0[i];
+      w.b(1)[i + w.xl(t)] = o1[i];
+      w.b(2)[i + w.xl(t)] = o2[i];
     }
   }
   __syncthreads();
@@ -357,17 +422,17 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
       b[q] = w.b(1)[i + P * q + w.SZ * z];
       c[q] = w.b(2)[i + P * q + w.SZ * z];
     }
+    Acc<T, P> k0, k1;
+    acc_mv<KBT>(k0, tb, fold<T, P>(a));
+    acc_mv<KDT>(k0, tb, fold<T, P>(b));
+    acc_mv<KBT>(k1, tb, fold<T, P>(c));
+    T o0[P], o1[P];
+    k0.unfold(o0);
+    k1.unfold(o1);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      T k0 = 0, k1 = 0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        k0 += tb.B[q][j] * a[q];
-        k0 += tb.D[q][j] * b[q];
-        k1 += tb.B[q][j] * c[q];
-      }
-      w.b(3)[i + P * j + w.SZ * z] = k0;
-      w.b(4)[i + P * j + w.SZ * z] = k1;
+      w.b(3)[i + P * j + w.SZ * z] = o0[j];
+      w.b(4)[i + P * j + w.SZ * z] = o1[j];
     }
   }
   __syncthreads();
@@ -378,16 +443,10 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
       a[q] = w.b(3)[w.zl(t, q)];
       b[q] = w.b(4)[w.zl(t, q)];
     }
-#pragma unroll
-    for (int z = 0; z < P; ++z) {
-      T o = 0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        o += tb.B[q][z] * a[q];
-        o += tb.D[q][z] * b[q];
-      }
-      out[z] = o;
-    }
+    Acc<T, P> o;
+    acc_mv<KBT>(o, tb, fold<T, P>(a));
+    acc_mv<KDT>(o, tb, fold<T, P>(b));
+    o.unfold(out);
   }
 }
 

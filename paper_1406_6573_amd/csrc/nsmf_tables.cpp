@@ -164,6 +164,20 @@ Tab<T, P> make_tab(const HostTables &h, bool bf16_ops) {
   for (int q = 0; q < P; ++q) t.w[q] = (T)h.w[q];
   for (int i = 0; i < P; ++i)
     for (int a = 0; a < P; ++a) t.G[i][a] = (T)h.G[i][a];
+  // folded forms, from the entries as stored (bfloat16-rounded for the bf16 variant)
+  for (int K = 0; K < 4; ++K) {
+    auto M = [&](int q, int m) -> double {
+      const int r = K < 2 ? q : m, c = K < 2 ? m : q;
+      return (K % 2 == 0) ? (double)t.B[r][c] : (double)t.D[r][c];
+    };
+    for (int q = 0; q < (P + 1) / 2; ++q) {
+      for (int m = 0; m < P / 2; ++m) {
+        t.Ke[K][q][m] = (T)(0.5 * (M(q, m) + M(q, P - 1 - m)));
+        t.Ko[K][q][m] = (T)(0.5 * (M(q, m) - M(q, P - 1 - m)));
+      }
+      t.Kc[K][q] = (P % 2) ? (T)M(q, P / 2) : T(0);
+    }
+  }
   return t;
 }
 
