@@ -759,23 +759,48 @@ __device__ __forceinline__ void frame_out(T (&y)[3][P], const T (&Q)[9]) {
 // upload).  Where two vertically adjacent elements of the block share a z-face, the lower
 // element's top slot also takes the upper element's bottom value and the latter is not stored
 // (pos = -1): fewer element-vector entries to write and to assemble.  P = 4: each thread stores
-// its z-line through pos[e][a] (loaded only now, so it holds no registers during the element
-// work); the block is one wavefront, and the upper element's bottom values come from lane
-// + P^2.  P = 3, 5: the block first stages its results in LDS; then lane l writes the l-th entry
-// of the block's stored slots sorted by entry, so that adjacent lanes write adjacent entries
-// (measured 3% faster there, slower for P = 4).  All threads of the block must call; the
-// staging area reuses the block's workspace.
-template <typename T, int P>
-__device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int64_t e, T *stage, int el, int t,
-                                           bool act, const T (&v)[3][P]) {
+// its z-line through pos[e][a]; the block is one wavefront, and the upper element's bottom values
+// come from lane + P^2.  P = 3, 5: the block first stages its results in LDS; then lane l writes
+// the l-th entry of the block's stored slots sorted by entry, so that adjacent lanes write
+// adjacent entries (measured 3% faster there, slower for P = 4).  The staging area reuses the
+// block's workspace.
+//
+// The store positions are read by store_index, separately from the store, so that a kernel can
+// request them early and hide their latency behind the element work.
+template <int P> struct StoreIndex {
+  static constexpr int R = P == 4 ? P : store_slots<P>() / Launch<P>::NT;
+  int32_t pos[R];      // P = 4: the thread's z-line slots; else the thread's sorted entries
+  uint32_t code[P == 4 ? 1 : R];
+};
+template <int P>
+__device__ __forceinline__ StoreIndex<P> store_index(const MeshView &m, int lb, int64_t e, int t, bool act) {
   constexpr int E = Launch<P>::E, NT = Launch<P>::NT, P2 = P * P, EP3 = E * P2 * P, SB = store_slots<P>();
+  StoreIndex<P> ix;
+  if constexpr (P == 4) {
+#pragma unroll
+    for (int z = 0; z < P; ++z) ix.pos[z] = act ? m.pos[e * EP3 / E + t + P2 * z] : 0;
+    ix.code[0] = 0;
+  } else {
+    const int32_t *sp = m.spos + (size_t)lb * SB;
+    const uint16_t *ss = m.sslot + (size_t)lb * SB;
+#pragma unroll
+    for (int r = 0; r < ix.R; ++r) {
+      const int k = r * NT + (int)threadIdx.x;
+      ix.pos[r] = sp[k];
+      ix.code[r] = ss[k];
+    }
+  }
+  return ix;
+}
+// All threads of the block must call.
+template <typename T, int P>
+__device__ __forceinline__ void evec_store(T *ev, const MeshView &m, const StoreIndex<P> &ix, T *stage, int el, int t,
+                                           bool act, const T (&v)[3][P]) {
+  constexpr int E = Launch<P>::E, NT = Launch<P>::NT, P2 = P * P, EP3 = E * P2 * P;
   if constexpr (P == 4) {
     static_assert(NT == 64 && E * P2 == 64, "one wavefront per block expected");
-    int32_t pos[P];
-#pragma unroll
-    for (int z = 0; z < P; ++z) pos[z] = act ? m.pos[e * EP3 / E + t + P2 * z] : 0;
     // bottom slot of the element above (lane + P^2; lanes past the wavefront read their own)
-    const int32_t up_pos = __shfl_down(pos[0], P2);
+    const int32_t up_pos = __shfl_down(ix.pos[0], P2);
     T up[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) up[c] = __shfl_down(v[c][0], P2);
@@ -783,9 +808,9 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
     const bool take_up = el + 1 < E && up_pos < 0;
 #pragma unroll
     for (int z = 0; z < P; ++z) {
-      if (pos[z] < 0) continue;
+      if (ix.pos[z] < 0) continue;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ev[c * m.n_ent + pos[z]] = (z == P - 1 && take_up) ? v[c][z] + up[c] : v[c][z];
+      for (int c = 0; c < 3; ++c) ev[c * m.n_ent + ix.pos[z]] = (z == P - 1 && take_up) ? v[c][z] + up[c] : v[c][z];
     }
   } else {
     static_assert(3 * EP3 <= E * Ws<T, P>::ES, "staging area exceeds the block workspace");
@@ -797,14 +822,11 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
         for (int z = 0; z < P; ++z) stage[c * EP3 + z * E * P2 + el * P2 + t] = v[c][z];
     __syncthreads();
     if (ev == nullptr) return;
-    const int32_t *sp = m.spos + (size_t)lb * SB;
-    const uint16_t *ss = m.sslot + (size_t)lb * SB;
 #pragma unroll
-    for (int r = 0; r < SB / NT; ++r) {
-      const int k = r * NT + (int)threadIdx.x;
-      const int32_t pos = sp[k];
+    for (int r = 0; r < ix.R; ++r) {
+      const int32_t pos = ix.pos[r];
       if (pos >= 0) {
-        const int code = ss[k], sl = code & 0x7FFF;
+        const int code = (int)ix.code[r], sl = code & 0x7FFF;
         // merged top slot: add the bottom slot (el + 1, x, y, 0) of the element above
         const int below = sl - (P - 1) * E * P2 + P2;
 #pragma unroll
@@ -813,6 +835,11 @@ __device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int
       }
     }
   }
+}
+template <typename T, int P>
+__device__ __forceinline__ void evec_store(T *ev, const MeshView &m, int lb, int64_t e, T *stage, int el, int t,
+                                           bool act, const T (&v)[3][P]) {
+  evec_store<T, P>(ev, m, store_index<P>(m, lb, e, t, act), stage, el, t, act, v);
 }
 
 // ================================================================= kernels
@@ -992,13 +1019,19 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
   const int64_t e = tile_elem<E>(m, lb, el);
   const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
-  // connectivity first: the gather of x waits on it
+  // connectivity first: the gather of x waits on it.  The store positions are requested at once
+  // too, so that their latency is hidden behind the element work instead of stalling the block's
+  // end, except in FP64 with P = 5, where the extra live registers would halve the occupancy.
+  constexpr bool kEarlyIndex = !(sizeof(T) == 8 && P == 5);
   uint32_t nw[P];
   load_words<P>(m.en + e * P3, t, act, nw);
+  StoreIndex<P> ix;
+  if constexpr (kEarlyIndex) ix = store_index<P>(m, lb, e, t, act);
   T y[3][P];
   apply_elem<T, P, GEO, VJP, PS, FR, true>(m, gv, *tbp, st_, fst, beta, xu, xp, yp, inv_n, g_logA, g_beta, smem, red, lb,
                                            tid, t, els, e, act, nw, y);
-  evec_store<T, P>(yu, m, lb, e, smem, els, t, act, y);
+  if constexpr (!kEarlyIndex) ix = store_index<P>(m, lb, e, t, act);
+  evec_store<T, P>(yu, m, ix, smem, els, t, act, y);
 }
 
 
