@@ -479,9 +479,9 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   NSMF_TRY(ctx, ctx->geo_el64.alloc(nel_geo), "hipMalloc");
   NSMF_TRY(ctx, ctx->geo_el32.alloc(nel_geo), "hipMalloc");
   if (ctx->geo == GEO_COLUMN) {
-    NSMF_TRY(ctx, ctx->geo_qp64.alloc(4 * nqp), "hipMalloc");
-    NSMF_TRY(ctx, ctx->geo_qp32.alloc(4 * nqp), "hipMalloc");
-    NSMF_TRY(ctx, launch_fill(s, ctx->geo_qp64.p, 8 * nqp), "fill");
+    NSMF_TRY(ctx, ctx->geo_qp64.alloc(NGEOQP * nqp), "hipMalloc");
+    NSMF_TRY(ctx, ctx->geo_qp32.alloc(NGEOQP * nqp), "hipMalloc");
+    NSMF_TRY(ctx, launch_fill(s, ctx->geo_qp64.p, 2 * NGEOQP * nqp), "fill");
   }
   NSMF_TRY(ctx, ctx->face64.alloc((size_t)NB * 4 * P2), "hipMalloc");
   NSMF_TRY(ctx, ctx->face32.alloc((size_t)NB * 4 * P2), "hipMalloc");
@@ -489,7 +489,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
                                      ctx->geo_qp64.p, ctx->face64.p, nullptr),
            "geometry");
   NSMF_TRY(ctx, launch_d2f(s, ctx->geo_el64.p, ctx->geo_el32.p, nel_geo), "convert");
-  if (ctx->geo == GEO_COLUMN) NSMF_TRY(ctx, launch_d2f(s, ctx->geo_qp64.p, ctx->geo_qp32.p, 4 * nqp), "convert");
+  if (ctx->geo == GEO_COLUMN) NSMF_TRY(ctx, launch_d2f(s, ctx->geo_qp64.p, ctx->geo_qp32.p, NGEOQP * nqp), "convert");
   NSMF_TRY(ctx, launch_d2f(s, ctx->face64.p, ctx->face32.p, (size_t)NB * 4 * P2), "convert");
   NSMF_TRY(ctx, hipStreamSynchronize(s), "geometry");
 

@@ -11,6 +11,8 @@ enum GeoKind { GEO_AFFINE = 0, GEO_COLUMN = 1 };
 
 // Node-id word of the device connectivity: bits 0..27 node id, bits 28..30 the
 // Dirichlet mask of components x, y, z of that node, bit 31 a node with a local frame.
+// per-point geometry fields of column-mapped elements: d zeta/dx, d zeta/dy, d zeta/dz
+constexpr int NGEOQP = 3;
 constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;
 constexpr int MASK_SHIFT = 28;
 constexpr uint32_t ROT_BIT = 1u << 31;   // the slot's node has its unknowns in a local frame

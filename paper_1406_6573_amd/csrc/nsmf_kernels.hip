@@ -479,29 +479,40 @@ __device__ __forceinline__ void load_field(const T *__restrict__ base, int lb, i
 }
 
 // ---------------------------------------------------------------- geometry access
+// Column-mapped elements: x depends on xi and y on eta only (affine per column), z on all three, so
+// J^-1 has the constant entries d xi/dx, d eta/dy and the per-point row (d zeta/dx, d zeta/dy,
+// d zeta/dz); detJ = (dx/dxi)(dy/deta)(dz/dzeta) = 1 / (jx jy c), so w detJ is formed from c where it
+// is used rather than stored (NGEOQP fields per point).
+template <typename T> __device__ __forceinline__ T recip(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);   // within 1 ulp
+  else return T(1) / x;
+}
 template <typename T, int P, int GEO> struct QpGeo {
   T jx, jy, jz;          // d xi/dx, d eta/dy, (affine) d zeta/dz
   T detJ;                // affine only
-  T a[P], b[P], c[P], wd[P];   // column: d zeta/dx, d zeta/dy, d zeta/dz, w detJ (x-line)
+  T wjz;                 // product w_j w_z of the Gauss weights of the thread's x-line (j, z)
+  T a[P], b[P], c[P];    // column: d zeta/dx, d zeta/dy, d zeta/dz (x-line)
+  // quadrature weight times detJ at point i of the x-line
+  __device__ __forceinline__ T wdet(const Tab<T, P> &tb, int i) const {
+    if (GEO == GEO_AFFINE) return tb.w[i] * wjz * detJ;
+    else return tb.w[i] * wjz * recip<T>(jx * jy * c[i]);
+  }
 };
 
 template <typename T, int P, int GEO, int NT>
 __device__ __forceinline__ void load_geo(QpGeo<T, P, GEO> &g, const GeoView<T> &gv, int64_t e, int lb, int tid,
                                          const Tab<T, P> &tb, int t) {
+  const int j = t % P, z = t / P;
+  g.wjz = tb.w[j] * tb.w[z];
   if (GEO == GEO_AFFINE) {
     const T *p = gv.el + 4 * e;
     g.jx = p[0]; g.jy = p[1]; g.jz = p[2]; g.detJ = p[3];
-    const int j = t % P, z = t / P;
-    const T wjz = tb.w[j] * tb.w[z] * g.detJ;
-#pragma unroll
-    for (int i = 0; i < P; ++i) g.wd[i] = tb.w[i] * wjz;
   } else {
     const T *p = gv.el + 2 * e;
     g.jx = p[0]; g.jy = p[1];
-    load_field<T, P, NT, 4>(gv.qp, lb, 0, tid, g.a);
-    load_field<T, P, NT, 4>(gv.qp, lb, 1, tid, g.b);
-    load_field<T, P, NT, 4>(gv.qp, lb, 2, tid, g.c);
-    load_field<T, P, NT, 4>(gv.qp, lb, 3, tid, g.wd);
+    load_field<T, P, NT, NGEOQP>(gv.qp, lb, 0, tid, g.a);
+    load_field<T, P, NT, NGEOQP>(gv.qp, lb, 1, tid, g.b);
+    load_field<T, P, NT, NGEOQP>(gv.qp, lb, 2, tid, g.c);
   }
 }
 
@@ -544,6 +555,9 @@ __device__ __forceinline__ void to_ref(const QpGeo<T, P, GEO> &g, int i, const T
 // P_{k-1}: exponents i+j+l <= k-1, ordered by (i+j+l, l, j, i); Q_{k-2}: the k-1 Gauss points
 // per direction, i fastest.  psi_m(x_i, y_j, z_l) = L[e0][i] L[e1][j] L[e2][l] at Gauss points.
 template <int P, int PS> constexpr int n_pres() { return PS == PS_P ? (P - 1) * P * (P + 1) / 6 : (P - 2) * (P - 2) * (P - 2); }
+// per-element stride (in doubles) of the apply kernel's reduction area: P^2 partial sums of the
+// parameter gradients, or the element's pressure coefficients while the forward sweeps run
+template <int P, int PS> constexpr int red_stride() { return n_pres<P, PS>() > P * P ? n_pres<P, PS>() : P * P; }
 template <int P, int PS> struct PExp {
   static constexpr int NP = n_pres<P, PS>();
   int e[NP][3];
@@ -859,7 +873,7 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
   constexpr int NT = Launch<P>::NT, P2 = P * P;
   constexpr int NP = n_pres<P, PS>();
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
-  double *redl = red + els * P2;
+  double *redl = red + els * red_stride<P, PS>();
   const int64_t N = m.n_nodes;
   // the linearisation data of the thread's P points are requested right after the connectivity
   // (the caller's) so that their latency overlaps the gather and the forward sweeps, for P = 4 and for
@@ -888,13 +902,18 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
     frame_in<T, P>(v, Q);
   }
   // geometry and pressure coefficients are needed only after the forward sweeps; requesting them
-  // here hides their latency behind the sweeps (per-point geometry of column-mapped elements)
+  // here hides their latency behind the sweeps (per-point geometry of column-mapped elements).
+  // The element's NP pressure coefficients are loaded once each (thread t < NP takes mode t) and
+  // passed through LDS (the parameter-gradient reduction area, not in use until after the
+  // quadrature-point step), instead of every thread holding all of them through the sweeps.
+  constexpr int NPT = (NP + P2 - 1) / P2;   // modes per thread
   QpGeo<T, P, GEO> g;
-  T xpl[NP];
+  T xpt[NPT];
   if (act) {
     load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
 #pragma unroll
-    for (int mm = 0; mm < NP; ++mm) xpl[mm] = xp[e * NP + mm];
+    for (int r = 0; r < NPT; ++r)
+      if (t + r * P2 < NP) xpt[r] = xp[e * NP + t + r * P2];
   }
   if constexpr (HANG)
     if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
@@ -903,10 +922,15 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
   T gr[3][3][P];
 #pragma unroll
   for (int c = 0; c < 3; ++c) grad_fwd<T, P>(v[c], gr[c][0], gr[c][1], gr[c][2], w, tb, t, act);
+  T *xps = reinterpret_cast<T *>(redl);
+  if (act)
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (t + r * P2 < NP) xps[t + r * P2] = xpt[r];
   __syncthreads();
 
   T pq[P];
-  if (act) pressure_interp<T, P, PS>(xpl, tb, t, pq);
+  if (act) pressure_interp<T, P, PS>(xps, tb, t, pq);
   T dw[P];
   double gA = 0.0;
   if constexpr (!kEarlyState) {
@@ -938,14 +962,15 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
     s += syz * eyz;
     if (VJP) gA += (double)s;
     const T ks = kS32 ? s : ka * s, muh = T(0.5) * mu;
-    const T pw = pq[i] * g.wd[i];
+    const T wd = g.wdet(tb, i);
+    const T pw = pq[i] * wd;
     tau[0][0] = mu * dxx - (ks * sxx + pw);
     tau[1][1] = mu * dyy - (ks * syy + pw);
     tau[2][2] = mu * dzz - (ks * szz + pw);
     tau[0][1] = tau[1][0] = muh * exy - ks * sxy;
     tau[0][2] = tau[2][0] = muh * exz - ks * sxz;
     tau[1][2] = tau[2][1] = muh * eyz - ks * syz;
-    dw[i] = (dxx + dyy + dzz) * g.wd[i];
+    dw[i] = (dxx + dyy + dzz) * wd;
     to_ref<T, P, GEO>(g, i, tau, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -1013,7 +1038,7 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
         T *__restrict__ yp, double inv_n, double *__restrict__ g_logA, double *__restrict__ g_beta) {
   constexpr int E = Launch<P>::E, P2 = P * P, P3 = P2 * P;
   __shared__ T smem[E * Ws<T, P>::ES];
-  __shared__ double red[E * P2];
+  __shared__ double red[E * red_stride<P, PS>()];
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = tile_elem<E>(m, lb, el);
@@ -1088,7 +1113,7 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
       const T dxy = 0.5 * (G[0][1] + G[1][0]), dxz = 0.5 * (G[0][2] + G[2][0]), dyz = 0.5 * (G[1][2] + G[2][1]);
       const T II = 0.5 * (dxx * dxx + dyy * dyy + dzz * dzz) + dxy * dxy + dxz * dxz + dyz * dyz;
       const T mu = Be * pow(II + eps, expo);
-      const T mup = g.wd[i] * mu;
+      const T mup = g.wdet(tb, i) * mu;
       const T ka = cf / ((II + eps) * mup);
       const T vals[NSTATE] = {mup, ka, mup * dxx, mup * dyy, mup * dzz, mup * dxy, mup * dxz, mup * dyz};
 #pragma unroll
@@ -1156,7 +1181,8 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
       const T mu = stv[0][i];
       const T sxx = stv[2][i], syy = stv[3][i], szz = stv[4][i];
       const T sxy = stv[5][i], sxz = stv[6][i], syz = stv[7][i];
-      const T pw = pq[i] * g.wd[i];
+      const T wd = g.wdet(tb, i);
+      const T pw = pq[i] * wd;
       T tau[3][3] = {{sxx - pw, sxy, sxz}, {sxy, syy - pw, syz}, {sxz, syz, szz - pw}};
       T f[3][3];
       to_ref<T, P, GEO>(g, i, tau, f);
@@ -1164,10 +1190,10 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < 3; ++r) fr[c][r][i] = f[c][r];
-      f0[0][i] = -bx * g.wd[i];
-      f0[1][i] = -by * g.wd[i];
-      f0[2][i] = -bz * g.wd[i];
-      dw[i] = (sxx + syy + szz) / mu * g.wd[i];
+      f0[0][i] = -bx * wd;
+      f0[1][i] = -by * wd;
+      f0[2][i] = -bz * wd;
+      dw[i] = (sxx + syy + szz) / mu * wd;
     }
   } else {
 #pragma unroll
@@ -1267,10 +1293,10 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
         if (GEO == GEO_AFFINE) {
           wd = tb.w[qx] * tb.w[qy] * tb.w[qz] * detJ;
         } else {
-          a = gv.qp[qp_at<P, NT, 4>(lb, 0, tidq, qx)];
-          b = gv.qp[qp_at<P, NT, 4>(lb, 1, tidq, qx)];
-          cc = gv.qp[qp_at<P, NT, 4>(lb, 2, tidq, qx)];
-          wd = gv.qp[qp_at<P, NT, 4>(lb, 3, tidq, qx)];
+          a = gv.qp[qp_at<P, NT, NGEOQP>(lb, 0, tidq, qx)];
+          b = gv.qp[qp_at<P, NT, NGEOQP>(lb, 1, tidq, qx)];
+          cc = gv.qp[qp_at<P, NT, NGEOQP>(lb, 2, tidq, qx)];
+          wd = tb.w[qx] * tb.w[qy] * tb.w[qz] / (jx * jy * cc);
         }
         // pressure: thread (j, z) of the x-line layout owns points (., j, z); here every
         // thread accumulates the points of its own tq = t for the lumped 1/mu mass
@@ -1403,9 +1429,9 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
       for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
       double a = 0, b = 0, cc = jz;
       if (GEO != GEO_AFFINE) {
-        a = gv.qp[qp_at<P, NT, 4>(lb, 0, tidq, qx)];
-        b = gv.qp[qp_at<P, NT, 4>(lb, 1, tidq, qx)];
-        cc = gv.qp[qp_at<P, NT, 4>(lb, 2, tidq, qx)];
+        a = gv.qp[qp_at<P, NT, NGEOQP>(lb, 0, tidq, qx)];
+        b = gv.qp[qp_at<P, NT, NGEOQP>(lb, 1, tidq, qx)];
+        cc = gv.qp[qp_at<P, NT, NGEOQP>(lb, 2, tidq, qx)];
       }
       double G[P][3], SG[P][3];
 #pragma unroll
@@ -1470,9 +1496,9 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
         for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
         double a = 0, b = 0, cc = jz;
         if (GEO != GEO_AFFINE) {
-          a = gv.qp[qp_at<P, NT, 4>(lb, 0, tidq, qx)];
-          b = gv.qp[qp_at<P, NT, 4>(lb, 1, tidq, qx)];
-          cc = gv.qp[qp_at<P, NT, 4>(lb, 2, tidq, qx)];
+          a = gv.qp[qp_at<P, NT, NGEOQP>(lb, 0, tidq, qx)];
+          b = gv.qp[qp_at<P, NT, NGEOQP>(lb, 1, tidq, qx)];
+          cc = gv.qp[qp_at<P, NT, NGEOQP>(lb, 2, tidq, qx)];
         }
         double G[P][3], SG[P][3];
 #pragma unroll
@@ -1757,10 +1783,9 @@ k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__r
       if (fabs(a[2][0]) > tol || fabs(a[2][1]) > tol || fabs(a[2][2] - r22) > tol) fl |= 2u;
       if (mode == 2) {
         const T j00 = a[0][0], j11 = a[1][1], j22 = a[2][2];
-        qp_out[qp_at<P, NT, 4>(lb, 0, tid, i)] = -a[2][0] / (j00 * j22);
-        qp_out[qp_at<P, NT, 4>(lb, 1, tid, i)] = -a[2][1] / (j11 * j22);
-        qp_out[qp_at<P, NT, 4>(lb, 2, tid, i)] = 1.0 / j22;
-        qp_out[qp_at<P, NT, 4>(lb, 3, tid, i)] = tb.w[i] * tb.w[j] * tb.w[z] * j00 * j11 * j22;
+        qp_out[qp_at<P, NT, NGEOQP>(lb, 0, tid, i)] = -a[2][0] / (j00 * j22);
+        qp_out[qp_at<P, NT, NGEOQP>(lb, 1, tid, i)] = -a[2][1] / (j11 * j22);
+        qp_out[qp_at<P, NT, NGEOQP>(lb, 2, tid, i)] = 1.0 / j22;
       }
     }
     if (t == 0 && mode == 1) {
