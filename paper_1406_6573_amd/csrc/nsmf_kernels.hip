@@ -2184,57 +2184,86 @@ k_lowo(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, c
 constexpr int ASM_NT = 256;
 constexpr int ASM_TILE = 4 * ASM_NT;
 
-// The entries of the block's nodes form one contiguous range [ptr[n0], ptr[n0 + NT]) of each
+// FP32: the entries of the block's nodes form one contiguous range [ptr[n0], ptr[n0 + NT]) of each
 // component plane of ev: it is streamed through LDS in tiles with coalesced loads, and each
-// thread sums its own node's segment from LDS in increasing slot order.
+// thread sums its own node's segment from LDS in increasing slot order.  FP64: see below.
 template <typename T>
 __global__ void __launch_bounds__(ASM_NT)
 k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_ent,
            const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f, T *__restrict__ y) {
-  __shared__ T tile[3][ASM_TILE];
-  const int64_t n0 = (int64_t)blockIdx.x * ASM_NT;
-  const int64_t n = n0 + threadIdx.x;
-  const int64_t nend = n0 + ASM_NT < N ? n0 + ASM_NT : N;
-  const int32_t r0 = ptr[n0], r1 = ptr[nend];
-  int32_t k0 = 0, k1 = 0;
-  if (n < N) {
-    k0 = ptr[n];
-    k1 = ptr[n + 1];
-  }
-  T s0 = 0, s1 = 0, s2 = 0;
-  for (int32_t c0 = r0; c0 < r1; c0 += ASM_TILE) {
-    const int32_t cn = r1 - c0 < ASM_TILE ? r1 - c0 : ASM_TILE;
-    T a[3][ASM_TILE / ASM_NT];
+  if constexpr (sizeof(T) == 8) {
+    // FP64: the tile would take 24 KiB of LDS per block and cap the occupancy; each thread reads
+    // its own segment instead, in predicated chunks of four entries (measured 3% faster there,
+    // 2% slower in FP32)
+    constexpr int CH = 4;
+    const int64_t n = (int64_t)blockIdx.x * ASM_NT + threadIdx.x;
+    if (n >= N) return;
+    const int32_t k0 = ptr[n], k1 = ptr[n + 1];
+    T sv[3] = {0, 0, 0};
+    for (int32_t k = k0; k < k1; k += CH) {
+      T a[3][CH];
 #pragma unroll
-    for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
-      const int j = (int)threadIdx.x + u * ASM_NT;
-      const bool in = j < cn;
-      a[0][u] = in ? ev[c0 + j] : T(0);
-      a[1][u] = in ? ev[n_ent + c0 + j] : T(0);
-      a[2][u] = in ? ev[2 * n_ent + c0 + j] : T(0);
+      for (int u = 0; u < CH; ++u) {
+        const bool in = k + u < k1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[c][u] = in ? ev[c * n_ent + k + u] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[c] += a[c][u];
     }
 #pragma unroll
-    for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
-      const int j = (int)threadIdx.x + u * ASM_NT;
-      tile[0][j] = a[0][u];
-      tile[1][j] = a[1][u];
-      tile[2][j] = a[2][u];
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = c * N + n;
+      y[i] = dm[i] ? (xm ? xm[i] : T(1)) : (f ? sv[c] - f[i] : sv[c]);
     }
-    __syncthreads();
-    const int32_t kb = k0 > c0 ? k0 : c0, ke = k1 < c0 + cn ? k1 : c0 + cn;
-    for (int32_t k = kb; k < ke; ++k) {
-      s0 += tile[0][k - c0];
-      s1 += tile[1][k - c0];
-      s2 += tile[2][k - c0];
+  } else {
+    __shared__ T tile[3][ASM_TILE];
+    const int64_t n0 = (int64_t)blockIdx.x * ASM_NT;
+    const int64_t n = n0 + threadIdx.x;
+    const int64_t nend = n0 + ASM_NT < N ? n0 + ASM_NT : N;
+    const int32_t r0 = ptr[n0], r1 = ptr[nend];
+    int32_t k0 = 0, k1 = 0;
+    if (n < N) {
+      k0 = ptr[n];
+      k1 = ptr[n + 1];
     }
-    __syncthreads();
-  }
-  if (n >= N) return;
-  const T sv[3] = {s0, s1, s2};
+    T s0 = 0, s1 = 0, s2 = 0;
+    for (int32_t c0 = r0; c0 < r1; c0 += ASM_TILE) {
+      const int32_t cn = r1 - c0 < ASM_TILE ? r1 - c0 : ASM_TILE;
+      T a[3][ASM_TILE / ASM_NT];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int64_t i = c * N + n;
-    y[i] = dm[i] ? (xm ? xm[i] : T(1)) : (f ? sv[c] - f[i] : sv[c]);
+      for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
+        const int j = (int)threadIdx.x + u * ASM_NT;
+        const bool in = j < cn;
+        a[0][u] = in ? ev[c0 + j] : T(0);
+        a[1][u] = in ? ev[n_ent + c0 + j] : T(0);
+        a[2][u] = in ? ev[2 * n_ent + c0 + j] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < ASM_TILE / ASM_NT; ++u) {
+        const int j = (int)threadIdx.x + u * ASM_NT;
+        tile[0][j] = a[0][u];
+        tile[1][j] = a[1][u];
+        tile[2][j] = a[2][u];
+      }
+      __syncthreads();
+      const int32_t kb = k0 > c0 ? k0 : c0, ke = k1 < c0 + cn ? k1 : c0 + cn;
+      for (int32_t k = kb; k < ke; ++k) {
+        s0 += tile[0][k - c0];
+        s1 += tile[1][k - c0];
+        s2 += tile[2][k - c0];
+      }
+      __syncthreads();
+    }
+    if (n >= N) return;
+    const T sv[3] = {s0, s1, s2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = c * N + n;
+      y[i] = dm[i] ? (xm ? xm[i] : T(1)) : (f ? sv[c] - f[i] : sv[c]);
+    }
   }
 }
 
