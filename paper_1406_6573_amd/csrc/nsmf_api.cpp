@@ -116,7 +116,8 @@ struct nsmf_ctx {
   bool lines_ok = false, have_lines = false;
   int64_t n_lines = 0;
   std::vector<int32_t> h_line_ptr, h_line_node, h_lptr, h_lslot;
-  DevBuf<int32_t> line_ptr, line_node, lptr, lslot;
+  DevBuf<int32_t> line_ptr, line_node, line_prow, line_row, line_first, lptr, lslot;
+  int64_t line_nr = 0;   // line-block rows per component (interleaved groups, padded)
   DevBuf<double> lbuf, lfac64;
   DevBuf<float> lfac32;
   // timing
@@ -161,7 +162,9 @@ struct nsmf_ctx {
     has_frames = false;
     c_cpt.free(); c_node.free(); c_w.free(); c_zeta.free(); c_wt.free(); c_ptr.free();
     n_cpts = 0;
-    line_ptr.free(); line_node.free(); lptr.free(); lslot.free(); lbuf.free(); lfac64.free(); lfac32.free();
+    line_ptr.free(); line_node.free(); line_prow.free(); line_row.free(); line_first.free(); lptr.free(); lslot.free();
+    lbuf.free(); lfac64.free(); lfac32.free();
+    line_nr = 0;
     h_line_ptr.clear(); h_line_node.clear(); h_lptr.clear(); h_lslot.clear();
     lines_ok = have_lines = false;
     n_lines = 0;
@@ -770,13 +773,47 @@ int nsmf_line_setup(nsmf_ctx *ctx, int64_t *n_lines) {
   hipStream_t s = ctx->stream;
   const int W = ctx->P;   // upper band entries per row: offsets 0..k
   if (!ctx->line_ptr.p) {
+    // Interleaved line-block rows: lines in groups of LINE_GROUP, node i of line l at row
+    // lrow[l] + LINE_GROUP i with lrow[l] = (group offset) + l mod LINE_GROUP, each group padded to
+    // its longest line; prow[n] = row of node n.  lfirst[l] = first node of a line whose node ids are
+    // consecutive, -1 otherwise.
+    const int64_t NL = ctx->n_lines;
+    std::vector<int32_t> prow((size_t)ctx->n_nodes), lrow((size_t)NL), lfirst((size_t)NL);
+    int64_t nr = 0;
+    for (int64_t g0 = 0; g0 < NL; g0 += LINE_GROUP) {
+      int32_t longest = 0;
+      for (int64_t l = g0; l < NL && l < g0 + LINE_GROUP; ++l)
+        longest = std::max(longest, ctx->h_line_ptr[l + 1] - ctx->h_line_ptr[l]);
+      for (int64_t l = g0; l < NL && l < g0 + LINE_GROUP; ++l) {
+        lrow[l] = (int32_t)(nr + (l - g0));
+        const int32_t b0 = ctx->h_line_ptr[l], b1 = ctx->h_line_ptr[l + 1];
+        bool cons = true;
+        for (int32_t q = b0; q < b1; ++q) {
+          prow[ctx->h_line_node[q]] = lrow[l] + LINE_GROUP * (q - b0);
+          if (q > b0) cons = cons && ctx->h_line_node[q] == ctx->h_line_node[b0] + (q - b0);
+        }
+        lfirst[l] = cons ? ctx->h_line_node[b0] : -1;
+      }
+      nr += (int64_t)LINE_GROUP * longest;
+    }
+    if (nr >= (int64_t)0x7FFFFFFF) return ctx->fail(NSMF_EUNSUP, "too many line-block rows for int32 indices");
+    ctx->line_nr = nr;
     NSMF_TRY(ctx, ctx->line_ptr.alloc(ctx->h_line_ptr.size()), "hipMalloc");
     NSMF_TRY(ctx, ctx->line_node.alloc(ctx->h_line_node.size()), "hipMalloc");
+    NSMF_TRY(ctx, ctx->line_prow.alloc(prow.size()), "hipMalloc");
+    NSMF_TRY(ctx, ctx->line_row.alloc(NL > 0 ? (size_t)NL : 1), "hipMalloc");
+    NSMF_TRY(ctx, ctx->line_first.alloc(NL > 0 ? (size_t)NL : 1), "hipMalloc");
+    NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_prow.p, prow.data(), prow.size() * 4, hipMemcpyHostToDevice, s), "copy");
+    if (NL > 0) {
+      NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_row.p, lrow.data(), lrow.size() * 4, hipMemcpyHostToDevice, s), "copy");
+      NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_first.p, lfirst.data(), lfirst.size() * 4, hipMemcpyHostToDevice, s),
+               "copy");
+    }
     NSMF_TRY(ctx, ctx->lptr.alloc(ctx->h_lptr.size()), "hipMalloc");
     NSMF_TRY(ctx, ctx->lslot.alloc(ctx->h_lslot.size() ? ctx->h_lslot.size() : 1), "hipMalloc");
     NSMF_TRY(ctx, ctx->lbuf.alloc((size_t)3 * ctx->n_inc * W), "hipMalloc");
-    NSMF_TRY(ctx, ctx->lfac64.alloc((size_t)3 * ctx->n_nodes * W), "hipMalloc");
-    NSMF_TRY(ctx, ctx->lfac32.alloc((size_t)3 * ctx->n_nodes * W), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lfac64.alloc((size_t)3 * ctx->line_nr * W), "hipMalloc");
+    NSMF_TRY(ctx, ctx->lfac32.alloc((size_t)3 * ctx->line_nr * W), "hipMalloc");
     NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_ptr.p, ctx->h_line_ptr.data(), ctx->h_line_ptr.size() * 4,
                                  hipMemcpyHostToDevice, s), "copy");
     NSMF_TRY(ctx, hipMemcpyAsync(ctx->line_node.p, ctx->h_line_node.data(), ctx->h_line_node.size() * 4,
@@ -790,8 +827,8 @@ int nsmf_line_setup(nsmf_ctx *ctx, int64_t *n_lines) {
   }
   NSMF_TRY(ctx,
            launch_lines(ctx->P, ctx->geo, s, ctx->mesh_view(), ctx->geo64(), ctx->tabs.p, ctx->st64.p, ctx->beta64.p,
-                        ctx->lptr.p, ctx->lslot.p, ctx->dmask.p, ctx->line_ptr.p, ctx->line_node.p, ctx->n_lines,
-                        ctx->lbuf.p, ctx->lfac64.p, ctx->lfac32.p),
+                        ctx->lptr.p, ctx->lslot.p, ctx->dmask.p, ctx->line_ptr.p, ctx->line_node.p, ctx->line_prow.p,
+                        ctx->line_row.p, ctx->line_nr, ctx->n_lines, ctx->lbuf.p, ctx->lfac64.p, ctx->lfac32.p),
            "line blocks");
   ctx->have_lines = true;
   if (n_lines) *n_lines = ctx->n_lines;
@@ -803,7 +840,8 @@ int nsmf_line_apply(nsmf_ctx *ctx, int prec, const void *x_u, void *y_u) {
   if (prec != 0 && prec != 1) return ctx->fail(NSMF_EINVAL, "line_apply precision must be 0 (double) or 1 (float)");
   if (!ctx->have_lines) return ctx->fail(NSMF_ESTATE, "line_apply needs nsmf_line_setup at the current state");
   NSMF_TRY(ctx,
-           launch_line_apply(ctx->stream, prec, ctx->P, ctx->n_nodes, ctx->line_ptr.p, ctx->line_node.p, ctx->n_lines,
+           launch_line_apply(ctx->stream, prec, ctx->P, ctx->n_nodes, ctx->line_ptr.p, ctx->line_node.p,
+                             ctx->line_row.p, ctx->line_nr, ctx->line_first.p, ctx->n_lines,
                              prec == 0 ? (const void *)ctx->lfac64.p : (const void *)ctx->lfac32.p, x_u, y_u),
            "line solve");
   return NSMF_OK;
@@ -820,7 +858,7 @@ int nsmf_vec_dots(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int6
   int rc = vec_check(ctx, prec, n);
   if (rc) return rc;
   if (!V || !w || !h || k < 1 || k > MAX_DOTS || ldv < n) return ctx->fail(NSMF_EINVAL, "bad nsmf_vec_dots arguments");
-  if (!ctx->dot_partial.p) NSMF_TRY(ctx, ctx->dot_partial.alloc((size_t)1024 * MAX_DOTS), "hipMalloc");
+  if (!ctx->dot_partial.p) NSMF_TRY(ctx, ctx->dot_partial.alloc((size_t)DOT_BLOCKS * MAX_DOTS), "hipMalloc");
   NSMF_TRY(ctx, launch_dots(ctx->stream, prec, n, k, V, ldv, w, ctx->dot_partial.p, h), "dots");
   return NSMF_OK;
 }

@@ -8,46 +8,143 @@
 namespace nsmf {
 
 constexpr int BLAS_NT = 256;
-constexpr int DOT_BLOCKS = 1024;
 
-// partial[b][i] = sum over the block's chunk of V[i][r] * w[r], i < k  (k <= MAX_DOTS)
-template <typename T>
+// 16-byte vectors of T (4 floats or 2 doubles) for the aligned paths below
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); static constexpr int W = 4; };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); static constexpr int W = 2; };
+template <typename T> __host__ __device__ inline bool aligned16(const T *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// partial[b][i] = sum over the block's chunk of V[i][r] * w[r], i < k  (k <= MAX_DOTS).  The basis
+// vectors are taken DOT_GROUP at a time, so w is read once per group rather than once per vector;
+// each thread's sums run in a fixed order and are combined by a fixed tree, so the result does not
+// depend on timing.  VEC: V, its row stride and w allow 16-byte loads; the chunks then cover whole
+// vectors of Vec16<T>::W entries, and the last block also takes the n mod W trailing entries.
+constexpr int DOT_GROUP = 8, DOT_ROWS = 2;
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(BLAS_NT)
 k_dots_partial(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const T *__restrict__ w,
                double *__restrict__ partial) {
-  __shared__ double red[BLAS_NT];
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = r0 + chunk < n ? r0 + chunk : n;
-  for (int i = 0; i < k; ++i) {
-    double s = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLAS_NT) s += (double)V[i * ldv + r] * (double)w[r];
-    red[threadIdx.x] = s;
+  __shared__ double red[DOT_GROUP][BLAS_NT];
+  constexpr int VW = VEC ? Vec16<T>::W : 1;
+  typedef typename Vec16<T>::type vec;
+  const int64_t nv = n / VW;   // whole vectors (VEC) or entries
+  const int64_t chunk = (nv + gridDim.x - 1) / gridDim.x;
+  const int64_t q0 = (int64_t)blockIdx.x * chunk, q1 = q0 + chunk < nv ? q0 + chunk : nv;
+  for (int i0 = 0; i0 < k; i0 += DOT_GROUP) {
+    double s[DOT_GROUP];
+#pragma unroll
+    for (int g = 0; g < DOT_GROUP; ++g) s[g] = 0.0;
+    // DOT_ROWS steps per iteration: that many times the independent loads in flight per thread
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += DOT_ROWS * BLAS_NT) {
+#pragma unroll
+      for (int u = 0; u < DOT_ROWS; ++u) {
+        const int64_t qu = q + (int64_t)u * BLAS_NT;
+        if (qu >= q1) break;
+        if constexpr (VEC) {
+          const vec wv = *reinterpret_cast<const vec *>(w + qu * VW);
+          vec v[DOT_GROUP];
+#pragma unroll
+          for (int g = 0; g < DOT_GROUP; ++g)
+            if (i0 + g < k) v[g] = *reinterpret_cast<const vec *>(V + (int64_t)(i0 + g) * ldv + qu * VW);
+#pragma unroll
+          for (int g = 0; g < DOT_GROUP; ++g)
+            if (i0 + g < k)
+#pragma unroll
+              for (int e = 0; e < VW; ++e) s[g] += (double)v[g][e] * (double)wv[e];
+        } else {
+          const double wr = (double)w[qu];
+          T v[DOT_GROUP];
+#pragma unroll
+          for (int g = 0; g < DOT_GROUP; ++g) v[g] = i0 + g < k ? V[(int64_t)(i0 + g) * ldv + qu] : T(0);
+#pragma unroll
+          for (int g = 0; g < DOT_GROUP; ++g) s[g] += (double)v[g] * wr;
+        }
+      }
+    }
+    if (VEC && blockIdx.x == gridDim.x - 1) {   // trailing entries
+      const int64_t r = nv * VW + threadIdx.x;
+      if (r < n)
+#pragma unroll
+        for (int g = 0; g < DOT_GROUP; ++g)
+          if (i0 + g < k) s[g] += (double)V[(int64_t)(i0 + g) * ldv + r] * (double)w[r];
+    }
+#pragma unroll
+    for (int g = 0; g < DOT_GROUP; ++g) red[g][threadIdx.x] = s[g];
     __syncthreads();
     for (int h = BLAS_NT / 2; h > 0; h >>= 1) {
-      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      if ((int)threadIdx.x < h)
+#pragma unroll
+        for (int g = 0; g < DOT_GROUP; ++g) red[g][threadIdx.x] += red[g][threadIdx.x + h];
       __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAX_DOTS + i] = red[0];
+    if ((int)threadIdx.x < DOT_GROUP && i0 + (int)threadIdx.x < k)
+      partial[(size_t)blockIdx.x * MAX_DOTS + i0 + threadIdx.x] = red[threadIdx.x][0];
     __syncthreads();
   }
 }
 
-__global__ void k_dots_final(int nb, int k, const double *__restrict__ partial, double *__restrict__ h) {
-  const int i = threadIdx.x;
-  if (i >= k) return;
+// h[i] = sum over the nb blocks of partial[b][i]: one block per dot, a fixed-order strided sum per
+// thread and a fixed tree across the block
+__global__ void __launch_bounds__(BLAS_NT) k_dots_final(int nb, const double *__restrict__ partial,
+                                                        double *__restrict__ h) {
+  __shared__ double red[BLAS_NT];
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * MAX_DOTS + i];
-  h[i] = s;
+  for (int b = threadIdx.x; b < nb; b += BLAS_NT) s += partial[(size_t)b * MAX_DOTS + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int hh = BLAS_NT / 2; hh > 0; hh >>= 1) {
+    if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[i] = red[0];
 }
 
-// w[r] += alpha * sum_i V[i][r] h[i]
-template <typename T>
+// w[r] += alpha * sum_i V[i][r] h[i]; the basis entries are loaded GEMV_GROUP at a time ahead of the
+// (fixed-order) accumulation, so that a thread has that many independent loads in flight.  VEC: each
+// thread takes Vec16<T>::W consecutive entries with 16-byte loads (V, its row stride and w aligned);
+// the threads past the whole vectors take the trailing entries one each.
+constexpr int GEMV_GROUP = 8;
+template <typename T, bool VEC>
 __global__ void k_gemv(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const double *__restrict__ h,
                        double alpha, T *__restrict__ w) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int VW = VEC ? Vec16<T>::W : 1;
+  typedef typename Vec16<T>::type vec;
+  const int64_t nv = n / VW;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (VEC && q < nv) {
+    double s[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) s[e] = 0.0;
+    for (int i0 = 0; i0 < k; i0 += GEMV_GROUP) {
+      vec v[GEMV_GROUP];
+#pragma unroll
+      for (int g = 0; g < GEMV_GROUP; ++g)
+        if (i0 + g < k) v[g] = *reinterpret_cast<const vec *>(V + (int64_t)(i0 + g) * ldv + q * VW);
+#pragma unroll
+      for (int g = 0; g < GEMV_GROUP; ++g)
+        if (i0 + g < k)
+#pragma unroll
+          for (int e = 0; e < VW; ++e) s[e] += (double)v[g][e] * h[i0 + g];
+    }
+    vec wv = *reinterpret_cast<const vec *>(w + q * VW);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) wv[e] = (T)((double)wv[e] + alpha * s[e]);
+    *reinterpret_cast<vec *>(w + q * VW) = wv;
+    return;
+  }
+  const int64_t r = VEC ? nv * VW + (q - nv) : q;
   if (r >= n) return;
   double s = 0.0;
-  for (int i = 0; i < k; ++i) s += (double)V[i * ldv + r] * h[i];
+  for (int i0 = 0; i0 < k; i0 += GEMV_GROUP) {
+    T v[GEMV_GROUP];
+#pragma unroll
+    for (int g = 0; g < GEMV_GROUP; ++g) v[g] = i0 + g < k ? V[(int64_t)(i0 + g) * ldv + r] : T(0);
+#pragma unroll
+    for (int g = 0; g < GEMV_GROUP; ++g)
+      if (i0 + g < k) s += (double)v[g] * h[i0 + g];
+  }
   w[r] = (T)((double)w[r] + alpha * s);
 }
 
@@ -87,27 +184,44 @@ __global__ void k_f2d(const float *in, double *out, int64_t n) {
 
 static inline int nblk(int64_t n) { return (int)((n + BLAS_NT - 1) / BLAS_NT); }
 
+// the 16-byte paths need V, w and (for more than one row) the row stride 16-byte aligned
+template <typename T>
+static bool vec_ok(const T *V, int64_t ldv, int k, const T *w) {
+  return aligned16(V) && aligned16(w) && (k == 1 || (ldv * (int64_t)sizeof(T)) % 16 == 0);
+}
+
+template <typename T>
+static void dots_t(hipStream_t s, int64_t n, int k, const T *V, int64_t ldv, const T *w, double *partial, int nb) {
+  if (vec_ok(V, ldv, k, w))
+    hipLaunchKernelGGL((k_dots_partial<T, true>), dim3(nb), dim3(BLAS_NT), 0, s, n, k, V, ldv, w, partial);
+  else
+    hipLaunchKernelGGL((k_dots_partial<T, false>), dim3(nb), dim3(BLAS_NT), 0, s, n, k, V, ldv, w, partial);
+}
+
 hipError_t launch_dots(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w,
                        double *partial, double *h) {
   const int nb = n < (int64_t)DOT_BLOCKS * BLAS_NT ? nblk(n) : DOT_BLOCKS;
-  if (prec == 0)
-    hipLaunchKernelGGL(k_dots_partial<double>, dim3(nb), dim3(BLAS_NT), 0, s, n, k, (const double *)V, ldv,
-                       (const double *)w, partial);
-  else
-    hipLaunchKernelGGL(k_dots_partial<float>, dim3(nb), dim3(BLAS_NT), 0, s, n, k, (const float *)V, ldv,
-                       (const float *)w, partial);
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(MAX_DOTS), 0, s, nb, k, partial, h);
+  if (prec == 0) dots_t<double>(s, n, k, (const double *)V, ldv, (const double *)w, partial, nb);
+  else dots_t<float>(s, n, k, (const float *)V, ldv, (const float *)w, partial, nb);
+  hipLaunchKernelGGL(k_dots_final, dim3(k), dim3(BLAS_NT), 0, s, nb, partial, h);
   return hipGetLastError();
+}
+
+template <typename T>
+static void gemv_t(hipStream_t s, int64_t n, int k, const T *V, int64_t ldv, const double *h, double alpha, T *w) {
+  if (vec_ok(V, ldv, k, (const T *)w)) {
+    constexpr int VW = Vec16<T>::W;
+    const int64_t items = n / VW + n % VW;
+    hipLaunchKernelGGL((k_gemv<T, true>), dim3(nblk(items)), dim3(BLAS_NT), 0, s, n, k, V, ldv, h, alpha, w);
+  } else {
+    hipLaunchKernelGGL((k_gemv<T, false>), dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, k, V, ldv, h, alpha, w);
+  }
 }
 
 hipError_t launch_gemv(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
                        double alpha, void *w) {
-  if (prec == 0)
-    hipLaunchKernelGGL(k_gemv<double>, dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, k, (const double *)V, ldv, h, alpha,
-                       (double *)w);
-  else
-    hipLaunchKernelGGL(k_gemv<float>, dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, k, (const float *)V, ldv, h, alpha,
-                       (float *)w);
+  if (prec == 0) gemv_t<double>(s, n, k, (const double *)V, ldv, h, alpha, (double *)w);
+  else gemv_t<float>(s, n, k, (const float *)V, ldv, h, alpha, (float *)w);
   return hipGetLastError();
 }
 

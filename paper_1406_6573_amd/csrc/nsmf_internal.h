@@ -19,6 +19,7 @@ constexpr uint32_t ROT_BIT = 1u << 31;   // the slot's node has its unknowns in 
 
 // Largest number of simultaneous dot products of nsmf_vec_dots (Krylov basis size + 1).
 constexpr int MAX_DOTS = 64;
+constexpr int DOT_BLOCKS = 2048;   // blocks of the multi-dot's first stage (partial sums per block)
 
 // Threads per block and elements per block for P = k+1 nodes per direction.  One
 // thread owns one line of P values of an element, so an element occupies P*P threads.
@@ -139,10 +140,22 @@ hipError_t launch_lowo(int P, hipStream_t s, const MeshView &m, const GeoView<do
 // vertical-line block preconditioner: element line blocks, node assembly, banded Cholesky
 hipError_t launch_lines(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                         const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
-                        const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
-                        double *buf, double *fac64, float *fac32);
+                        const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node,
+                        const int32_t *prow, const int32_t *lrow, int64_t NR, int64_t n_lines, double *buf,
+                        double *fac64, float *fac32);
+// Line-block rows are interleaved by groups of LINE_GROUP consecutive lines: node i of line l sits at
+// row lrow[l] + LINE_GROUP i, lrow[l] = (row offset of l's group) + l mod LINE_GROUP; prow[n] is node
+// n's row, NR the rows per component (the groups padded to their longest line).  line_first[l]: id
+// of the first node of line l if the line's node ids are consecutive, else -1.  The factorisation
+// and the solves run one thread per (line, component), the lines of a component padded to a
+// multiple of LINE_GROUP so that a group is one wavefront.
+constexpr int LINE_GROUP = 64;
+__host__ __device__ inline int64_t line_threads(int64_t n_lines) {
+  return (n_lines + LINE_GROUP - 1) / LINE_GROUP * LINE_GROUP;
+}
 hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const int32_t *line_ptr, const int32_t *line_node,
-                             int64_t n_lines, const void *fac, const void *x, void *y);
+                             const int32_t *lrow, int64_t NR, const int32_t *line_first, int64_t n_lines,
+                             const void *fac, const void *x, void *y);
 
 // The run of independent slots z = lo..hi on the z-line (x = i, y = j) of an element, false when
 // every slot of the line is dependent.  A hanging face or edge that contains the line makes all of

@@ -1567,36 +1567,45 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
           buf[((size_t)c * m.n_inc + e * P3 + t + P2 * zb) * P + d] = zb - d >= lo ? rows[c][zb - d][d] : 0.0;
 }
 
-// Node rows of the line blocks: A[(c N + n) W + d] = sum of the rows of the node's conforming slots
-// (fixed order, deterministic); entry d couples n with the node d places below it on its line.
-__global__ void k_line_band(int64_t N, int64_t n_inc, int W, const int32_t *__restrict__ lptr,
-                            const int32_t *__restrict__ lslot, const double *__restrict__ buf, double *__restrict__ A) {
+// Node rows of the line blocks: A[(c NR + prow[n]) W + d] = sum of the rows of the node's conforming
+// slots (fixed order, deterministic); entry d couples n with the node d places below it on its line.
+// Rows are interleaved by groups of LINE_GROUP lines: node i of line l of group g sits at row
+// base[g] + LINE_GROUP i + (l mod LINE_GROUP), so that the threads of one wavefront, which handle
+// consecutive lines, read consecutive rows at each step of the factorisation and the solves.
+__global__ void k_line_band(int64_t N, int64_t n_inc, int64_t NR, int W, const int32_t *__restrict__ lptr,
+                            const int32_t *__restrict__ lslot, const int32_t *__restrict__ prow,
+                            const double *__restrict__ buf, double *__restrict__ A) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const int32_t k0 = lptr[n], k1 = lptr[n + 1];
+  const int64_t q = prow[n];
   for (int c = 0; c < 3; ++c)
     for (int d = 0; d < W; ++d) {
       double s = 0.0;
       for (int32_t k = k0; k < k1; ++k) s += buf[((size_t)c * n_inc + lslot[k]) * W + d];
-      A[((size_t)c * N + n) * W + d] = s;
+      A[((size_t)c * NR + q) * W + d] = s;
     }
 }
 
-// Banded Cholesky of each line block, one thread per (line, component), in place: row i of the
-// line holds A[i][i - d] on entry and the factor entry G[i][i - d] on exit (A = G G^T).  Rows of
+// Banded Cholesky of each line block, one thread per (line, component), in place (interleaved rows,
+// see k_line_band): row i of the line holds A[i][i - d] on entry and the factor entry G[i][i - d] on
+// exit (A = G G^T), except entry 0, which holds 1 / G[i][i] so that the solves multiply.  Rows of
 // Dirichlet-flagged components are unit rows, and couplings with them are dropped (the blocks of
 // J_c = P K P + (I - P)).  A non-positive pivot (not expected: the blocks are principal
 // submatrices of an SPD matrix) falls back to a diagonal row.
 template <int W>
-__global__ void k_line_factor(int64_t N, int64_t n_lines, const int32_t *__restrict__ line_ptr,
-                              const int32_t *__restrict__ line_node, const uint8_t *__restrict__ dm,
-                              double *__restrict__ F, float *__restrict__ F32) {
+__global__ void k_line_factor(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__ line_ptr,
+                              const int32_t *__restrict__ line_node, const int32_t *__restrict__ lrow,
+                              const uint8_t *__restrict__ dm, double *__restrict__ F, float *__restrict__ F32) {
   constexpr int K = W - 1;
+  const int64_t L = line_threads(n_lines);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= 3 * n_lines) return;
-  const int c = (int)(g / n_lines);
-  const int64_t l = g % n_lines;
+  if (g >= 3 * L) return;
+  const int c = (int)(g / L);
+  const int64_t l = g % L;
+  if (l >= n_lines) return;
   const int32_t b0 = line_ptr[l], len = line_ptr[l + 1] - b0;
+  const size_t r0 = (size_t)c * NR + lrow[l];
   double prev[K + 1][W];   // prev[r] = factor row of line row i - r (r = 1..K)
   bool pmask[K + 1];
 #pragma unroll
@@ -1608,7 +1617,7 @@ __global__ void k_line_factor(int64_t N, int64_t n_lines, const int32_t *__restr
   for (int32_t i = 0; i < len; ++i) {
     const int32_t n = line_node[b0 + i];
     const bool mi = dm[(size_t)c * N + n] != 0;
-    double *row = F + ((size_t)c * N + n) * W;
+    double *row = F + (r0 + (size_t)LINE_GROUP * i) * W;
     double a[W], gi[W];
 #pragma unroll
     for (int d = 0; d < W; ++d) {
@@ -1636,8 +1645,9 @@ __global__ void k_line_factor(int64_t N, int64_t n_lines, const int32_t *__restr
     gi[0] = sqrt(s);
 #pragma unroll
     for (int d = 0; d < W; ++d) {
-      row[d] = gi[d];
-      F32[((size_t)c * N + n) * W + d] = (float)gi[d];
+      const double gv = d == 0 ? 1.0 / gi[0] : gi[d];
+      row[d] = gv;
+      F32[(r0 + (size_t)LINE_GROUP * i) * W + d] = (float)gv;
     }
 #pragma unroll
     for (int r = K; r >= 2; --r) {
@@ -1651,34 +1661,63 @@ __global__ void k_line_factor(int64_t N, int64_t n_lines, const int32_t *__restr
   }
 }
 
-// y = (line blocks)^{-1} x per component: forward G v = x, backward G^T y = v along each line.
+// y = (line blocks)^{-1} x per component: forward G v = x, backward G^T y = v along each line, one
+// thread per (line, component).  The factor rows are interleaved by groups of lines (k_line_band),
+// so a wavefront reads consecutive rows at each step; the nodes of a line whose ids are consecutive
+// (first[l] >= 0, the usual case on column meshes) are addressed without reading line_node.  Rows and
+// values are loaded in batches of LB nodes ahead of the recurrence, so that a thread has LB
+// independent loads in flight instead of one dependent chain per node.
 template <typename T, int W>
-__global__ void k_line_apply(int64_t N, int64_t n_lines, const int32_t *__restrict__ line_ptr,
-                             const int32_t *__restrict__ line_node, const T *__restrict__ F, const T *__restrict__ x,
+__global__ void k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__ line_ptr,
+                             const int32_t *__restrict__ line_node, const int32_t *__restrict__ lrow,
+                             const int32_t *__restrict__ first, const T *__restrict__ F, const T *__restrict__ x,
                              T *__restrict__ y) {
-  constexpr int K = W - 1;
+  constexpr int K = W - 1, LB = 4;
+  const int64_t L = line_threads(n_lines);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= 3 * n_lines) return;
-  const int c = (int)(g / n_lines);
-  const int64_t l = g % n_lines;
-  const int32_t b0 = line_ptr[l], len = line_ptr[l + 1] - b0;
+  if (g >= 3 * L) return;
+  const int c = (int)(g / L);
+  const int64_t l = g % L;
+  if (l >= n_lines) return;
+  const int32_t b0 = line_ptr[l], len = line_ptr[l + 1] - b0, f0 = first[l];
+  const T *Fl = F + ((size_t)c * NR + lrow[l]) * W;
+  const size_t cN = (size_t)c * N;
+  // forward: v_i = (x_i - sum_d G[i][i-d] v_{i-d}) / G[i][i]
   T v[K + 1];
 #pragma unroll
   for (int r = 0; r <= K; ++r) v[r] = 0;
-  for (int32_t i = 0; i < len; ++i) {
-    const int32_t n = line_node[b0 + i];
-    const T *row = F + ((size_t)c * N + n) * W;
-    T s = x[(size_t)c * N + n];
+  for (int32_t i0 = 0; i0 < len; i0 += LB) {
+    T rw[LB][W], xv[LB];
+    int32_t nd[LB];
 #pragma unroll
-    for (int d = 1; d < W; ++d)
-      if (i - d >= 0) s -= row[d] * v[d];
-    s /= row[0];
-    y[(size_t)c * N + n] = s;
+    for (int u = 0; u < LB; ++u) {
+      const int32_t i = i0 + u;
+      nd[u] = i < len ? (f0 >= 0 ? f0 + i : line_node[b0 + i]) : 0;
+    }
 #pragma unroll
-    for (int r = K; r >= 2; --r) v[r] = v[r - 1];
-    v[1] = s;
+    for (int u = 0; u < LB; ++u) {
+      const int32_t i = i0 + u;
+      const bool in = i < len;
+#pragma unroll
+      for (int d = 0; d < W; ++d) rw[u][d] = in ? Fl[(size_t)LINE_GROUP * i * W + d] : T(0);
+      xv[u] = in ? x[cN + nd[u]] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int32_t i = i0 + u;
+      if (i >= len) break;
+      T s = xv[u];
+#pragma unroll
+      for (int d = 1; d < W; ++d)
+        if (i - d >= 0) s -= rw[u][d] * v[d];
+      s *= rw[u][0];
+      y[cN + nd[u]] = s;
+#pragma unroll
+      for (int r = K; r >= 2; --r) v[r] = v[r - 1];
+      v[1] = s;
+    }
   }
-  // backward: z_i = (v_i - sum_d G[i+d][i] z_{i+d}) / G[i][i]
+  // backward: z_i = (v_i - sum_d G[i+d][i] z_{i+d}) / G[i][i]; gr[r] holds the row of node i + r
   T zr[K + 1], gr[K + 1][W];
 #pragma unroll
   for (int r = 0; r <= K; ++r) {
@@ -1686,24 +1725,42 @@ __global__ void k_line_apply(int64_t N, int64_t n_lines, const int32_t *__restri
 #pragma unroll
     for (int d = 0; d < W; ++d) gr[r][d] = 0;
   }
-  for (int32_t i = len - 1; i >= 0; --i) {
-    const int32_t n = line_node[b0 + i];
-    const T *row = F + ((size_t)c * N + n) * W;
-    T s = y[(size_t)c * N + n];
+  for (int32_t i0 = len - 1; i0 >= 0; i0 -= LB) {
+    T rw[LB][W], yv[LB];
+    int32_t nd[LB];
 #pragma unroll
-    for (int d = 1; d < W; ++d)
-      if (i + d < len) s -= gr[d][d] * zr[d];
-    const T z = s / row[0];
-    y[(size_t)c * N + n] = z;
-#pragma unroll
-    for (int r = K; r >= 2; --r) {
-      zr[r] = zr[r - 1];
-#pragma unroll
-      for (int d = 0; d < W; ++d) gr[r][d] = gr[r - 1][d];
+    for (int u = 0; u < LB; ++u) {
+      const int32_t i = i0 - u;
+      nd[u] = i >= 0 ? (f0 >= 0 ? f0 + i : line_node[b0 + i]) : 0;
     }
-    zr[1] = z;
 #pragma unroll
-    for (int d = 0; d < W; ++d) gr[1][d] = row[d];
+    for (int u = 0; u < LB; ++u) {
+      const int32_t i = i0 - u;
+      const bool in = i >= 0;
+#pragma unroll
+      for (int d = 0; d < W; ++d) rw[u][d] = in ? Fl[(size_t)LINE_GROUP * i * W + d] : T(0);
+      yv[u] = in ? y[cN + nd[u]] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int32_t i = i0 - u;
+      if (i < 0) break;
+      T s = yv[u];
+#pragma unroll
+      for (int d = 1; d < W; ++d)
+        if (i + d < len) s -= gr[d][d] * zr[d];
+      const T z = s * rw[u][0];
+      y[cN + nd[u]] = z;
+#pragma unroll
+      for (int r = K; r >= 2; --r) {
+        zr[r] = zr[r - 1];
+#pragma unroll
+        for (int d = 0; d < W; ++d) gr[r][d] = gr[r - 1][d];
+      }
+      zr[1] = z;
+#pragma unroll
+      for (int d = 0; d < W; ++d) gr[1][d] = rw[u][d];
+    }
   }
 }
 
@@ -2424,46 +2481,49 @@ hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t 
 template <int P, int GEO>
 static hipError_t lines_pg(hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                            const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
-                           const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
-                           double *buf, double *fac64, float *fac32) {
+                           const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node,
+                           const int32_t *prow, const int32_t *lrow, int64_t NR, int64_t n_lines, double *buf,
+                           double *fac64, float *fac32) {
   if (g.rot != nullptr)   // nodal frames: rotated bottom rows
     hipLaunchKernelGGL((k_lines<P, GEO, true>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
                        &((const TabSet<P> *)tabs)->d, st, beta, buf);
   else
     hipLaunchKernelGGL((k_lines<P, GEO, false>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
                        &((const TabSet<P> *)tabs)->d, st, beta, buf);
-  hipLaunchKernelGGL(k_line_band, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, P, lptr, lslot,
-                     (const double *)buf, fac64);
+  hipLaunchKernelGGL(k_line_band, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, NR, P, lptr,
+                     lslot, prow, (const double *)buf, fac64);
   if (n_lines > 0)
-    hipLaunchKernelGGL(k_line_factor<P>, dim3(grid1(3 * n_lines, 256)), dim3(256), 0, s, m.n_nodes, n_lines, line_ptr,
-                       line_node, dm, fac64, fac32);
+    hipLaunchKernelGGL(k_line_factor<P>, dim3(grid1(3 * line_threads(n_lines), 256)), dim3(256), 0, s, m.n_nodes,
+                       n_lines, NR, line_ptr, line_node, lrow, dm, fac64, fac32);
   return hipGetLastError();
 }
 hipError_t launch_lines(int P, int geo, hipStream_t s, const MeshView &m, const GeoView<double> &g, const void *tabs,
                         const double *st, const double *beta, const int32_t *lptr, const int32_t *lslot,
-                        const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node, int64_t n_lines,
-                        double *buf, double *fac64, float *fac32) {
-#define NSMF_LN(PP, GG)                                                                                        \
-  if (P == PP && geo == GG)                                                                                    \
-    return lines_pg<PP, GG>(s, m, g, tabs, st, beta, lptr, lslot, dm, line_ptr, line_node, n_lines, buf, fac64, \
-                            fac32);
+                        const uint8_t *dm, const int32_t *line_ptr, const int32_t *line_node,
+                        const int32_t *prow, const int32_t *lrow, int64_t NR, int64_t n_lines, double *buf,
+                        double *fac64, float *fac32) {
+#define NSMF_LN(PP, GG)                                                                                          \
+  if (P == PP && geo == GG)                                                                                      \
+    return lines_pg<PP, GG>(s, m, g, tabs, st, beta, lptr, lslot, dm, line_ptr, line_node, prow, lrow, NR, n_lines, \
+                            buf, fac64, fac32);
   NSMF_LN(3, GEO_AFFINE) NSMF_LN(3, GEO_COLUMN) NSMF_LN(4, GEO_AFFINE) NSMF_LN(4, GEO_COLUMN)
   NSMF_LN(5, GEO_AFFINE) NSMF_LN(5, GEO_COLUMN)
 #undef NSMF_LN
   return hipErrorInvalidValue;
 }
 hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const int32_t *line_ptr, const int32_t *line_node,
-                             int64_t n_lines, const void *fac, const void *x, void *y) {
+                             const int32_t *lrow, int64_t NR, const int32_t *line_first, int64_t n_lines,
+                             const void *fac, const void *x, void *y) {
   if (n_lines <= 0) return hipSuccess;
-  const dim3 grid(grid1(3 * n_lines, 256)), blk(256);
+  const dim3 grid(grid1(3 * line_threads(n_lines), 256)), blk(256);
 #define NSMF_LA(WW)                                                                                             \
   if (P == WW) {                                                                                                \
     if (prec == 0)                                                                                              \
-      hipLaunchKernelGGL((k_line_apply<double, WW>), grid, blk, 0, s, N, n_lines, line_ptr, line_node,          \
-                         (const double *)fac, (const double *)x, (double *)y);                                  \
+      hipLaunchKernelGGL((k_line_apply<double, WW>), grid, blk, 0, s, N, n_lines, NR, line_ptr, line_node,      \
+                         lrow, line_first, (const double *)fac, (const double *)x, (double *)y);                \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_line_apply<float, WW>), grid, blk, 0, s, N, n_lines, line_ptr, line_node,           \
-                         (const float *)fac, (const float *)x, (float *)y);                                     \
+      hipLaunchKernelGGL((k_line_apply<float, WW>), grid, blk, 0, s, N, n_lines, NR, line_ptr, line_node,       \
+                         lrow, line_first, (const float *)fac, (const float *)x, (float *)y);                   \
     return hipGetLastError();                                                                                   \
   }
   NSMF_LA(3) NSMF_LA(4) NSMF_LA(5)

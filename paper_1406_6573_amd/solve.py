@@ -183,8 +183,11 @@ class NewtonKrylov:
         dev = engine.dev
         kt = torch.float64 if precision == "fp64" else torch.float32
         self.kt = kt
-        self.V = torch.empty((restart + 1, self.n), dtype=kt, device=dev)
-        self.Z = torch.empty((restart, self.n), dtype=kt, device=dev)
+        # basis rows padded to a multiple of 64 entries: every row starts 256-byte aligned, which lets the
+        # multi-dot and basis-combination kernels use 16-byte loads
+        ld = (self.n + 63) // 64 * 64
+        self.V = torch.empty((restart + 1, ld), dtype=kt, device=dev)[:, :self.n]
+        self.Z = torch.empty((restart, ld), dtype=kt, device=dev)[:, :self.n]
         self.h = torch.empty(64, dtype=torch.float64, device=dev)
         # Hessenberg columns of one cycle: two Gram-Schmidt passes and the squared norm per step, on the
         # device and their pinned host copies

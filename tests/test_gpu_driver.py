@@ -121,6 +121,24 @@ def test_vector_kernels(torch_cuda):
         y[::2] = float("inf")
         eng.vec_axpby(-3.0, w, 0.0, y)
         assert torch.equal(y, (-3.0 * w.double()).to(dt))
+    # basis rows padded to a 16-byte multiple (the driver's layout): the 16-byte load paths, with the
+    # trailing entries of an odd length, more vectors than one group, and an unaligned w (scalar path)
+    for dt in (torch.float64, torch.float32):
+        k2 = 11
+        ld = (n + 63) // 64 * 64
+        Vp = torch.empty((k2, ld), dtype=dt, device="cuda")[:, :n]
+        Vp.copy_(torch.rand((k2, n), dtype=dt, device="cuda", generator=g) - 0.5)
+        buf = torch.rand(n + 1, dtype=dt, device="cuda", generator=g) - 0.5
+        for wv in (buf[:n].clone(), buf[1:]):
+            h = torch.empty(64, dtype=torch.float64, device="cuda")
+            eng.vec_dots(Vp, k2, wv, h)
+            ref = Vp.double() @ wv.double()
+            assert torch.allclose(h[:k2], ref, rtol=1e-12, atol=1e-12)
+            w2 = wv.clone() if wv.data_ptr() % 16 == 0 else wv
+            before = w2.double().clone()
+            eng.vec_gemv(Vp, k2, h, -0.5, w2)
+            ref2 = before - 0.5 * (Vp.double().T @ h[:k2])
+            assert torch.allclose(w2.double(), ref2, rtol=1e-6 if dt == torch.float32 else 1e-13, atol=1e-6)
     x = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
     x32 = torch.empty(n, dtype=torch.float32, device="cuda")
     eng.vec_convert(x, x32)
