@@ -1661,63 +1661,100 @@ __global__ void k_line_factor(int64_t N, int64_t n_lines, int64_t NR, const int3
   }
 }
 
-// y = (line blocks)^{-1} x per component: forward G v = x, backward G^T y = v along each line, one
-// thread per (line, component).  The factor rows are interleaved by groups of lines (k_line_band),
-// so a wavefront reads consecutive rows at each step; the nodes of a line whose ids are consecutive
-// (first[l] >= 0, the usual case on column meshes) are addressed without reading line_node.  Rows and
-// values are loaded in batches of LB nodes ahead of the recurrence, so that a thread has LB
-// independent loads in flight instead of one dependent chain per node.
+// y = (line blocks)^{-1} x per component: forward G v = x, backward G^T y = v along each line.  One
+// block (one wavefront) per group of LINE_GROUP lines and component, one thread per line.  The factor
+// rows are interleaved by group (k_line_band), so the wavefront reads consecutive rows at each step.
+// x and y are in node order, where the nodes of one line are far apart across the lanes; they pass
+// through LDS in chunks of LINE_CH nodes of every line of the group: lane q moves element q mod LINE_CH
+// of line q / LINE_CH (+ 4 r lines in round r), so each access is a run of LINE_CH consecutive
+// entries of one line (lines with consecutive node ids, first[l] >= 0; others gather through
+// line_node).  The backward sweep takes its chunks from each line's end.  Factor rows are loaded LB
+// nodes ahead of the recurrence.
+constexpr int LINE_CH = 16;
 template <typename T, int W>
-__global__ void k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__ line_ptr,
-                             const int32_t *__restrict__ line_node, const int32_t *__restrict__ lrow,
-                             const int32_t *__restrict__ first, const T *__restrict__ F, const T *__restrict__ x,
-                             T *__restrict__ y) {
-  constexpr int K = W - 1, LB = 4;
-  const int64_t L = line_threads(n_lines);
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= 3 * L) return;
-  const int c = (int)(g / L);
-  const int64_t l = g % L;
-  if (l >= n_lines) return;
-  const int32_t b0 = line_ptr[l], len = line_ptr[l + 1] - b0, f0 = first[l];
-  const T *Fl = F + ((size_t)c * NR + lrow[l]) * W;
+__global__ void __launch_bounds__(LINE_GROUP)
+k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__ line_ptr,
+             const int32_t *__restrict__ line_node, const int32_t *__restrict__ lrow,
+             const int32_t *__restrict__ first, const T *__restrict__ F, const T *__restrict__ x,
+             T *__restrict__ y) {
+  constexpr int K = W - 1, LB = 4, CH = LINE_CH, LPR = LINE_GROUP / CH;   // lines per round
+  static_assert(LINE_GROUP % CH == 0 && CH % LB == 0, "chunk shape");
+  __shared__ T buf[LINE_GROUP][CH + 1];
+  __shared__ int32_t mlen[LINE_GROUP], mfirst[LINE_GROUP], mb0[LINE_GROUP];
+  const int64_t G = line_threads(n_lines) / LINE_GROUP;
+  const int c = (int)(blockIdx.x / G);
+  const int lane = (int)threadIdx.x;
+  const int64_t l = (blockIdx.x % G) * LINE_GROUP + lane;
+  int32_t b0 = 0, len = 0, f0 = -1;
+  int64_t r0 = 0;
+  if (l < n_lines) {
+    b0 = line_ptr[l];
+    len = line_ptr[l + 1] - b0;
+    f0 = first[l];
+    r0 = lrow[l];
+  }
+  mlen[lane] = len;
+  mfirst[lane] = f0;
+  mb0[lane] = b0;
+  int32_t lmax = len;   // longest line of the group: the chunk loops are uniform over the wavefront
+#pragma unroll
+  for (int off = LINE_GROUP / 2; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off));
+  __syncthreads();
+  const T *Fl = F + ((size_t)c * NR + r0) * W;
   const size_t cN = (size_t)c * N;
+  // node of entry i of group line j
+  auto node_of = [&](int j, int32_t i) -> int64_t {
+    const int32_t fj = mfirst[j];
+    return fj >= 0 ? (int64_t)fj + i : (int64_t)line_node[mb0[j] + i];
+  };
+  const int je = lane / CH, ee = lane % CH;   // this lane's (line, element) in round 0
   // forward: v_i = (x_i - sum_d G[i][i-d] v_{i-d}) / G[i][i]
   T v[K + 1];
 #pragma unroll
   for (int r = 0; r <= K; ++r) v[r] = 0;
-  for (int32_t i0 = 0; i0 < len; i0 += LB) {
-    T rw[LB][W], xv[LB];
-    int32_t nd[LB];
+  for (int32_t i0 = 0; i0 < lmax; i0 += CH) {
 #pragma unroll
-    for (int u = 0; u < LB; ++u) {
-      const int32_t i = i0 + u;
-      nd[u] = i < len ? (f0 >= 0 ? f0 + i : line_node[b0 + i]) : 0;
+    for (int r = 0; r < CH; ++r) {
+      const int j = r * LPR + je;
+      const int32_t i = i0 + ee;
+      if (i < mlen[j]) buf[j][ee] = x[cN + node_of(j, i)];
     }
+    __syncthreads();
+    for (int e0 = 0; e0 < CH; e0 += LB) {
+      T rw[LB][W];
 #pragma unroll
-    for (int u = 0; u < LB; ++u) {
-      const int32_t i = i0 + u;
-      const bool in = i < len;
+      for (int u = 0; u < LB; ++u) {
+        const int32_t i = i0 + e0 + u;
+        const bool in = i < len;
 #pragma unroll
-      for (int d = 0; d < W; ++d) rw[u][d] = in ? Fl[(size_t)LINE_GROUP * i * W + d] : T(0);
-      xv[u] = in ? x[cN + nd[u]] : T(0);
+        for (int d = 0; d < W; ++d) rw[u][d] = in ? Fl[(size_t)LINE_GROUP * i * W + d] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int32_t i = i0 + e0 + u;
+        if (i >= len) break;
+        T s = buf[lane][e0 + u];
+#pragma unroll
+        for (int d = 1; d < W; ++d)
+          if (i - d >= 0) s -= rw[u][d] * v[d];
+        s *= rw[u][0];
+        buf[lane][e0 + u] = s;
+#pragma unroll
+        for (int r = K; r >= 2; --r) v[r] = v[r - 1];
+        v[1] = s;
+      }
     }
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < LB; ++u) {
-      const int32_t i = i0 + u;
-      if (i >= len) break;
-      T s = xv[u];
-#pragma unroll
-      for (int d = 1; d < W; ++d)
-        if (i - d >= 0) s -= rw[u][d] * v[d];
-      s *= rw[u][0];
-      y[cN + nd[u]] = s;
-#pragma unroll
-      for (int r = K; r >= 2; --r) v[r] = v[r - 1];
-      v[1] = s;
+    for (int r = 0; r < CH; ++r) {
+      const int j = r * LPR + je;
+      const int32_t i = i0 + ee;
+      if (i < mlen[j]) y[cN + node_of(j, i)] = buf[j][ee];
     }
+    __syncthreads();
   }
-  // backward: z_i = (v_i - sum_d G[i+d][i] z_{i+d}) / G[i][i]; gr[r] holds the row of node i + r
+  // backward: z_i = (v_i - sum_d G[i+d][i] z_{i+d}) / G[i][i]; gr[r] holds the row of node i + r.
+  // Chunk k holds entries i = len - 1 - (k0 + e) of each line.
   T zr[K + 1], gr[K + 1][W];
 #pragma unroll
   for (int r = 0; r <= K; ++r) {
@@ -1725,42 +1762,52 @@ __global__ void k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32
 #pragma unroll
     for (int d = 0; d < W; ++d) gr[r][d] = 0;
   }
-  for (int32_t i0 = len - 1; i0 >= 0; i0 -= LB) {
-    T rw[LB][W], yv[LB];
-    int32_t nd[LB];
+  for (int32_t k0 = 0; k0 < lmax; k0 += CH) {
 #pragma unroll
-    for (int u = 0; u < LB; ++u) {
-      const int32_t i = i0 - u;
-      nd[u] = i >= 0 ? (f0 >= 0 ? f0 + i : line_node[b0 + i]) : 0;
+    for (int r = 0; r < CH; ++r) {
+      const int j = r * LPR + je;
+      const int32_t lj = mlen[j], ri = k0 + ee;
+      if (ri < lj) buf[j][ee] = y[cN + node_of(j, lj - 1 - ri)];
     }
+    __syncthreads();
+    for (int e0 = 0; e0 < CH; e0 += LB) {
+      T rw[LB][W];
 #pragma unroll
-    for (int u = 0; u < LB; ++u) {
-      const int32_t i = i0 - u;
-      const bool in = i >= 0;
+      for (int u = 0; u < LB; ++u) {
+        const int32_t i = len - 1 - (k0 + e0 + u);
+        const bool in = i >= 0;
 #pragma unroll
-      for (int d = 0; d < W; ++d) rw[u][d] = in ? Fl[(size_t)LINE_GROUP * i * W + d] : T(0);
-      yv[u] = in ? y[cN + nd[u]] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < LB; ++u) {
-      const int32_t i = i0 - u;
-      if (i < 0) break;
-      T s = yv[u];
-#pragma unroll
-      for (int d = 1; d < W; ++d)
-        if (i + d < len) s -= gr[d][d] * zr[d];
-      const T z = s * rw[u][0];
-      y[cN + nd[u]] = z;
-#pragma unroll
-      for (int r = K; r >= 2; --r) {
-        zr[r] = zr[r - 1];
-#pragma unroll
-        for (int d = 0; d < W; ++d) gr[r][d] = gr[r - 1][d];
+        for (int d = 0; d < W; ++d) rw[u][d] = in ? Fl[(size_t)LINE_GROUP * i * W + d] : T(0);
       }
-      zr[1] = z;
 #pragma unroll
-      for (int d = 0; d < W; ++d) gr[1][d] = rw[u][d];
+      for (int u = 0; u < LB; ++u) {
+        const int32_t i = len - 1 - (k0 + e0 + u);
+        if (i < 0) break;
+        T s = buf[lane][e0 + u];
+#pragma unroll
+        for (int d = 1; d < W; ++d)
+          if (i + d < len) s -= gr[d][d] * zr[d];
+        const T z = s * rw[u][0];
+        buf[lane][e0 + u] = z;
+#pragma unroll
+        for (int r = K; r >= 2; --r) {
+          zr[r] = zr[r - 1];
+#pragma unroll
+          for (int d = 0; d < W; ++d) gr[r][d] = gr[r - 1][d];
+        }
+        zr[1] = z;
+#pragma unroll
+        for (int d = 0; d < W; ++d) gr[1][d] = rw[u][d];
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const int j = r * LPR + je;
+      const int32_t lj = mlen[j], ri = k0 + ee;
+      if (ri < lj) y[cN + node_of(j, lj - 1 - ri)] = buf[j][ee];
+    }
+    __syncthreads();
   }
 }
 
@@ -2515,7 +2562,7 @@ hipError_t launch_line_apply(hipStream_t s, int prec, int P, int64_t N, const in
                              const int32_t *lrow, int64_t NR, const int32_t *line_first, int64_t n_lines,
                              const void *fac, const void *x, void *y) {
   if (n_lines <= 0) return hipSuccess;
-  const dim3 grid(grid1(3 * line_threads(n_lines), 256)), blk(256);
+  const dim3 grid((unsigned)(3 * (line_threads(n_lines) / LINE_GROUP))), blk(LINE_GROUP);
 #define NSMF_LA(WW)                                                                                             \
   if (P == WW) {                                                                                                \
     if (prec == 0)                                                                                              \
