@@ -278,6 +278,22 @@ int nsmf_vec_gemv(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int6
 int nsmf_vec_axpby(nsmf_ctx *ctx, int prec, int64_t n, double a, const void *x, double b, void *y);
 int nsmf_vec_mul(nsmf_ctx *ctx, int prec, int64_t n, const double *d, const void *x, void *z);
 int nsmf_vec_normalize(nsmf_ctx *ctx, int prec, int64_t n, const double *nrm2, void *x);
+
+/* Second Gram-Schmidt pass decided on the device (no host round trip in the Arnoldi step).
+ *   nsmf_vec_dots_if, nsmf_vec_gemv_if: nsmf_vec_dots / nsmf_vec_gemv when flag[0] != 0; when
+ *       flag[0] == 0, dots_if writes h[i] = 0 (i < k) and gemv_if leaves w unchanged.  flag: DEVICE int32.
+ *   nsmf_gs_norm: h: DEVICE doubles [k + 1], the dots of rows V_0..V_{k-1} and of w itself with w
+ *       (h[k] = |w|^2) taken before the projection w -= V h.  Writes nrm2[0] = h[k] - sum_{i<k} h[i]^2,
+ *       the squared norm of the projected w when the rows are orthonormal (DEVICE double), and, if
+ *       flag_out is not NULL, flag_out[0] = (nrm2[0] < eta2 h[k]): the criterion of Daniel, Gragg,
+ *       Kaufman and Stewart (1976) for a second pass, eta2 = 1/2 in the driver.  If flag_in is not
+ *       NULL and flag_in[0] == 0, nothing is written.  0 <= k < 64, 0 <= eta2 <= 1. */
+int nsmf_vec_dots_if(nsmf_ctx *ctx, const int32_t *flag, int prec, int64_t n, int k, const void *V, int64_t ldv,
+                     const void *w, double *h);
+int nsmf_vec_gemv_if(nsmf_ctx *ctx, const int32_t *flag, int prec, int64_t n, int k, const void *V, int64_t ldv,
+                     const double *h, double alpha, void *w);
+int nsmf_gs_norm(nsmf_ctx *ctx, int k, const double *h, double eta2, const int32_t *flag_in, int32_t *flag_out,
+                 double *nrm2);
 int nsmf_vec_convert(nsmf_ctx *ctx, int64_t n, int to_fp32, const void *in, void *out);
 
 /* Sizes of the uploaded mesh; any pointer may be NULL. */

@@ -872,6 +872,36 @@ int nsmf_vec_gemv(nsmf_ctx *ctx, int prec, int64_t n, int k, const void *V, int6
   return NSMF_OK;
 }
 
+int nsmf_vec_dots_if(nsmf_ctx *ctx, const int32_t *flag, int prec, int64_t n, int k, const void *V, int64_t ldv,
+                     const void *w, double *h) {
+  int rc = vec_check(ctx, prec, n);
+  if (rc) return rc;
+  if (!flag || !V || !w || !h || k < 1 || k > MAX_DOTS || ldv < n)
+    return ctx->fail(NSMF_EINVAL, "bad nsmf_vec_dots_if arguments");
+  if (!ctx->dot_partial.p) NSMF_TRY(ctx, ctx->dot_partial.alloc((size_t)DOT_BLOCKS * MAX_DOTS), "hipMalloc");
+  NSMF_TRY(ctx, launch_dots(ctx->stream, prec, n, k, V, ldv, w, ctx->dot_partial.p, h, flag), "dots");
+  return NSMF_OK;
+}
+
+int nsmf_vec_gemv_if(nsmf_ctx *ctx, const int32_t *flag, int prec, int64_t n, int k, const void *V, int64_t ldv,
+                     const double *h, double alpha, void *w) {
+  int rc = vec_check(ctx, prec, n);
+  if (rc) return rc;
+  if (!flag || !V || !w || !h || k < 1 || k > MAX_DOTS || ldv < n)
+    return ctx->fail(NSMF_EINVAL, "bad nsmf_vec_gemv_if arguments");
+  NSMF_TRY(ctx, launch_gemv(ctx->stream, prec, n, k, V, ldv, h, alpha, w, flag), "gemv");
+  return NSMF_OK;
+}
+
+int nsmf_gs_norm(nsmf_ctx *ctx, int k, const double *h, double eta2, const int32_t *flag_in, int32_t *flag_out,
+                 double *nrm2) {
+  if (!ctx) return NSMF_EINVAL;
+  if (!h || !nrm2 || k < 0 || k >= MAX_DOTS || !(eta2 >= 0.0 && eta2 <= 1.0))
+    return ctx->fail(NSMF_EINVAL, "bad nsmf_gs_norm arguments");
+  NSMF_TRY(ctx, launch_gs_norm(ctx->stream, k, h, eta2, flag_in, flag_out, nrm2), "gs_norm");
+  return NSMF_OK;
+}
+
 int nsmf_vec_axpby(nsmf_ctx *ctx, int prec, int64_t n, double a, const void *x, double b, void *y) {
   int rc = vec_check(ctx, prec, n);
   if (rc) return rc;

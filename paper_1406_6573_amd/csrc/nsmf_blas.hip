@@ -24,8 +24,9 @@ constexpr int DOT_GROUP = 8, DOT_ROWS = 2;
 template <typename T, bool VEC>
 __global__ void __launch_bounds__(BLAS_NT)
 k_dots_partial(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const T *__restrict__ w,
-               double *__restrict__ partial) {
+               double *__restrict__ partial, const int32_t *__restrict__ flag) {
   __shared__ double red[DOT_GROUP][BLAS_NT];
+  if (flag != nullptr && flag[0] == 0) return;   // conditional call not taken (k_dots_final zeroes h)
   constexpr int VW = VEC ? Vec16<T>::W : 1;
   typedef typename Vec16<T>::type vec;
   const int64_t nv = n / VW;   // whole vectors (VEC) or entries
@@ -87,9 +88,13 @@ k_dots_partial(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const T *
 // h[i] = sum over the nb blocks of partial[b][i]: one block per dot, a fixed-order strided sum per
 // thread and a fixed tree across the block
 __global__ void __launch_bounds__(BLAS_NT) k_dots_final(int nb, const double *__restrict__ partial,
-                                                        double *__restrict__ h) {
+                                                        double *__restrict__ h, const int32_t *__restrict__ flag) {
   __shared__ double red[BLAS_NT];
   const int i = blockIdx.x;
+  if (flag != nullptr && flag[0] == 0) {   // conditional call not taken: h[i] = 0
+    if (threadIdx.x == 0) h[i] = 0.0;
+    return;
+  }
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += BLAS_NT) s += partial[(size_t)b * MAX_DOTS + i];
   red[threadIdx.x] = s;
@@ -108,7 +113,8 @@ __global__ void __launch_bounds__(BLAS_NT) k_dots_final(int nb, const double *__
 constexpr int GEMV_GROUP = 8;
 template <typename T, bool VEC>
 __global__ void k_gemv(int64_t n, int k, const T *__restrict__ V, int64_t ldv, const double *__restrict__ h,
-                       double alpha, T *__restrict__ w) {
+                       double alpha, T *__restrict__ w, const int32_t *__restrict__ flag) {
+  if (flag != nullptr && flag[0] == 0) return;   // conditional call not taken
   constexpr int VW = VEC ? Vec16<T>::W : 1;
   typedef typename Vec16<T>::type vec;
   const int64_t nv = n / VW;
@@ -191,37 +197,60 @@ static bool vec_ok(const T *V, int64_t ldv, int k, const T *w) {
 }
 
 template <typename T>
-static void dots_t(hipStream_t s, int64_t n, int k, const T *V, int64_t ldv, const T *w, double *partial, int nb) {
+static void dots_t(hipStream_t s, int64_t n, int k, const T *V, int64_t ldv, const T *w, double *partial, int nb,
+                   const int32_t *flag) {
   if (vec_ok(V, ldv, k, w))
-    hipLaunchKernelGGL((k_dots_partial<T, true>), dim3(nb), dim3(BLAS_NT), 0, s, n, k, V, ldv, w, partial);
+    hipLaunchKernelGGL((k_dots_partial<T, true>), dim3(nb), dim3(BLAS_NT), 0, s, n, k, V, ldv, w, partial, flag);
   else
-    hipLaunchKernelGGL((k_dots_partial<T, false>), dim3(nb), dim3(BLAS_NT), 0, s, n, k, V, ldv, w, partial);
+    hipLaunchKernelGGL((k_dots_partial<T, false>), dim3(nb), dim3(BLAS_NT), 0, s, n, k, V, ldv, w, partial, flag);
 }
 
 hipError_t launch_dots(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w,
-                       double *partial, double *h) {
+                       double *partial, double *h, const int32_t *flag) {
   const int nb = n < (int64_t)DOT_BLOCKS * BLAS_NT ? nblk(n) : DOT_BLOCKS;
-  if (prec == 0) dots_t<double>(s, n, k, (const double *)V, ldv, (const double *)w, partial, nb);
-  else dots_t<float>(s, n, k, (const float *)V, ldv, (const float *)w, partial, nb);
-  hipLaunchKernelGGL(k_dots_final, dim3(k), dim3(BLAS_NT), 0, s, nb, partial, h);
+  if (prec == 0) dots_t<double>(s, n, k, (const double *)V, ldv, (const double *)w, partial, nb, flag);
+  else dots_t<float>(s, n, k, (const float *)V, ldv, (const float *)w, partial, nb, flag);
+  hipLaunchKernelGGL(k_dots_final, dim3(k), dim3(BLAS_NT), 0, s, nb, partial, h, flag);
   return hipGetLastError();
 }
 
 template <typename T>
-static void gemv_t(hipStream_t s, int64_t n, int k, const T *V, int64_t ldv, const double *h, double alpha, T *w) {
+static void gemv_t(hipStream_t s, int64_t n, int k, const T *V, int64_t ldv, const double *h, double alpha, T *w,
+                   const int32_t *flag) {
   if (vec_ok(V, ldv, k, (const T *)w)) {
     constexpr int VW = Vec16<T>::W;
     const int64_t items = n / VW + n % VW;
-    hipLaunchKernelGGL((k_gemv<T, true>), dim3(nblk(items)), dim3(BLAS_NT), 0, s, n, k, V, ldv, h, alpha, w);
+    hipLaunchKernelGGL((k_gemv<T, true>), dim3(nblk(items)), dim3(BLAS_NT), 0, s, n, k, V, ldv, h, alpha, w, flag);
   } else {
-    hipLaunchKernelGGL((k_gemv<T, false>), dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, k, V, ldv, h, alpha, w);
+    hipLaunchKernelGGL((k_gemv<T, false>), dim3(nblk(n)), dim3(BLAS_NT), 0, s, n, k, V, ldv, h, alpha, w, flag);
   }
 }
 
 hipError_t launch_gemv(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
-                       double alpha, void *w) {
-  if (prec == 0) gemv_t<double>(s, n, k, (const double *)V, ldv, h, alpha, (double *)w);
-  else gemv_t<float>(s, n, k, (const float *)V, ldv, h, alpha, (float *)w);
+                       double alpha, void *w, const int32_t *flag) {
+  if (prec == 0) gemv_t<double>(s, n, k, (const double *)V, ldv, h, alpha, (double *)w, flag);
+  else gemv_t<float>(s, n, k, (const float *)V, ldv, h, alpha, (float *)w, flag);
+  return hipGetLastError();
+}
+
+// Squared norm after the projection w -= V h, from the dots of the rows and of w itself (h[k] = |w|^2):
+// nrm2 = h[k] - sum_{i<k} h[i]^2 (exact when the rows are orthonormal), summed in a fixed order, and
+// the test for a second Gram-Schmidt pass, nrm2 < eta2 h[k] (the criterion of Daniel, Gragg, Kaufman
+// and Stewart, 1976).  A flag_in of 0 leaves everything unchanged.
+__global__ void k_gs_norm(int k, const double *__restrict__ h, double eta2, const int32_t *__restrict__ flag_in,
+                          int32_t *__restrict__ flag_out, double *__restrict__ nrm2) {
+  if (flag_in != nullptr && flag_in[0] == 0) return;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s += h[i] * h[i];
+  const double est = h[k] - s;
+  nrm2[0] = est;
+  if (flag_out != nullptr) flag_out[0] = est < eta2 * h[k] ? 1 : 0;
+}
+
+hipError_t launch_gs_norm(hipStream_t s, int k, const double *h, double eta2, const int32_t *flag_in, int32_t *flag_out,
+                          double *nrm2) {
+  hipLaunchKernelGGL(k_gs_norm, dim3(1), dim3(64), 0, s, k, h, eta2, flag_in, flag_out, nrm2);
   return hipGetLastError();
 }
 

@@ -183,10 +183,13 @@ hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *pt
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);
 hipError_t launch_f2d(hipStream_t s, const float *in, double *out, int64_t n);
 hipError_t launch_recip(hipStream_t s, int64_t n, double *x);
+// flag (DEVICE, may be null): when flag[0] == 0 the call is not taken (dots write h = 0)
 hipError_t launch_dots(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const void *w,
-                       double *partial, double *h);
+                       double *partial, double *h, const int32_t *flag = nullptr);
 hipError_t launch_gemv(hipStream_t s, int prec, int64_t n, int k, const void *V, int64_t ldv, const double *h,
-                       double alpha, void *w);
+                       double alpha, void *w, const int32_t *flag = nullptr);
+hipError_t launch_gs_norm(hipStream_t s, int k, const double *h, double eta2, const int32_t *flag_in, int32_t *flag_out,
+                          double *nrm2);
 hipError_t launch_axpby(hipStream_t s, int prec, int64_t n, double a, const void *x, double b, void *y);
 hipError_t launch_mul(hipStream_t s, int prec, int64_t n, const double *d, const void *x, void *z);
 hipError_t launch_normalize(hipStream_t s, int prec, int64_t n, const double *nrm2, void *x);

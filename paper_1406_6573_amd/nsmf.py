@@ -28,7 +28,7 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
             "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization",
             "nsmf_jacobian_apply_noalloc", "nsmf_lowo_apply", "nsmf_coarse_setup", "nsmf_coarse_prolong",
-            "nsmf_coarse_restrict", "nsmf_vec_normalize"]
+            "nsmf_coarse_restrict", "nsmf_vec_normalize", "nsmf_vec_dots_if", "nsmf_vec_gemv_if", "nsmf_gs_norm"]
 
 
 class NsmfError(RuntimeError):
@@ -93,6 +93,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_vec_axpby.argtypes = [vp, ci, i64, dbl, vp, dbl, vp]
     lib.nsmf_vec_mul.argtypes = [vp, ci, i64, vp, vp, vp]
     lib.nsmf_vec_normalize.argtypes = [vp, ci, i64, vp, vp]
+    lib.nsmf_vec_dots_if.argtypes = [vp, vp, ci, i64, ci, vp, i64, vp, vp]
+    lib.nsmf_vec_gemv_if.argtypes = [vp, vp, ci, i64, ci, vp, i64, vp, dbl, vp]
+    lib.nsmf_gs_norm.argtypes = [vp, ci, vp, dbl, vp, vp, vp]
     lib.nsmf_vec_convert.argtypes = [vp, i64, ci, vp, vp]
     _lib = lib
     return lib
@@ -410,6 +413,48 @@ class Engine:
         self._flat(d, n, self.torch.float64, "d")
         self.sync_stream()
         self._check(self.lib.nsmf_vec_mul(self.h, self._prec_of(z), n, _ptr(d), _ptr(x), _ptr(z)))
+
+    def _flag(self, f, name):
+        if f is None:
+            return None
+        if not (f.is_cuda and f.device.index == self.device) or f.dtype != self.torch.int32 or f.numel() < 1:
+            raise ValueError(f"{name} must be an int32 CUDA tensor on device {self.device}")
+        return f
+
+    def vec_dots_if(self, flag, V, k, w, h):
+        """vec_dots when flag[0] != 0 (a device int32), else h[:k] = 0; decided on the device."""
+        prec = self._prec_of(w)
+        n = w.numel()
+        self._flat(w, n, w.dtype, "w")
+        self._basis(V, k, n, w.dtype)
+        self._flat(h, k, self.torch.float64, "h")
+        self._flag(flag, "flag")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_dots_if(self.h, _ptr(flag), prec, n, int(k), _ptr(V), V.stride(0), _ptr(w),
+                                              _ptr(h)))
+
+    def vec_gemv_if(self, flag, V, k, h, alpha, w):
+        """vec_gemv when flag[0] != 0 (a device int32), else w unchanged; decided on the device."""
+        prec = self._prec_of(w)
+        n = w.numel()
+        self._flat(w, n, w.dtype, "w")
+        self._basis(V, k, n, w.dtype)
+        self._flat(h, k, self.torch.float64, "h")
+        self._flag(flag, "flag")
+        self.sync_stream()
+        self._check(self.lib.nsmf_vec_gemv_if(self.h, _ptr(flag), prec, n, int(k), _ptr(V), V.stride(0), _ptr(h),
+                                              float(alpha), _ptr(w)))
+
+    def gs_norm(self, k, h, eta2, flag_in, flag_out, nrm2):
+        """nrm2[0] = h[k] - sum_{i<k} h[i]^2 and flag_out[0] = (nrm2[0] < eta2 h[k]) on the device (see
+        nsmf_gs_norm); nothing is written when flag_in is given and flag_in[0] == 0."""
+        self._flat(h, k + 1, self.torch.float64, "h")
+        self._flat(nrm2, 1, self.torch.float64, "nrm2")
+        self._flag(flag_in, "flag_in")
+        self._flag(flag_out, "flag_out")
+        self.sync_stream()
+        self._check(self.lib.nsmf_gs_norm(self.h, int(k), _ptr(h), float(eta2), _ptr(flag_in), _ptr(flag_out),
+                                          _ptr(nrm2)))
 
     def vec_normalize(self, nrm2, x):
         """x = x / sqrt(nrm2[0]) with nrm2 a float64 device tensor (x = 0 when nrm2[0] <= 0)."""

@@ -189,10 +189,12 @@ class NewtonKrylov:
         self.V = torch.empty((restart + 1, ld), dtype=kt, device=dev)[:, :self.n]
         self.Z = torch.empty((restart, ld), dtype=kt, device=dev)[:, :self.n]
         self.h = torch.empty(64, dtype=torch.float64, device=dev)
-        # Hessenberg columns of one cycle: two Gram-Schmidt passes and the squared norm per step, on the
-        # device and their pinned host copies
+        # Hessenberg columns of one cycle: the two Gram-Schmidt passes (the second zero when not taken)
+        # and the squared norm per step, on the device and their pinned host copies
         self.Hd = torch.zeros((restart, 3, 64), dtype=torch.float64, device=dev)
         self.Hh = torch.zeros((restart, 3, 64), dtype=torch.float64, pin_memory=True)
+        self.reorth = torch.zeros(1, dtype=torch.int32, device=dev)   # second Gram-Schmidt pass taken
+        self.reorth_eta2 = 0.01
         self.events = [torch.cuda.Event() for _ in range(restart)]
         self.minv = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.w64 = torch.empty(self.n, dtype=torch.float64, device=dev)
@@ -266,8 +268,9 @@ class NewtonKrylov:
         """Approximately solve J x = b (vectors of the Krylov precision), x += correction.
         Returns (iterations, residual estimate / ||b||).
 
-        An Arnoldi step runs entirely on the device: both Gram-Schmidt passes (multi-dots into a device
-        Hessenberg column, basis combination), the norm and the normalisation by it.  The column is
+        An Arnoldi step runs entirely on the device: the Gram-Schmidt pass (multi-dots into a device
+        Hessenberg column, basis combination), the norm, the test for a second pass and that pass when
+        the test asks for it (both on the device), and the normalisation.  The column is
         copied to pinned host memory asynchronously, and the host applies the Givens rotations to
         column j - 1 while step j is queued, so no step waits for the host.  When column j - 1 meets
         the tolerance, the already computed column j is used as well (one step more than a
@@ -312,11 +315,18 @@ class NewtonKrylov:
             self.precondition(V[j], Z[j])                  # z_j = M^-1 v_j
             wj = V[j + 1]
             self.apply(Z[j], wj)
-            for ps in range(2):                            # classical Gram-Schmidt, twice
-                eng.vec_dots(V, j + 1, wj, Hd[j, ps])
-                eng.vec_gemv(V, j + 1, Hd[j, ps], -1.0, wj)
-            eng.vec_dots(wj.view(1, -1), 1, wj, Hd[j, 2])   # ||w||^2
-            eng.vec_normalize(Hd[j, 2], wj)
+            # classical Gram-Schmidt; the rows include w itself, so the last dot is |w|^2.  The squared
+            # norm after the projection follows from the dots; a second pass runs, decided on the device,
+            # only when it fell below eta2 |w|^2 (the Daniel-Gragg-Kaufman-Stewart test; eta2 = 0.01 lets
+            # a pass lose at most one digit of orthogonality before it is repeated)
+            h1, h2, hn = Hd[j, 0], Hd[j, 1], Hd[j, 2]
+            eng.vec_dots(V, j + 2, wj, h1)
+            eng.vec_gemv(V, j + 1, h1, -1.0, wj)
+            eng.gs_norm(j + 1, h1, self.reorth_eta2, None, self.reorth, hn)
+            eng.vec_dots_if(self.reorth, V, j + 2, wj, h2)
+            eng.vec_gemv_if(self.reorth, V, j + 1, h2, -1.0, wj)
+            eng.gs_norm(j + 1, h2, 0.0, self.reorth, None, hn)
+            eng.vec_normalize(hn, wj)
             Hh[j].copy_(Hd[j], non_blocking=True)
             events[j].record()
             if j >= 1:

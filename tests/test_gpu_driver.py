@@ -139,6 +139,47 @@ def test_vector_kernels(torch_cuda):
             eng.vec_gemv(Vp, k2, h, -0.5, w2)
             ref2 = before - 0.5 * (Vp.double().T @ h[:k2])
             assert torch.allclose(w2.double(), ref2, rtol=1e-6 if dt == torch.float32 else 1e-13, atol=1e-6)
+    # conditional second Gram-Schmidt pass: gs_norm against the projected norm, the flag from the
+    # criterion, and the _if kernels taken or not
+    for dt in (torch.float64, torch.float32):
+        k3 = 9
+        ld = (n + 63) // 64 * 64
+        B = torch.empty((k3 + 1, ld), dtype=dt, device="cuda")[:, :n]
+        Q, _ = torch.linalg.qr(torch.rand((n, k3), dtype=torch.float64, device="cuda", generator=g) - 0.5)
+        B[:k3] = Q.T.to(dt)
+        wv = B[k3]
+        for frac, expect in ((0.3, 0), (0.999, 1)):
+            # w = frac of its norm inside span(Q) (squared norm of the projection 1 - frac^2 of |w|^2)
+            a = torch.rand(k3, dtype=torch.float64, device="cuda", generator=g) - 0.5
+            perp = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) - 0.5
+            perp -= Q @ (Q.T @ perp)
+            x0 = frac * (Q @ a) / (Q @ a).norm() + (1 - frac ** 2) ** 0.5 * perp / perp.norm()
+            wv.copy_(x0.to(dt))
+            h = torch.zeros(64, dtype=torch.float64, device="cuda")
+            h2 = torch.full((64,), 7.0, dtype=torch.float64, device="cuda")
+            nrm2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+            flag = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+            eng.vec_dots(B, k3 + 1, wv, h)
+            assert abs(float(h[k3]) - float(wv.double().norm() ** 2)) < 1e-6
+            w_before = wv.double().clone()
+            eng.vec_gemv(B, k3, h, -1.0, wv)
+            eng.gs_norm(k3, h, 0.5, None, flag, nrm2)
+            assert int(flag) == expect
+            tol = 1e-5 if dt == torch.float32 else 1e-12
+            assert abs(float(nrm2) - float(wv.double().norm() ** 2)) < tol
+            w1 = wv.double().clone()
+            eng.vec_dots_if(flag, B, k3 + 1, wv, h2)
+            eng.vec_gemv_if(flag, B, k3, h2, -1.0, wv)
+            if expect:
+                assert torch.allclose(h2[:k3], B[:k3].double() @ w1, atol=1e-6)
+                assert torch.allclose(wv.double(), w1 - B[:k3].double().T @ h2[:k3], atol=1e-6)
+                eng.gs_norm(k3, h2, 0.0, flag, None, nrm2)
+                assert abs(float(nrm2) - float(wv.double().norm() ** 2)) < tol
+            else:
+                assert torch.count_nonzero(h2[:k3]) == 0 and torch.equal(wv.double(), w1)
+                before = float(nrm2)
+                eng.gs_norm(k3, h2, 0.0, flag, None, nrm2)   # not taken: nrm2 unchanged
+                assert float(nrm2) == before
     x = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
     x32 = torch.empty(n, dtype=torch.float32, device="cuda")
     eng.vec_convert(x, x32)
