@@ -188,6 +188,14 @@ int nsmf_jacobian_apply(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_
  * NSMF_ESTATE (no state), NSMF_EHIP. */
 int nsmf_jacobian_apply_noalloc(nsmf_ctx *ctx, int prec, const void *x_u, const void *x_p, void *y_u, void *y_p);
 
+/* Pressure gradient y_u = B^T x_p: the discrete form of the term -int p div v of eq. (weak),
+ * i.e. the velocity rows of nsmf_jacobian_apply at zero velocity (Dirichlet rows 0, nodal frames
+ * applied).  It depends on the mesh only (no state needed).  x_p [n_el][n_p] and y_u [3][n_nodes]
+ * DEVICE, of the precision prec (0 FP64, 1 FP32, 2 FP32 with bfloat16-rounded 1D operators).  Used
+ * by the block upper-triangular preconditioner of Sec. 4.2.  Errors: NSMF_EINVAL, NSMF_ESTATE (no
+ * mesh). */
+int nsmf_gradient_apply(nsmf_ctx *ctx, int prec, const void *x_p, void *y_u);
+
 /* Vector-Jacobian product of the residual at the state for cotangent w = (w_u, w_p).
  * Sec. 2.3: the adjoint (transposed) linearisation of eq. (weak) uses the same fourth-order
  * tensor of eq. (rank4) as the Newton step, and A(u) is symmetric (Sec. 4.1), so

@@ -651,6 +651,22 @@ int nsmf_jacobian_apply_noalloc(nsmf_ctx *ctx, int prec, const void *x_u, const 
   return NSMF_OK;
 }
 
+int nsmf_gradient_apply(nsmf_ctx *ctx, int prec, const void *x_p, void *y_u) {
+  if (!ctx || !x_p || !y_u) return NSMF_EINVAL;
+  if (prec < 0 || prec > 2) return ctx->fail(NSMF_EINVAL, "precision must be 0, 1 or 2");
+  if (!ctx->have_mesh) return ctx->fail(NSMF_ESTATE, "no mesh uploaded");
+  hipStream_t s = ctx->stream;
+  GeoView<double> g64 = ctx->geo64();
+  GeoView<float> g32 = ctx->geo32();
+  const void *gv = prec == 0 ? (const void *)&g64 : (const void *)&g32;
+  NSMF_TRY(ctx, launch_grad_p(ctx->P, ctx->geo, ctx->ps, prec, s, ctx->mesh_view(), gv, ctx->tabs.p, x_p, ctx->ev.p),
+           "gradient kernel");
+  NSMF_TRY(ctx, launch_assemble(s, prec, ctx->n_nodes, ctx->inc_ptr.p, ctx->ev.p, ctx->n_ent, ctx->dmask.p, nullptr,
+                                nullptr, y_u, 0.0),
+           "assembly");
+  return NSMF_OK;
+}
+
 int nsmf_residual_vjp(nsmf_ctx *ctx, int prec, const void *w_u, const void *w_p, void *g_u, void *g_p,
                       double *g_logA, double *g_beta) {
   return apply_common(ctx, prec, true, w_u, w_p, g_u, g_p, g_logA, g_beta);

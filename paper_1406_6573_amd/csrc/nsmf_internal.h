@@ -123,6 +123,9 @@ hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t 
                         const void *tabs, const void *state, const void *fstate, const void *beta,
                         const void *x_u, const void *x_p, void *y_u, void *y_p, double inv_n,
                         double *g_logA, double *g_beta);
+// y_u = B^T x_p into the element vector (prec 0, 1, 2 as launch_apply)
+hipError_t launch_grad_p(int P, int geo, int ps, int prec, hipStream_t s, const MeshView &m, const void *gview,
+                         const void *tabs, const void *xp, void *yu);
 hipError_t launch_residual(int P, int geo, int ps, hipStream_t s, const MeshView &m, const GeoView<double> &g,
                            const void *tabs, const double *st64, const double *fst64, const double *beta,
                            const double *p, const double *body, double *r_u, double *r_p);
@@ -178,8 +181,9 @@ inline bool zline_run_host(uint32_t cm, int P, int i, int j, int &lo, int &hi) {
   hi = (((f >> 5) & 1u) || edge(0, j, P - 1) || edge(1, i, P - 1)) ? P - 2 : P - 1;
   return true;
 }
+// mval: value of the Dirichlet rows when xm is null
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_ent,
-                           const uint8_t *dm, const void *xm, const void *f, void *y);
+                           const uint8_t *dm, const void *xm, const void *f, void *y, double mval = 1.0);
 hipError_t launch_d2f(hipStream_t s, const double *in, float *out, int64_t n);
 hipError_t launch_f2d(hipStream_t s, const float *in, double *out, int64_t n);
 hipError_t launch_recip(hipStream_t s, int64_t n, double *x);

@@ -1060,6 +1060,71 @@ k_apply(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const void
 }
 
 
+// Pressure gradient y = B^T x_p (eq. (weak): the term -int p div v), the velocity rows of the
+// Jacobian apply at zero velocity: per quadrature point only tau = -p w detJ I, so the gather, the
+// forward sweeps, the linearisation data and the basal term drop out; the transposed sweeps, R_e^T,
+// the frames and the element-vector store are those of k_apply.
+template <typename T, int P, int GEO, int PS, bool FR>
+__global__ void __launch_bounds__(Launch<P>::NT)
+k_grad_p(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *__restrict__ xp, T *__restrict__ yu) {
+  constexpr int E = Launch<P>::E, NT = Launch<P>::NT, P2 = P * P, P3 = P2 * P;
+  constexpr int NP = n_pres<P, PS>(), NPT = (NP + P2 - 1) / P2;
+  __shared__ T smem[E * Ws<T, P>::ES];
+  __shared__ double red[E * red_stride<P, PS>()];
+  const Tab<T, P> &tb = *tbp;
+  const int lb = logical_block();
+  const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
+  const int64_t e = tile_elem<E>(m, lb, el);
+  const bool act = e >= 0;
+  const int els = el < E ? el : E - 1;
+  Ws<T, P> w{smem + els * Ws<T, P>::ES};
+  const StoreIndex<P> ix = store_index<P>(m, lb, e, t, act);
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  const bool rot = FR && act && (m.en[e * P3 + t] & ROT_BIT);
+  QpGeo<T, P, GEO> g;
+  T xpt[NPT];
+  if (act) {
+    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (t + r * P2 < NP) xpt[r] = xp[e * NP + t + r * P2];
+  }
+  T *xps = reinterpret_cast<T *>(red + els * red_stride<P, PS>());
+  if (act)
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (t + r * P2 < NP) xps[t + r * P2] = xpt[r];
+  __syncthreads();
+  T pq[P];
+  if (act) pressure_interp<T, P, PS>(xps, tb, t, pq);
+  T f[3][3][P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T tau[3][3], ff[3][3];
+    const T pw = act ? pq[i] * g.wdet(tb, i) : T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) tau[c][r] = c == r ? -pw : T(0);
+    to_ref<T, P, GEO>(g, i, tau, ff);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) f[c][r][i] = act ? ff[c][r] : T(0);
+  }
+  T y[3][P];
+  const T zero[P] = {};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad_bwd<T, P, false>(f[c][0], f[c][1], f[c][2], zero, y[c], w, tb, t, act);
+  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  if (rot) {
+    T Q[9];
+    frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
+    frame_out<T, P>(y, Q);
+  }
+  evec_store<T, P>(yu, m, ix, smem, els, t, act, y);
+}
+
 // Linearisation point: per quadrature point mu' = w detJ mu, kappa, Sigma0 = mu' D(u)
 // (FP64, eq. (glen) and eq. (rank4)); per basal face point w|S| T u.  The Picard operator keeps
 // mu and drops the D (x) D part of the tensor: kappa = 0.
@@ -2284,7 +2349,8 @@ k_lowo(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, c
 // ---------------------------------------------------------------- assembly  y = sum_e R_e^T y_e
 // One thread per node: sums the node's contiguous segment of the node-ordered element vector
 // (fixed order, so the result is deterministic).  Rows of Dirichlet-flagged components take the
-// value xm (x for the Jacobian, u for the residual); other rows subtract f when given.
+// value xm (x for the Jacobian, u for the residual), or mval without xm; other rows subtract f when
+// given.
 constexpr int ASM_NT = 256;
 constexpr int ASM_TILE = 4 * ASM_NT;
 
@@ -2294,7 +2360,8 @@ constexpr int ASM_TILE = 4 * ASM_NT;
 template <typename T>
 __global__ void __launch_bounds__(ASM_NT)
 k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_ent,
-           const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f, T *__restrict__ y) {
+           const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f, T *__restrict__ y,
+           T mval) {
   if constexpr (sizeof(T) == 8) {
     // FP64: the tile would take 24 KiB of LDS per block and cap the occupancy; each thread reads
     // its own segment instead, in predicated chunks of four entries (measured 3% faster there,
@@ -2320,7 +2387,7 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = c * N + n;
-      y[i] = dm[i] ? (xm ? xm[i] : T(1)) : (f ? sv[c] - f[i] : sv[c]);
+      y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]);
     }
   } else {
     __shared__ T tile[3][ASM_TILE];
@@ -2366,7 +2433,7 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = c * N + n;
-      y[i] = dm[i] ? (xm ? xm[i] : T(1)) : (f ? sv[c] - f[i] : sv[c]);
+      y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]);
     }
   }
 }
@@ -2384,13 +2451,13 @@ __global__ void k_d2f(const double *in, float *out, int64_t n) {
 static inline int grid1(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_ent,
-                           const uint8_t *dm, const void *xm, const void *f, void *y) {
+                           const uint8_t *dm, const void *xm, const void *f, void *y, double mval) {
   if (prec == 0)
     hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const double *)ev, n_ent,
-                       dm, (const double *)xm, (const double *)f, (double *)y);
+                       dm, (const double *)xm, (const double *)f, (double *)y, mval);
   else
     hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev, n_ent, dm,
-                       (const float *)xm, (const float *)f, (float *)y);
+                       (const float *)xm, (const float *)f, (float *)y, (float)mval);
   return hipGetLastError();
 }
 
@@ -2521,6 +2588,37 @@ hipError_t launch_apply(int P, int geo, int ps, int prec, bool vjp, hipStream_t 
   NSMF_AP2(float, 5)
 #undef NSMF_AP2
 #undef NSMF_AP
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P, int GEO, int PS>
+static hipError_t grad_p_t(hipStream_t s, const MeshView &m, const void *gview, const void *tabs, bool bf16,
+                           const void *xp, void *yu) {
+  const TabSet<P> *ts = (const TabSet<P> *)tabs;
+  const Tab<T, P> *tb;
+  if constexpr (sizeof(T) == 8) tb = &ts->d;
+  else tb = bf16 ? &ts->fb : &ts->f;
+  const GeoView<T> &gv = *(const GeoView<T> *)gview;
+  if (gv.rot != nullptr)
+    hipLaunchKernelGGL((k_grad_p<T, P, GEO, PS, true>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, gv, tb,
+                       (const T *)xp, (T *)yu);
+  else
+    hipLaunchKernelGGL((k_grad_p<T, P, GEO, PS, false>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, gv, tb,
+                       (const T *)xp, (T *)yu);
+  return hipGetLastError();
+}
+hipError_t launch_grad_p(int P, int geo, int ps, int prec, hipStream_t s, const MeshView &m, const void *gview,
+                         const void *tabs, const void *xp, void *yu) {
+  const bool bf = prec == 2;
+#define NSMF_GP(TT, PP, GG)                                                                            \
+  if (P == PP && geo == GG && (sizeof(TT) == 8) == (prec == 0) && ps == PS_P)                         \
+    return grad_p_t<TT, PP, GG, PS_P>(s, m, gview, tabs, bf, xp, yu);                                 \
+  if (P == PP && geo == GG && (sizeof(TT) == 8) == (prec == 0) && ps == PS_Q)                         \
+    return grad_p_t<TT, PP, GG, PS_Q>(s, m, gview, tabs, bf, xp, yu);
+#define NSMF_GP2(TT, PP) NSMF_GP(TT, PP, GEO_AFFINE) NSMF_GP(TT, PP, GEO_COLUMN)
+  NSMF_GP2(double, 3) NSMF_GP2(double, 4) NSMF_GP2(double, 5) NSMF_GP2(float, 3) NSMF_GP2(float, 4) NSMF_GP2(float, 5)
+#undef NSMF_GP2
+#undef NSMF_GP
   return hipErrorInvalidValue;
 }
 

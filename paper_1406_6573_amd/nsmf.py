@@ -28,7 +28,8 @@ EXPORTED = ["nsmf_create", "nsmf_destroy", "nsmf_set_stream", "nsmf_upload_mesh"
             "nsmf_version", "nsmf_jacobi_diag", "nsmf_vec_dots", "nsmf_vec_gemv", "nsmf_vec_axpby", "nsmf_vec_mul",
             "nsmf_vec_convert", "nsmf_line_setup", "nsmf_line_apply", "nsmf_set_linearization",
             "nsmf_jacobian_apply_noalloc", "nsmf_lowo_apply", "nsmf_coarse_setup", "nsmf_coarse_prolong",
-            "nsmf_coarse_restrict", "nsmf_vec_normalize", "nsmf_vec_dots_if", "nsmf_vec_gemv_if", "nsmf_gs_norm"]
+            "nsmf_coarse_restrict", "nsmf_vec_normalize", "nsmf_vec_dots_if", "nsmf_vec_gemv_if", "nsmf_gs_norm",
+            "nsmf_gradient_apply"]
 
 
 class NsmfError(RuntimeError):
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nsmf_set_state.argtypes = [vp, vp, vp]
     lib.nsmf_residual.argtypes = [vp, vp, vp, vp]
     lib.nsmf_jacobian_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.nsmf_gradient_apply.argtypes = [vp, ctypes.c_int, vp, vp]
     lib.nsmf_jacobian_apply_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     lib.nsmf_residual_vjp.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
     lib.nsmf_query.argtypes = [vp, i64p, i64p, i64p, i64p, i64p]
@@ -267,6 +269,18 @@ class Engine:
         self.sync_stream()
         self._check(self.lib.nsmf_jacobian_apply(self.h, prec, _ptr(x_u), _ptr(x_p), _ptr(out[0]), _ptr(out[1])))
         return out
+
+    def gradient_apply(self, x_p, prec="fp64", out=None):
+        """y_u = B^T x_p, the velocity rows of the Jacobian apply at zero velocity (mesh only)."""
+        prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        dt = self._dtype(prec)
+        sz = self.sizes
+        x_p = self._vec(x_p, (sz["n_el"], sz["n_p"]), dt, "x_p")
+        y_u = (self.torch.empty((3, sz["n_nodes"]), dtype=dt, device=self.dev) if out is None
+               else self._vec(out, (3, sz["n_nodes"]), dt, "out"))
+        self.sync_stream()
+        self._check(self.lib.nsmf_gradient_apply(self.h, prec, _ptr(x_p), _ptr(y_u)))
+        return y_u
 
     def jacobian_apply_noalloc(self, x_u, x_p, out, prec="fp64"):
         """y = J_c x through the allocation-free entry point: the partial sums live in the library's

@@ -9,8 +9,9 @@ banded Cholesky factors of F restricted to each column of nodes, which resolve
 the strong vertical coupling of thin columns.  With triangular=True the
 preconditioner is the block upper-triangular [[F~, B^T], [0, S~]] of Sec. 4.2
 instead of the block-diagonal one: z_p = S~^-1 v_p, z_u = F~^-1 (v_u - B^T z_p),
-with B^T z_p from the engine's Jacobian apply at zero velocity (one more apply
-per iteration, fewer iterations).  A backtracking line search on ||r|| accepts
+with B^T z_p from the engine's pressure-gradient apply (the velocity rows of the
+Jacobian apply at zero velocity; one more, lighter, element pass per iteration,
+fewer iterations).  A backtracking line search on ||r|| accepts
 the step.  With linearization="picard" the steps solve with the Picard operator
 instead (viscosity kept, the anisotropic part of the Newton tensor dropped;
 Sec. 2.3), which converges linearly where Newton converges quadratically.
@@ -194,7 +195,10 @@ class NewtonKrylov:
         self.Hd = torch.zeros((restart, 3, 64), dtype=torch.float64, device=dev)
         self.Hh = torch.zeros((restart, 3, 64), dtype=torch.float64, pin_memory=True)
         self.reorth = torch.zeros(1, dtype=torch.int32, device=dev)   # second Gram-Schmidt pass taken
-        self.reorth_eta2 = 0.01
+        # second Gram-Schmidt pass when the projection kept less than eta2 of |w|^2: 0.01 (a pass may
+        # lose one digit of orthogonality) for cycles whose target is 1e-6 or looser, 1/2 (the
+        # classical constant) for tighter targets, whose attainable residual the loss would limit
+        self.reorth_eta2_loose, self.reorth_eta2_tight, self.reorth_tol = 0.01, 0.5, 1e-6
         self.events = [torch.cuda.Event() for _ in range(restart)]
         self.minv = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.w64 = torch.empty(self.n, dtype=torch.float64, device=dev)
@@ -202,7 +206,6 @@ class NewtonKrylov:
         self.d64 = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.tmp = torch.empty(self.n, dtype=kt, device=dev)
         if triangular:
-            self.zero_u = torch.zeros((3, self.N), dtype=kt, device=dev)
             self.bt = torch.empty(self.n, dtype=kt, device=dev)
         self.coarse, self.coarse_mode = None, coarse_mode
         if coarse is not None:
@@ -231,9 +234,9 @@ class NewtonKrylov:
         eng.vec_mul(self.minv[3 * self.N:], vp.reshape(-1), zp.reshape(-1))      # z_p = S~^-1 v_p
         ru = vu
         if self.triangular:                                                       # v_u - B^T z_p
-            bu, bp = self.split(self.bt)
+            bu, _ = self.split(self.bt)
             prec = "fp64" if v.dtype == torch.float64 else "fp32"
-            eng.jacobian_apply(self.zero_u, zp, prec, out=(bu, bp))
+            eng.gradient_apply(zp, prec, out=bu)
             eng.vec_axpby(1.0, vu.reshape(-1), -1.0, bu.reshape(-1))
             ru = bu
         if self.coarse is not None:
@@ -276,6 +279,7 @@ class NewtonKrylov:
         the tolerance, the already computed column j is used as well (one step more than a
         synchronous loop would take)."""
         eng, V, Z, m = self.eng, self.V, self.Z, self.m
+        eta2 = self.reorth_eta2_loose if tol >= self.reorth_tol else self.reorth_eta2_tight
         w = V[0]
         self.apply(x, w)
         eng.vec_axpby(1.0, b, -1.0, w)                   # r = b - J x, stored in V[0]
@@ -317,12 +321,11 @@ class NewtonKrylov:
             self.apply(Z[j], wj)
             # classical Gram-Schmidt; the rows include w itself, so the last dot is |w|^2.  The squared
             # norm after the projection follows from the dots; a second pass runs, decided on the device,
-            # only when it fell below eta2 |w|^2 (the Daniel-Gragg-Kaufman-Stewart test; eta2 = 0.01 lets
-            # a pass lose at most one digit of orthogonality before it is repeated)
+            # only when it fell below eta2 |w|^2 (the Daniel-Gragg-Kaufman-Stewart test)
             h1, h2, hn = Hd[j, 0], Hd[j, 1], Hd[j, 2]
             eng.vec_dots(V, j + 2, wj, h1)
             eng.vec_gemv(V, j + 1, h1, -1.0, wj)
-            eng.gs_norm(j + 1, h1, self.reorth_eta2, None, self.reorth, hn)
+            eng.gs_norm(j + 1, h1, eta2, None, self.reorth, hn)
             eng.vec_dots_if(self.reorth, V, j + 2, wj, h2)
             eng.vec_gemv_if(self.reorth, V, j + 1, h2, -1.0, wj)
             eng.gs_norm(j + 1, h2, 0.0, self.reorth, None, hn)

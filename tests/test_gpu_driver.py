@@ -701,3 +701,48 @@ def test_adjoint_gradient_matches_oracle(torch_cuda):
           f"beta rel {eB:.2e} (max {mB:.2e})", flush=True)
     assert eA < 1e-8 and eB < 1e-8 and mA < 1e-8 and mB < 1e-8
     eng.close()
+
+
+@pytest.mark.parametrize("k,variant", [(2, "hang"), (3, "frames"), (4, "periodic"), (3, "q")])
+def test_gradient_apply_matches_jacobian_at_zero_velocity(torch_cuda, k, variant):
+    """nsmf_gradient_apply (B^T x_p) against the oracle's B^T in FP64, and against the velocity rows of
+    the Jacobian apply at zero velocity in FP64, FP32 and with bfloat16 operators (the same arithmetic on
+    the pressure term in another kernel, so equal up to the rounding order of the multiply-adds)."""
+    torch = torch_cuda
+    from paper_1406_6573_amd import Engine
+    from oracle import StokesOracle
+    kw = dict(q=dict(pspace="Q", mapped=True), hang={}, frames=dict(mapped=True, frames=True),
+              periodic=dict(periodic=(True, True)))[variant]
+    case = small_case(k, **kw)
+    m = case["mesh"]
+    eng = Engine()
+    eng.upload_mesh(m)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    eng.set_params(case["n"], case["eps"], case["B0"], case["body"], t(case["logA"]), t(case["beta"]))
+    eng.set_state(t(case["u"]), t(case["p"]))
+    rng = np.random.default_rng(3)
+    xp = rng.uniform(-1, 1, (m.n_el, m.n_p))
+    o = StokesOracle(m, case["n"], case["eps"], case["B0"], case["logA"], case["beta"], body=case["body"])
+    o.set_state(case["u"], case["p"])
+    K = o.jacobian()
+    N = m.n_nodes
+    x = np.concatenate([np.zeros(3 * N), xp.ravel()])
+    ref = (K @ x)[:3 * N]
+    sc = np.maximum((abs(K) @ np.abs(x))[:3 * N], 1e-300)
+    got = eng.gradient_apply(t(xp)).cpu().numpy().ravel()
+    assert np.max(np.abs(got - ref) / sc) < 1e-12
+    # per entry, relative to (|B^T||x_p|)_i.  With the velocity part of x zero the scale holds only
+    # the pressure path's terms, so the FP32 bound follows that path's depth: about 60 roundings
+    # (pressure interpolation, w detJ, the geometry, three transposed sweeps, R_e^T, the assembly) with
+    # a factor 4 of margin, 256 u; the Jacobian's FP32 rows are another rounding order of the same
+    # arithmetic
+    u32 = 2.0 ** -24
+    for prec, dt, b_ref, b_jac in (("fp64", torch.float64, 1e-12, 1e-14), ("fp32", torch.float32, 256 * u32, 256 * u32),
+                                   ("bf16ops", torch.float32, 16 * 2.0 ** -9, 256 * u32)):
+        xpt = t(xp).to(dt)
+        g = eng.gradient_apply(xpt, prec).double().cpu().numpy().ravel()
+        yu, _ = eng.jacobian_apply(torch.zeros((3, N), dtype=dt, device="cuda"), xpt, prec)
+        yu = yu.double().cpu().numpy().ravel()
+        assert np.max(np.abs(g - ref) / sc) < b_ref, prec
+        assert np.max(np.abs(g - yu) / sc) < b_jac, prec
+    eng.close()
