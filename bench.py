@@ -47,9 +47,9 @@ def algorithmic_bytes(sz, geo_kind, word):
 TRAFFIC_FILES = {2: "apply_slab64x64x8_q3_traffic.json", 3: "apply_terrain128x128x16_q4_traffic.json"}
 
 
-def measured_traffic(config_id, prec="fp32_apply"):
-    """HBM bytes per apply (every kernel of one apply) from the committed counter summary of the
-    workload, if it was taken with the current kernel sources (otherwise None)."""
+def counter_record(config_id):
+    """The committed counter summary of the workload, if it was taken with the current kernel sources
+    (otherwise None)."""
     import hashlib
     if config_id not in TRAFFIC_FILES:
         return None
@@ -60,9 +60,32 @@ def measured_traffic(config_id, prec="fp32_apply"):
     h = hashlib.sha256()
     for p in rec["sources"]:
         h.update(open(os.path.join(ROOT, p), "rb").read())
-    if h.hexdigest() != rec["source_sha256"]:
+    return rec if h.hexdigest() == rec["source_sha256"] else None
+
+
+def measured_traffic(config_id, prec="fp32_apply"):
+    """HBM bytes per apply (every kernel of one apply) from the counter summary, or None."""
+    rec = counter_record(config_id)
+    return None if rec is None else 1e6 * sum(rec[prec].values())
+
+
+# VALU issue: packed FP32 is not used, so a wave64 FP32 or FP64 instruction takes 4 cycles of a
+# 16-lane SIMD; 256 CUs x 4 SIMDs at 2.4 GHz
+N_SIMD, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
+
+
+def valu_issue(config_id, kernel_ms):
+    """Compute side of the FP32 apply: the element kernel's VALU instruction count from the counter
+    summary, the time their issue alone takes on the whole chip, and its share of the apply's measured
+    device time (None without a current summary)."""
+    rec = counter_record(config_id)
+    if rec is None or "fp32_element_kernel_valu" not in rec:
         return None
-    return 1e6 * sum(rec[prec].values())
+    v = rec["fp32_element_kernel_valu"]
+    floor_ms = v["valu_instructions"] * CYCLES_PER_VALU / (N_SIMD * CLOCK_HZ) * 1e3
+    return {"kernel": v["kernel"], "valu_instructions": v["valu_instructions"],
+            "valu_instructions_per_wavefront": round(v["valu_instructions"] / v["wavefronts"]),
+            "issue_floor_ms": floor_ms, "frac_of_apply": floor_ms / kernel_ms}
 
 
 def cpu_baseline(seed=0):
@@ -361,6 +384,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach32 / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / 1e9,
+                     "compute": valu_issue(args.config, out["fp32"]["kernel_ms"]) if args.pspace == "P" else None,
                      "traffic_unit": "GB per apply",
                      "kernel": f"one FP32 apply (all its kernels), Q{k} {geo}",
                      "kernel_ms": out["fp32"]["kernel_ms"], "algorithmic_bytes": r["bytes32"]},
