@@ -2354,10 +2354,13 @@ k_lowo(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, c
 constexpr int ASM_NT = 256;
 constexpr int ASM_TILE = 4 * ASM_NT;
 
-// FP32: the entries of the block's nodes form one contiguous range [ptr[n0], ptr[n0 + NT]) of each
+// FP32: the entries of the block's nodes form one contiguous range [ptr[n0], ptr[n0 + M NT]) of each
 // component plane of ev: it is streamed through LDS in tiles with coalesced loads, and each
-// thread sums its own node's segment from LDS in increasing slot order.  FP64: see below.
-template <typename T>
+// thread sums its own nodes' segments (nodes n0 + t + NT j, j < M) from LDS in increasing slot
+// order.  A block takes M = 2 node groups when the mesh averages at most two entries per node
+// (one tile then covers the block's range, and the two dependent reads of ptr that start a
+// block are amortised over twice the nodes); M = 1 otherwise.  FP64: see below.
+template <typename T, int M>
 __global__ void __launch_bounds__(ASM_NT)
 k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_ent,
            const uint8_t *__restrict__ dm, const T *__restrict__ xm, const T *__restrict__ f, T *__restrict__ y,
@@ -2390,17 +2393,20 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
       y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]);
     }
   } else {
+    constexpr int NPB = ASM_NT * M;
     __shared__ T tile[3][ASM_TILE];
-    const int64_t n0 = (int64_t)blockIdx.x * ASM_NT;
-    const int64_t n = n0 + threadIdx.x;
-    const int64_t nend = n0 + ASM_NT < N ? n0 + ASM_NT : N;
+    const int64_t n0 = (int64_t)blockIdx.x * NPB;
+    const int64_t nend = n0 + NPB < N ? n0 + NPB : N;
     const int32_t r0 = ptr[n0], r1 = ptr[nend];
-    int32_t k0 = 0, k1 = 0;
-    if (n < N) {
-      k0 = ptr[n];
-      k1 = ptr[n + 1];
+    int32_t k0[M], k1[M];
+    T sv[M][3];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t n = n0 + threadIdx.x + (int64_t)ASM_NT * j;
+      k0[j] = n < N ? ptr[n] : 0;
+      k1[j] = n < N ? ptr[n + 1] : 0;
+      sv[j][0] = sv[j][1] = sv[j][2] = 0;
     }
-    T s0 = 0, s1 = 0, s2 = 0;
     for (int32_t c0 = r0; c0 < r1; c0 += ASM_TILE) {
       const int32_t cn = r1 - c0 < ASM_TILE ? r1 - c0 : ASM_TILE;
       T a[3][ASM_TILE / ASM_NT];
@@ -2420,20 +2426,26 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
         tile[2][j] = a[2][u];
       }
       __syncthreads();
-      const int32_t kb = k0 > c0 ? k0 : c0, ke = k1 < c0 + cn ? k1 : c0 + cn;
-      for (int32_t k = kb; k < ke; ++k) {
-        s0 += tile[0][k - c0];
-        s1 += tile[1][k - c0];
-        s2 += tile[2][k - c0];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const int32_t kb = k0[j] > c0 ? k0[j] : c0, ke = k1[j] < c0 + cn ? k1[j] : c0 + cn;
+        for (int32_t k = kb; k < ke; ++k) {
+          sv[j][0] += tile[0][k - c0];
+          sv[j][1] += tile[1][k - c0];
+          sv[j][2] += tile[2][k - c0];
+        }
       }
       __syncthreads();
     }
-    if (n >= N) return;
-    const T sv[3] = {s0, s1, s2};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t i = c * N + n;
-      y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]);
+    for (int j = 0; j < M; ++j) {
+      const int64_t n = n0 + threadIdx.x + (int64_t)ASM_NT * j;
+      if (n >= N) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t i = c * N + n;
+        y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[j][c] - f[i] : sv[j][c]);
+      }
     }
   }
 }
@@ -2453,11 +2465,14 @@ static inline int grid1(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 hipError_t launch_assemble(hipStream_t s, int prec, int64_t N, const int32_t *ptr, const void *ev, int64_t n_ent,
                            const uint8_t *dm, const void *xm, const void *f, void *y, double mval) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_assemble<double>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const double *)ev, n_ent,
-                       dm, (const double *)xm, (const double *)f, (double *)y, mval);
+    hipLaunchKernelGGL((k_assemble<double, 1>), dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const double *)ev,
+                       n_ent, dm, (const double *)xm, (const double *)f, (double *)y, mval);
+  else if (n_ent <= 2 * N)
+    hipLaunchKernelGGL((k_assemble<float, 2>), dim3(grid1(N, 2 * ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev,
+                       n_ent, dm, (const float *)xm, (const float *)f, (float *)y, (float)mval);
   else
-    hipLaunchKernelGGL(k_assemble<float>, dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev, n_ent, dm,
-                       (const float *)xm, (const float *)f, (float *)y, (float)mval);
+    hipLaunchKernelGGL((k_assemble<float, 1>), dim3(grid1(N, ASM_NT)), dim3(ASM_NT), 0, s, N, ptr, (const float *)ev,
+                       n_ent, dm, (const float *)xm, (const float *)f, (float *)y, (float)mval);
   return hipGetLastError();
 }
 
