@@ -451,11 +451,14 @@ __device__ void grad_bwd(const T (&fx)[P], const T (&fy)[P], const T (&fz)[P], c
 }
 
 // Per-quadrature-point field f of point i on the x-line of thread tid in block lb.  P = 4:
-// thread-major, the thread's 4 points contiguous, read as one 16/32-byte line with the
-// non-temporal hint (the stream is read once per launch and would otherwise displace from L2
-// the reused lines: gathered nodal values and partially written element-vector lines; 11%
-// faster FP32 apply on the Q3 slab).  P = 3, 5: point-major, so that each of the thread's
-// scalar loads is one contiguous span across the wavefront.
+// thread-major, the thread's 4 points contiguous, read as one 16/32-byte line.  P = 3, 5:
+// point-major, so that each of the thread's scalar loads is one contiguous span across the
+// wavefront.  All with the non-temporal hint: the stream is read once per launch and would
+// otherwise displace from L2 the reused lines, gathered nodal values and partially written
+// element-vector lines (FP32 apply 11% faster on the Q3 slab, element kernel 3% faster on the
+// Q4 terrain and 6% on the Q2 dome).  The hint does not pay on the smaller read-once streams
+// (node words, store positions, pressure coefficients): their lines straddle elements of
+// neighbouring blocks.
 template <int P, int NT, int F>
 __device__ __forceinline__ size_t qp_at(int lb, int f, int tid, int i) {
   if constexpr (P == 4) return (((size_t)lb * F + f) * NT + tid) * P + i;
@@ -474,7 +477,7 @@ __device__ __forceinline__ void load_field(const T *__restrict__ base, int lb, i
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
   } else {
 #pragma unroll
-    for (int i = 0; i < P; ++i) o[i] = base[qp_at<P, NT, F>(lb, f, tid, i)];
+    for (int i = 0; i < P; ++i) o[i] = __builtin_nontemporal_load(base + qp_at<P, NT, F>(lb, f, tid, i));
   }
 }
 
