@@ -464,6 +464,14 @@ __device__ __forceinline__ size_t qp_at(int lb, int f, int tid, int i) {
   if constexpr (P == 4) return (((size_t)lb * F + f) * NT + tid) * P + i;
   else return (((size_t)lb * F + f) * P + i) * NT + tid;
 }
+// Store of a per-point value: point-major layouts (P = 3, 5) write whole lines per instruction and
+// take the non-temporal hint (the state is written once per Newton step and read by the next
+// kernels from HBM; 7% faster linearisation on the Q4 terrain); the thread-major P = 4 layout
+// fills a line over four instructions and keeps the plain store.
+template <int P, typename T> __device__ __forceinline__ void st_store(T *p, T v) {
+  if constexpr (P == 4) *p = v;
+  else __builtin_nontemporal_store(v, p);
+}
 template <typename T, int P, int NT, int F>
 __device__ __forceinline__ void load_field(const T *__restrict__ base, int lb, int f, int tid, T (&o)[P]) {
   if constexpr (P == 4 && sizeof(T) == 4) {
@@ -1185,11 +1193,11 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
       const T ka = cf / ((II + eps) * mup);
       const T vals[NSTATE] = {mup, ka, mup * dxx, mup * dyy, mup * dzz, mup * dxy, mup * dxz, mup * dyz};
 #pragma unroll
-      for (int f = 0; f < NSTATE; ++f) s64[qp_at<P, NT, NSTATE>(lb, f, tid, i)] = vals[f];
+      for (int f = 0; f < NSTATE; ++f) st_store<P>(s64 + qp_at<P, NT, NSTATE>(lb, f, tid, i), vals[f]);
       const T sk = sqrt(ka);
-      s32[qp_at<P, NT, NSTATE32>(lb, 0, tid, i)] = (float)mup;
+      st_store<P>(s32 + qp_at<P, NT, NSTATE32>(lb, 0, tid, i), (float)mup);
 #pragma unroll
-      for (int f = 0; f < 6; ++f) s32[qp_at<P, NT, NSTATE32>(lb, 1 + f, tid, i)] = (float)(sk * vals[2 + f]);
+      for (int f = 0; f < 6; ++f) st_store<P>(s32 + qp_at<P, NT, NSTATE32>(lb, 1 + f, tid, i), (float)(sk * vals[2 + f]));
     }
   }
   const int fid = act ? m.bface_of[e] : -1;
@@ -2353,7 +2361,9 @@ k_lowo(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, c
 // One thread per node: sums the node's contiguous segment of the node-ordered element vector
 // (fixed order, so the result is deterministic).  Rows of Dirichlet-flagged components take the
 // value xm (x for the Jacobian, u for the residual), or mval without xm; other rows subtract f when
-// given.
+// given.  y is written with the non-temporal hint: a write-once stream whose dirty lines would
+// otherwise be evicted from L2 during the next element kernel (FP32 apply on the Q4 terrain 0.7%
+// faster).
 constexpr int ASM_NT = 256;
 constexpr int ASM_TILE = 4 * ASM_NT;
 
@@ -2393,7 +2403,7 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = c * N + n;
-      y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]);
+      __builtin_nontemporal_store(dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]), y + i);
     }
   } else {
     constexpr int NPB = ASM_NT * M;
@@ -2447,7 +2457,7 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int64_t i = c * N + n;
-        y[i] = dm[i] ? (xm ? xm[i] : mval) : (f ? sv[j][c] - f[i] : sv[j][c]);
+        __builtin_nontemporal_store(dm[i] ? (xm ? xm[i] : mval) : (f ? sv[j][c] - f[i] : sv[j][c]), y + i);
       }
     }
   }
