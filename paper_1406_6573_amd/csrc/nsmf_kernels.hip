@@ -2372,7 +2372,11 @@ constexpr int ASM_TILE = 4 * ASM_NT;
 // thread sums its own nodes' segments (nodes n0 + t + NT j, j < M) from LDS in increasing slot
 // order.  A block takes M = 2 node groups when the mesh averages at most two entries per node
 // (one tile then covers the block's range, and the two dependent reads of ptr that start a
-// block are amortised over twice the nodes); M = 1 otherwise.  FP64: see below.
+// block are amortised over twice the nodes); M = 1 otherwise.  Both precisions request each
+// node's Dirichlet flags (and f) together with its segment pointers, so that only the element
+// vector is waited for before the sums; FP32 clamps the node index instead of guarding the loads,
+// since a guarded byte load compiles to a branch with an immediate wait (assembly 144 -> 117 us
+// on the Q4 terrain).  FP64: see below.
 template <typename T, int M>
 __global__ void __launch_bounds__(ASM_NT)
 k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev, int64_t n_ent,
@@ -2386,6 +2390,13 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
     const int64_t n = (int64_t)blockIdx.x * ASM_NT + threadIdx.x;
     if (n >= N) return;
     const int32_t k0 = ptr[n], k1 = ptr[n + 1];
+    int dv[3];
+    T fv[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dv[c] = dm[c * N + n];
+      if (f) fv[c] = f[c * N + n];
+    }
     T sv[3] = {0, 0, 0};
     for (int32_t k = k0; k < k1; k += CH) {
       T a[3][CH];
@@ -2403,7 +2414,7 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = c * N + n;
-      __builtin_nontemporal_store(dm[i] ? (xm ? xm[i] : mval) : (f ? sv[c] - f[i] : sv[c]), y + i);
+      __builtin_nontemporal_store(dv[c] ? (xm ? xm[i] : mval) : sv[c] - fv[c], y + i);
     }
   } else {
     constexpr int NPB = ASM_NT * M;
@@ -2412,13 +2423,20 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
     const int64_t nend = n0 + NPB < N ? n0 + NPB : N;
     const int32_t r0 = ptr[n0], r1 = ptr[nend];
     int32_t k0[M], k1[M];
-    T sv[M][3];
+    int dv[M][3];
+    T sv[M][3], fv[M][3];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const int64_t n = n0 + threadIdx.x + (int64_t)ASM_NT * j;
-      k0[j] = n < N ? ptr[n] : 0;
-      k1[j] = n < N ? ptr[n + 1] : 0;
-      sv[j][0] = sv[j][1] = sv[j][2] = 0;
+      // nodes past N sum node N - 1 again (in bounds) and store nothing
+      const int64_t n = n0 + threadIdx.x + (int64_t)ASM_NT * j, nc = n < N ? n : N - 1;
+      k0[j] = ptr[nc];
+      k1[j] = ptr[nc + 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dv[j][c] = dm[c * N + nc];
+        fv[j][c] = f ? f[c * N + nc] : T(0);
+        sv[j][c] = 0;
+      }
     }
     for (int32_t c0 = r0; c0 < r1; c0 += ASM_TILE) {
       const int32_t cn = r1 - c0 < ASM_TILE ? r1 - c0 : ASM_TILE;
@@ -2457,7 +2475,7 @@ k_assemble(int64_t N, const int32_t *__restrict__ ptr, const T *__restrict__ ev,
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int64_t i = c * N + n;
-        __builtin_nontemporal_store(dm[i] ? (xm ? xm[i] : mval) : (f ? sv[j][c] - f[i] : sv[j][c]), y + i);
+        __builtin_nontemporal_store(dv[j][c] ? (xm ? xm[i] : mval) : sv[j][c] - fv[j][c], y + i);
       }
     }
   }
