@@ -892,6 +892,11 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
   // P = 3, 5 the extra live registers would cost occupancy, and with FP32 and P = 3 the early request
   // measured 4% slower.  The tile's slice is always allocated, also for threads without an element.
   const uint32_t cm = (HANG && act) ? m.cmask[e] : 0u;
+  // basal face of the element, needed after the transposed sweeps: for P = 3, 5 requested here, so
+  // that the block does not wait on it at the barrier before the Robin term (element kernel 1% faster
+  // on the Q4 terrain, 2% on the Q2 dome); for P = 4 the early request measured 2% slower
+  int fid = -1;
+  if constexpr (P != 4) fid = act ? m.bface_of[e] : -1;
   // FP32 apply: the 7-value FP32 state; FP64 and the VJP (which needs Sigma0 : D itself for the
   // logA gradient): the 8-value FP64 state
   constexpr bool kS32 = sizeof(T) == 4 && !VJP;
@@ -1002,7 +1007,7 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
 #pragma unroll
   for (int c = 0; c < 3; ++c) grad_bwd<T, P, false>(gr[c][0], gr[c][1], gr[c][2], zero, y[c], w, tb, t, act);
   // basal Robin term on the zeta = -1 face: y += int beta (T x).(T v)
-  const int fid = act ? m.bface_of[e] : -1;
+  if constexpr (P == 4) fid = act ? m.bface_of[e] : -1;
   if (__syncthreads_or(fid >= 0)) {
     T uq[3], tq[3], out[3];
     face_interp<T, P>(xb, uq, w, tb, t, act);
