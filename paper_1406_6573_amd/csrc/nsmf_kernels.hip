@@ -674,6 +674,13 @@ template <typename T, int P>
 __device__ void face_interp(const T (&xb)[3], T (&uq)[3], Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
   constexpr int P2 = P * P;
   const int i = t % P, j = t / P;
+  // the thread's table rows are requested before the barriers (per-lane table reads)
+  T bi[P], bj[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    bi[a] = tb.B[i][a];
+    bj[a] = tb.B[j][a];
+  }
   if (act)
 #pragma unroll
     for (int c = 0; c < 3; ++c) w.b(0)[c * P2 + t] = xb[c];
@@ -683,7 +690,7 @@ __device__ void face_interp(const T (&xb)[3], T (&uq)[3], Ws<T, P> w, const Tab<
     for (int c = 0; c < 3; ++c) {
       T s = 0;
 #pragma unroll
-      for (int a = 0; a < P; ++a) s += tb.B[i][a] * w.b(0)[c * P2 + a + P * j];
+      for (int a = 0; a < P; ++a) s += bi[a] * w.b(0)[c * P2 + a + P * j];
       w.b(1)[c * P2 + t] = s;
     }
   __syncthreads();
@@ -692,7 +699,7 @@ __device__ void face_interp(const T (&xb)[3], T (&uq)[3], Ws<T, P> w, const Tab<
     for (int c = 0; c < 3; ++c) {
       T s = 0;
 #pragma unroll
-      for (int b = 0; b < P; ++b) s += tb.B[j][b] * w.b(1)[c * P2 + i + P * b];
+      for (int b = 0; b < P; ++b) s += bj[b] * w.b(1)[c * P2 + i + P * b];
       uq[c] = s;
     }
 }
@@ -701,6 +708,12 @@ template <typename T, int P>
 __device__ void face_test(const T (&tq)[3], T (&out)[3], Ws<T, P> w, const Tab<T, P> &tb, int t, bool act) {
   constexpr int P2 = P * P;
   const int i = t % P, j = t / P;
+  T ci[P], cj[P];   // table columns i and j, requested before the barriers
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    ci[a] = tb.B[a][i];
+    cj[a] = tb.B[a][j];
+  }
   if (act)
 #pragma unroll
     for (int c = 0; c < 3; ++c) w.b(2)[c * P2 + t] = tq[c];
@@ -710,7 +723,7 @@ __device__ void face_test(const T (&tq)[3], T (&out)[3], Ws<T, P> w, const Tab<T
     for (int c = 0; c < 3; ++c) {
       T s = 0;
 #pragma unroll
-      for (int jj = 0; jj < P; ++jj) s += tb.B[jj][j] * w.b(2)[c * P2 + i + P * jj];
+      for (int jj = 0; jj < P; ++jj) s += cj[jj] * w.b(2)[c * P2 + i + P * jj];
       w.b(3)[c * P2 + t] = s;
     }
   __syncthreads();
@@ -719,7 +732,7 @@ __device__ void face_test(const T (&tq)[3], T (&out)[3], Ws<T, P> w, const Tab<T
     for (int c = 0; c < 3; ++c) {
       T s = 0;
 #pragma unroll
-      for (int ii = 0; ii < P; ++ii) s += tb.B[ii][i] * w.b(3)[c * P2 + ii + P * j];
+      for (int ii = 0; ii < P; ++ii) s += ci[ii] * w.b(3)[c * P2 + ii + P * j];
       out[c] = s;
     }
   __syncthreads();
@@ -1010,12 +1023,20 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
   if constexpr (P == 4) fid = act ? m.bface_of[e] : -1;
   if (__syncthreads_or(fid >= 0)) {
     T uq[3], tq[3], out[3];
+    // the face point's geometry and beta are requested before the interpolation's barriers
+    T ws = 0, n0 = 0, n1 = 0, n2 = 0, bf = 0;
+    if (fid >= 0) {
+      const T *fg = gv.face + (size_t)fid * NFACEGEO * P2;
+      ws = fg[t];
+      n0 = fg[P2 + t];
+      n1 = fg[2 * P2 + t];
+      n2 = fg[3 * P2 + t];
+      bf = beta[fid];
+    }
     face_interp<T, P>(xb, uq, w, tb, t, act);
     double gb = 0.0;
     if (fid >= 0) {
-      const T *fg = gv.face + (size_t)fid * NFACEGEO * P2;
-      const T ws = fg[t], n0 = fg[P2 + t], n1 = fg[2 * P2 + t], n2 = fg[3 * P2 + t];
-      const T bw = beta[fid] * ws;
+      const T bw = bf * ws;
       const T nu = n0 * uq[0] + n1 * uq[1] + n2 * uq[2];
       tq[0] = bw * (uq[0] - n0 * nu);
       tq[1] = bw * (uq[1] - n1 * nu);
