@@ -1847,7 +1847,7 @@ k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__
   const int c = (int)(blockIdx.x / G);
   const int lane = (int)threadIdx.x;
   const int64_t l = (blockIdx.x % G) * LINE_GROUP + lane;
-  int32_t b0 = 0, len = 0, f0 = -1;
+  int32_t b0 = 0, len = 0, f0 = 0;   // lanes past the last line: an empty line at node 0
   int64_t r0 = 0;
   if (l < n_lines) {
     b0 = line_ptr[l];
@@ -1864,23 +1864,48 @@ k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__
   __syncthreads();
   const T *Fl = F + ((size_t)c * NR + r0) * W;
   const size_t cN = (size_t)c * N;
-  // node of entry i of group line j
-  auto node_of = [&](int j, int32_t i) -> int64_t {
-    const int32_t fj = mfirst[j];
-    return fj >= 0 ? (int64_t)fj + i : (int64_t)line_node[mb0[j] + i];
-  };
   const int je = lane / CH, ee = lane % CH;   // this lane's (line, element) in round 0
+  // node of entry i of group line j.  Without branches on the lane's line: a lane of a line with
+  // consecutive node ids reads line_node[0] and discards it (a branch would make the other lanes'
+  // register writes wait for the outstanding load); no read at all when every line of the group
+  // has consecutive ids (a wavefront-uniform test).
+  const bool all_seq = __all(f0 >= 0);
+  // nd[r] = node of entry ent(j) of line j = r LPR + je, for the CH lines of the lane's chunk slot
+  auto chunk_nodes = [&](auto ent, int32_t (&nd)[CH]) {
+    if (all_seq) {
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        const int j = r * LPR + je;
+        nd[r] = mfirst[j] + ent(j);
+      }
+    } else {
+      int32_t ln[CH];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        const int j = r * LPR + je;
+        ln[r] = line_node[mfirst[j] >= 0 ? 0 : mb0[j] + ent(j)];
+      }
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        const int j = r * LPR + je;
+        nd[r] = mfirst[j] >= 0 ? mfirst[j] + ent(j) : ln[r];
+      }
+    }
+  };
   // forward: v_i = (x_i - sum_d G[i][i-d] v_{i-d}) / G[i][i]
   T v[K + 1];
 #pragma unroll
   for (int r = 0; r <= K; ++r) v[r] = 0;
   for (int32_t i0 = 0; i0 < lmax; i0 += CH) {
+    // the chunk's nodes first, then all its loads, then the LDS writes: no load waits alone.
+    // Entries past a line's end take the line's first node (in bounds); their slots are not read.
+    int32_t nd[CH];
+    chunk_nodes([&](int j) { const int32_t i = i0 + ee; return i < mlen[j] ? i : 0; }, nd);
+    T xv[CH];
 #pragma unroll
-    for (int r = 0; r < CH; ++r) {
-      const int j = r * LPR + je;
-      const int32_t i = i0 + ee;
-      if (i < mlen[j]) buf[j][ee] = x[cN + node_of(j, i)];
-    }
+    for (int r = 0; r < CH; ++r) xv[r] = x[cN + nd[r]];
+#pragma unroll
+    for (int r = 0; r < CH; ++r) buf[r * LPR + je][ee] = xv[r];
     __syncthreads();
     for (int e0 = 0; e0 < CH; e0 += LB) {
       T rw[LB][W];
@@ -1910,8 +1935,7 @@ k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__
 #pragma unroll
     for (int r = 0; r < CH; ++r) {
       const int j = r * LPR + je;
-      const int32_t i = i0 + ee;
-      if (i < mlen[j]) y[cN + node_of(j, i)] = buf[j][ee];
+      if (i0 + ee < mlen[j]) y[cN + nd[r]] = buf[j][ee];
     }
     __syncthreads();
   }
@@ -1925,12 +1949,13 @@ k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__
     for (int d = 0; d < W; ++d) gr[r][d] = 0;
   }
   for (int32_t k0 = 0; k0 < lmax; k0 += CH) {
+    int32_t nd[CH];
+    chunk_nodes([&](int j) { const int32_t lj = mlen[j], ri = k0 + ee; return ri < lj ? lj - 1 - ri : 0; }, nd);
+    T yv[CH];
 #pragma unroll
-    for (int r = 0; r < CH; ++r) {
-      const int j = r * LPR + je;
-      const int32_t lj = mlen[j], ri = k0 + ee;
-      if (ri < lj) buf[j][ee] = y[cN + node_of(j, lj - 1 - ri)];
-    }
+    for (int r = 0; r < CH; ++r) yv[r] = y[cN + nd[r]];
+#pragma unroll
+    for (int r = 0; r < CH; ++r) buf[r * LPR + je][ee] = yv[r];
     __syncthreads();
     for (int e0 = 0; e0 < CH; e0 += LB) {
       T rw[LB][W];
@@ -1966,8 +1991,7 @@ k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__
 #pragma unroll
     for (int r = 0; r < CH; ++r) {
       const int j = r * LPR + je;
-      const int32_t lj = mlen[j], ri = k0 + ee;
-      if (ri < lj) y[cN + node_of(j, lj - 1 - ri)] = buf[j][ee];
+      if (k0 + ee < mlen[j]) y[cN + nd[r]] = buf[j][ee];
     }
     __syncthreads();
   }
