@@ -304,7 +304,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
     if (ok) {
       for (int64_t n = 0; n < N; ++n) cnt[n + 1] += cnt[n];
       ctx->h_lptr.assign(cnt.begin(), cnt.end());
-      ctx->h_lslot.resize(cnt[N]);
+      ctx->h_lslot.assign(cnt[N] + 1, 0);   // + a sentinel (slot 0), so lslot[lptr[n]] is readable for every n
       std::vector<int32_t> next(cnt.begin(), cnt.end() - 1);
       for (int64_t e = 0; e < n_el; ++e)
         for (int t = 0; t < P2; ++t) {

@@ -1175,17 +1175,19 @@ k_grad_p(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *
   const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
-  const StoreIndex<P> ix = store_index<P>(m, lb, e, t, act);
-  const uint32_t cm = act ? m.cmask[e] : 0u;
-  const bool rot = FR && act && (m.en[e * P3 + t] & ROT_BIT);
-  QpGeo<T, P, GEO> g;
+  // in order of use: the pressure coefficients and factors (before the barrier), then geometry,
+  // then what the transposed sweeps and the store need
   T xpt[NPT];
-  if (act) {
-    load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+  if (act)
 #pragma unroll
     for (int r = 0; r < NPT; ++r)
       if (t + r * P2 < NP) xpt[r] = xp[e * NP + t + r * P2];
-  }
+  const PRows<T, P> pr = pressure_rows<T, P>(tb, t);
+  QpGeo<T, P, GEO> g;
+  if (act) load_geo<T, P, GEO, NT>(g, gv, e, lb, tid, tb, t);
+  const StoreIndex<P> ix = store_index<P>(m, lb, e, t, act);
+  const uint32_t cm = act ? m.cmask[e] : 0u;
+  const bool rot = FR && act && (m.en[e * P3 + t] & ROT_BIT);
   T *xps = reinterpret_cast<T *>(red + els * red_stride<P, PS>());
   if (act)
 #pragma unroll
@@ -1193,7 +1195,7 @@ k_grad_p(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *
       if (t + r * P2 < NP) xps[t + r * P2] = xpt[r];
   __syncthreads();
   T pq[P];
-  if (act) pressure_interp<T, P, PS>(xps, tb, t, pq);
+  if (act) pressure_interp<T, P, PS>(xps, tb, pr, pq);
   T f[3][3][P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
@@ -1734,19 +1736,42 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
 // Rows are interleaved by groups of LINE_GROUP lines: node i of line l of group g sits at row
 // base[g] + LINE_GROUP i + (l mod LINE_GROUP), so that the threads of one wavefront, which handle
 // consecutive lines, read consecutive rows at each step of the factorisation and the solves.
-__global__ void k_line_band(int64_t N, int64_t n_inc, int64_t NR, int W, const int32_t *__restrict__ lptr,
+// The node's first MS slot indices are read once (clamped into the node's list; lslot carries one
+// sentinel entry past the end, so an empty list reads in bounds), then each component's entries of
+// all of them are requested together and summed in slot order; slots past MS (none in a 2:1
+// balanced hexahedral mesh) take a plain loop.  Reading slot index and entry per slot in a loop
+// waited on two dependent loads per entry (10 ms on the Q4 terrain).
+template <int W>
+__global__ void k_line_band(int64_t N, int64_t n_inc, int64_t NR, const int32_t *__restrict__ lptr,
                             const int32_t *__restrict__ lslot, const int32_t *__restrict__ prow,
                             const double *__restrict__ buf, double *__restrict__ A) {
+  constexpr int MS = 8, MW = W;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  const int32_t k0 = lptr[n], k1 = lptr[n + 1];
+  const int32_t k0 = lptr[n], k1 = lptr[n + 1], cnt = k1 - k0;
   const int64_t q = prow[n];
-  for (int c = 0; c < 3; ++c)
-    for (int d = 0; d < W; ++d) {
-      double s = 0.0;
-      for (int32_t k = k0; k < k1; ++k) s += buf[((size_t)c * n_inc + lslot[k]) * W + d];
-      A[((size_t)c * NR + q) * W + d] = s;
-    }
+  int32_t sl[MS];
+#pragma unroll
+  for (int u = 0; u < MS; ++u) sl[u] = lslot[k0 + (u < cnt ? u : 0)];
+  for (int c = 0; c < 3; ++c) {
+    double v[MS][MW];
+#pragma unroll
+    for (int u = 0; u < MS; ++u)
+#pragma unroll
+      for (int d = 0; d < MW; ++d) v[u][d] = buf[((size_t)c * n_inc + sl[u]) * W + d];
+    double s[MW];
+#pragma unroll
+    for (int d = 0; d < MW; ++d) s[d] = 0.0;
+#pragma unroll
+    for (int u = 0; u < MS; ++u)
+      if (u < cnt)
+#pragma unroll
+        for (int d = 0; d < MW; ++d) s[d] += v[u][d];
+    for (int32_t k = k0 + MS; k < k1; ++k)
+      for (int d = 0; d < W; ++d) s[d] += buf[((size_t)c * n_inc + lslot[k]) * W + d];
+#pragma unroll
+    for (int d = 0; d < MW; ++d) A[((size_t)c * NR + q) * W + d] = s[d];
+  }
 }
 
 // Banded Cholesky of each line block, one thread per (line, component), in place (interleaved rows,
@@ -2791,8 +2816,15 @@ static hipError_t lines_pg(hipStream_t s, const MeshView &m, const GeoView<doubl
   else
     hipLaunchKernelGGL((k_lines<P, GEO, false>), dim3(m.nblocks), dim3(Launch<P>::NT), 0, s, m, g,
                        &((const TabSet<P> *)tabs)->d, st, beta, buf);
-  hipLaunchKernelGGL(k_line_band, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, NR, P, lptr,
-                     lslot, prow, (const double *)buf, fac64);
+  if (P == 3)
+    hipLaunchKernelGGL(k_line_band<3>, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, NR, lptr,
+                       lslot, prow, (const double *)buf, fac64);
+  else if (P == 4)
+    hipLaunchKernelGGL(k_line_band<4>, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, NR, lptr,
+                       lslot, prow, (const double *)buf, fac64);
+  else
+    hipLaunchKernelGGL(k_line_band<5>, dim3(grid1(m.n_nodes, 256)), dim3(256), 0, s, m.n_nodes, m.n_inc, NR, lptr,
+                       lslot, prow, (const double *)buf, fac64);
   if (n_lines > 0)
     hipLaunchKernelGGL(k_line_factor<P>, dim3(grid1(3 * line_threads(n_lines), 256)), dim3(256), 0, s, m.n_nodes,
                        n_lines, NR, line_ptr, line_node, lrow, dm, fac64, fac32);
