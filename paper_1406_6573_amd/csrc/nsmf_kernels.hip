@@ -1407,8 +1407,10 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
 // beta w|S| phi_a^2 (1 - n_c^2); hanging slots reach their parent nodes through squared
 // interpolation weights (tb2), i.e. sum_e sum_a R_e[a,n]^2 F_e[a,a].  Pressure: the lumped
 // mass weighted by 1/mu with a minus sign, the Schur-complement approximation of Sec. 6.
+// (three wavefronts per SIMD requested: the FP64 Q4 kernel otherwise takes 228 VGPRs, two
+// wavefronts; with the bound it spills 4 and runs 5% faster)
 template <int P, int GEO, int PS, bool FR>
-__global__ void __launch_bounds__(Launch<P>::NT)
+__global__ void __launch_bounds__(Launch<P>::NT, 3)
 k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
        const Tab<double, P> *__restrict__ tb2p, const double *__restrict__ st,
        const double *__restrict__ beta, double *__restrict__ ev, double *__restrict__ dp) {
@@ -1437,64 +1439,90 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   // elements with framed bottom slots: the whole 3x3 blocks, so that a node in a local frame Q
   // gets q_c^T (sum_a R[a, n]^2 F_aa) q_c (FR: the mesh has nodal frames)
   const bool offd = FR && act && m.rot_of[e] >= 0;
+  const int i = t % P, j = t / P;            // slot (i, j, z) of the z-line
+  double jx = 0, jy = 0, jz = 0, detJ = 0;
   if (act) {
-    const int i = t % P, j = t / P;          // slot (i, j, z) of the z-line
-    double jx = 0, jy = 0, jz = 0, detJ = 0;
     if (GEO == GEO_AFFINE) {
       jx = gv.el[4 * e]; jy = gv.el[4 * e + 1]; jz = gv.el[4 * e + 2]; detJ = gv.el[4 * e + 3];
     } else {
       jx = gv.el[2 * e]; jy = gv.el[2 * e + 1];
     }
-    for (int tq = 0; tq < P2; ++tq) {          // quadrature points (qx, qy, qz), qy + P qz = tq
-      const int qy = tq % P, qz = tq / P;
-      const int tidq = el * P2 + tq;
-      for (int qx = 0; qx < P; ++qx) {
-        const double mu = st[qp_at<P, NT, NSTATE>(lb, 0, tidq, qx)];
-        const double ka = st[qp_at<P, NT, NSTATE>(lb, 1, tidq, qx)];
-        double S[6];
-        for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
-        double a = 0, b = 0, cc = jz, wd;
-        if (GEO == GEO_AFFINE) {
-          wd = tb.w[qx] * tb.w[qy] * tb.w[qz] * detJ;
-        } else {
-          a = gv.qp[qp_at<P, NT, NGEOQP>(lb, 0, tidq, qx)];
-          b = gv.qp[qp_at<P, NT, NGEOQP>(lb, 1, tidq, qx)];
-          cc = gv.qp[qp_at<P, NT, NGEOQP>(lb, 2, tidq, qx)];
-          wd = tb.w[qx] * tb.w[qy] * tb.w[qz] / (jx * jy * cc);
-        }
-        // pressure: thread (j, z) of the x-line layout owns points (., j, z); here every
-        // thread accumulates the points of its own tq = t for the lumped 1/mu mass
-        if (tq == t) {
-          const double g = wd * wd / mu;
-          constexpr PExp<P, PS> pe{};
+  }
+  // The element's quadrature points are visited one z-plane (qz) at a time: thread t first stages
+  // the state and geometry of point (qx, qy) = (t % P, t / P) of the plane in the element's
+  // workspace, then every thread reads the plane from LDS (one load latency per plane instead of
+  // one per point).  Points are visited in the same order as a plain loop over (qy + P qz, qx).
+  constexpr int NV = NSTATE + NGEOQP;        // staged values per point
+  static_assert(NV * P2 <= Ws<T, P>::ES, "plane staging exceeds the element workspace");
+  T *stg = w.s;
+#pragma unroll 1
+  for (int qz = 0; qz < P; ++qz) {
+    __syncthreads();
+    if (act) {
+      const int tidq = el * P2 + j + P * qz;   // x-line (qy, qz) = (j, qz), point qx = i
 #pragma unroll
-          for (int mm = 0; mm < NP; ++mm) {
-            const double psi = tb.L[pe.e[mm][0]][qx] * tb.L[pe.e[mm][1]][qy] * tb.L[pe.e[mm][2]][qz];
-            part[mm] += g * psi * psi;
-          }
-        }
-        for (int z = 0; z < P; ++z) {
-          const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
-          const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
-          const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
-          double G[3];
+      for (int f = 0; f < NSTATE; ++f) stg[f * P2 + t] = st[qp_at<P, NT, NSTATE>(lb, f, tidq, i)];
+      if (GEO != GEO_AFFINE)
+#pragma unroll
+        for (int f = 0; f < NGEOQP; ++f) stg[(NSTATE + f) * P2 + t] = gv.qp[qp_at<P, NT, NGEOQP>(lb, f, tidq, i)];
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll 1
+      for (int qy = 0; qy < P; ++qy) {
+        const int tq = qy + P * qz;
+#pragma unroll 1
+        for (int qx = 0; qx < P; ++qx) {
+          const int pt = qx + P * qy;
+          const double mu = stg[pt];
+          const double ka = stg[P2 + pt];
+          double S[6];
+          for (int f = 0; f < 6; ++f) S[f] = stg[(2 + f) * P2 + pt];
+          double a = 0, b = 0, cc = jz, wd;
           if (GEO == GEO_AFFINE) {
-            G[0] = gr0 * jx; G[1] = gr1 * jy; G[2] = gr2 * jz;
+            wd = tb.w[qx] * tb.w[qy] * tb.w[qz] * detJ;
           } else {
-            G[0] = gr0 * jx + gr2 * a; G[1] = gr1 * jy + gr2 * b; G[2] = gr2 * cc;
+            a = stg[NSTATE * P2 + pt];
+            b = stg[(NSTATE + 1) * P2 + pt];
+            cc = stg[(NSTATE + 2) * P2 + pt];
+            wd = tb.w[qx] * tb.w[qy] * tb.w[qz] / (jx * jy * cc);
           }
-          const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-          const double SG[3] = {S[0] * G[0] + S[3] * G[1] + S[4] * G[2], S[3] * G[0] + S[1] * G[1] + S[5] * G[2],
-                                S[4] * G[0] + S[5] * G[1] + S[2] * G[2]};
-          for (int c = 0; c < 3; ++c) y[c][z] += 0.5 * mu * (g2 + G[c] * G[c]) - ka * SG[c] * SG[c];
-          if (offd) {
-            yo[0][z] += 0.5 * mu * G[0] * G[1] - ka * SG[0] * SG[1];
-            yo[1][z] += 0.5 * mu * G[0] * G[2] - ka * SG[0] * SG[2];
-            yo[2][z] += 0.5 * mu * G[1] * G[2] - ka * SG[1] * SG[2];
+          // pressure: thread (j, z) of the x-line layout owns points (., j, z); here every
+          // thread accumulates the points of its own tq = t for the lumped 1/mu mass
+          if (tq == t) {
+            const double g = wd * wd / mu;
+            constexpr PExp<P, PS> pe{};
+#pragma unroll
+            for (int mm = 0; mm < NP; ++mm) {
+              const double psi = tb.L[pe.e[mm][0]][qx] * tb.L[pe.e[mm][1]][qy] * tb.L[pe.e[mm][2]][qz];
+              part[mm] += g * psi * psi;
+            }
+          }
+          for (int z = 0; z < P; ++z) {
+            const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
+            const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
+            const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
+            double G[3];
+            if (GEO == GEO_AFFINE) {
+              G[0] = gr0 * jx; G[1] = gr1 * jy; G[2] = gr2 * jz;
+            } else {
+              G[0] = gr0 * jx + gr2 * a; G[1] = gr1 * jy + gr2 * b; G[2] = gr2 * cc;
+            }
+            const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+            const double SG[3] = {S[0] * G[0] + S[3] * G[1] + S[4] * G[2], S[3] * G[0] + S[1] * G[1] + S[5] * G[2],
+                                  S[4] * G[0] + S[5] * G[1] + S[2] * G[2]};
+            for (int c = 0; c < 3; ++c) y[c][z] += 0.5 * mu * (g2 + G[c] * G[c]) - ka * SG[c] * SG[c];
+            if (offd) {
+              yo[0][z] += 0.5 * mu * G[0] * G[1] - ka * SG[0] * SG[1];
+              yo[1][z] += 0.5 * mu * G[0] * G[2] - ka * SG[0] * SG[2];
+              yo[2][z] += 0.5 * mu * G[1] * G[2] - ka * SG[1] * SG[2];
+            }
           }
         }
       }
-    }
+  }
+  __syncthreads();   // the workspace is reused below
+  if (act) {
     const int fid = m.bface_of[e];
     if (fid >= 0) {
       const double *fg = gv.face + (size_t)fid * NFACEGEO * P2;
