@@ -1594,10 +1594,10 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
   const int lb = logical_block();
   const int tid = threadIdx.x, el = tid / P2, t = tid % P2;
   const int64_t e = tile_elem<E>(m, lb, el);
-  if (e < 0) return;                        // no barriers in this kernel
+  const int els = el < E ? el : E - 1;
   const int i = t % P, j = t / P;
-  int lo, hi;
-  if (!zline_run<P>(m.cmask[e], i, j, lo, hi)) return;
+  int lo = 0, hi = -1;
+  const bool act = e >= 0 && zline_run<P>(m.cmask[e], i, j, lo, hi);   // this thread's z-line has a run
   double rows[3][P][P];                     // rows[c][za][d] = F_e[za, za + d]
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -1606,52 +1606,75 @@ k_lines(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
 #pragma unroll
       for (int d = 0; d < P; ++d) rows[c][a][d] = 0;
   double jx = 0, jy = 0, jz = 0;
-  if (GEO == GEO_AFFINE) {
-    jx = gv.el[4 * e]; jy = gv.el[4 * e + 1]; jz = gv.el[4 * e + 2];
-  } else {
-    jx = gv.el[2 * e]; jy = gv.el[2 * e + 1];
-  }
-  for (int tq = 0; tq < P2; ++tq) {
-    const int qy = tq % P, qz = tq / P, tidq = el * P2 + tq;
-    for (int qx = 0; qx < P; ++qx) {
-      const double mu = st[qp_at<P, NT, NSTATE>(lb, 0, tidq, qx)];
-      const double ka = st[qp_at<P, NT, NSTATE>(lb, 1, tidq, qx)];
-      double S[6];
-#pragma unroll
-      for (int f = 0; f < 6; ++f) S[f] = st[qp_at<P, NT, NSTATE>(lb, 2 + f, tidq, qx)];
-      double a = 0, b = 0, cc = jz;
-      if (GEO != GEO_AFFINE) {
-        a = gv.qp[qp_at<P, NT, NGEOQP>(lb, 0, tidq, qx)];
-        b = gv.qp[qp_at<P, NT, NGEOQP>(lb, 1, tidq, qx)];
-        cc = gv.qp[qp_at<P, NT, NGEOQP>(lb, 2, tidq, qx)];
-      }
-      double G[P][3], SG[P][3];
-#pragma unroll
-      for (int z = 0; z < P; ++z) {
-        const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
-        const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
-        const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
-        if (GEO == GEO_AFFINE) {
-          G[z][0] = gr0 * jx; G[z][1] = gr1 * jy; G[z][2] = gr2 * jz;
-        } else {
-          G[z][0] = gr0 * jx + gr2 * a; G[z][1] = gr1 * jy + gr2 * b; G[z][2] = gr2 * cc;
-        }
-        SG[z][0] = S[0] * G[z][0] + S[3] * G[z][1] + S[4] * G[z][2];
-        SG[z][1] = S[3] * G[z][0] + S[1] * G[z][1] + S[5] * G[z][2];
-        SG[z][2] = S[4] * G[z][0] + S[5] * G[z][1] + S[2] * G[z][2];
-      }
-#pragma unroll
-      for (int za = 0; za < P; ++za)
-#pragma unroll
-        for (int d = 0; d < P; ++d) {
-          if (za + d >= P) continue;
-          const int zb = za + d;
-          const double g = G[za][0] * G[zb][0] + G[za][1] * G[zb][1] + G[za][2] * G[zb][2];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) rows[c][za][d] += 0.5 * mu * (g + G[za][c] * G[zb][c]) - ka * SG[za][c] * SG[zb][c];
-        }
+  if (e >= 0) {
+    if (GEO == GEO_AFFINE) {
+      jx = gv.el[4 * e]; jy = gv.el[4 * e + 1]; jz = gv.el[4 * e + 2];
+    } else {
+      jx = gv.el[2 * e]; jy = gv.el[2 * e + 1];
     }
   }
+  // The element's points are visited one z-plane (qz) at a time, staged in LDS by the element's
+  // threads (each the point (qx, qy) = (i, j) of the plane), in the order of a plain loop over
+  // (qy + P qz, qx): one load latency per plane instead of one per point.
+  constexpr int NV = NSTATE + NGEOQP;
+  __shared__ double stg[E][NV * P2];
+#pragma unroll 1
+  for (int qz = 0; qz < P; ++qz) {
+    __syncthreads();
+    if (e >= 0) {
+      const int tidq = el * P2 + j + P * qz;
+#pragma unroll
+      for (int f = 0; f < NSTATE; ++f) stg[els][f * P2 + t] = st[qp_at<P, NT, NSTATE>(lb, f, tidq, i)];
+      if (GEO != GEO_AFFINE)
+#pragma unroll
+        for (int f = 0; f < NGEOQP; ++f) stg[els][(NSTATE + f) * P2 + t] = gv.qp[qp_at<P, NT, NGEOQP>(lb, f, tidq, i)];
+    }
+    __syncthreads();
+    if (!act) continue;
+#pragma unroll 1
+    for (int qy = 0; qy < P; ++qy)
+#pragma unroll 1
+      for (int qx = 0; qx < P; ++qx) {
+        const double *sp = &stg[els][qx + P * qy];
+        const double mu = sp[0];
+        const double ka = sp[P2];
+        double S[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) S[f] = sp[(2 + f) * P2];
+        double a = 0, b = 0, cc = jz;
+        if (GEO != GEO_AFFINE) {
+          a = sp[NSTATE * P2];
+          b = sp[(NSTATE + 1) * P2];
+          cc = sp[(NSTATE + 2) * P2];
+        }
+        double G[P][3], SG[P][3];
+#pragma unroll
+        for (int z = 0; z < P; ++z) {
+          const double gr0 = tb.D[qx][i] * tb.B[qy][j] * tb.B[qz][z];
+          const double gr1 = tb.B[qx][i] * tb.D[qy][j] * tb.B[qz][z];
+          const double gr2 = tb.B[qx][i] * tb.B[qy][j] * tb.D[qz][z];
+          if (GEO == GEO_AFFINE) {
+            G[z][0] = gr0 * jx; G[z][1] = gr1 * jy; G[z][2] = gr2 * jz;
+          } else {
+            G[z][0] = gr0 * jx + gr2 * a; G[z][1] = gr1 * jy + gr2 * b; G[z][2] = gr2 * cc;
+          }
+          SG[z][0] = S[0] * G[z][0] + S[3] * G[z][1] + S[4] * G[z][2];
+          SG[z][1] = S[3] * G[z][0] + S[1] * G[z][1] + S[5] * G[z][2];
+          SG[z][2] = S[4] * G[z][0] + S[5] * G[z][1] + S[2] * G[z][2];
+        }
+#pragma unroll
+        for (int za = 0; za < P; ++za)
+#pragma unroll
+          for (int d = 0; d < P; ++d) {
+            if (za + d >= P) continue;
+            const int zb = za + d;
+            const double g = G[za][0] * G[zb][0] + G[za][1] * G[zb][1] + G[za][2] * G[zb][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rows[c][za][d] += 0.5 * mu * (g + G[za][c] * G[zb][c]) - ka * SG[za][c] * SG[zb][c];
+          }
+      }
+  }
+  if (!act) return;                         // no barriers below
   const int fid = m.bface_of[e];
   if (fid >= 0) {
     const double *fg = gv.face + (size_t)fid * NFACEGEO * P2;
