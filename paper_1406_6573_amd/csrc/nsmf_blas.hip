@@ -310,15 +310,28 @@ __global__ void k_prolong(int64_t N, int64_t nc, const int32_t *__restrict__ cpt
                           T *__restrict__ x) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
+  // node inputs first (unsigned corner ids: widening them needs no wait for the load)
+  uint32_t cj[4];
+  double wj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    cj[j] = (uint32_t)cpt[4 * n + j];
+    wj[j] = cw[4 * n + j];
+  }
+  int dv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dv[c] = dm[(size_t)c * N + n];
   double l[NCZ];
   zprof(zeta[n], l);
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
     double v = 0.0;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const double *p = xc + ((size_t)c * nc + cpt[4 * n + j]) * NCZ;
-      v += cw[4 * n + j] * (l[0] * p[0] + l[1] * p[1] + l[2] * p[2]);
+      const double *p = xc + ((size_t)c * nc + cj[j]) * NCZ;
+      v += wj[j] * (l[0] * p[0] + l[1] * p[1] + l[2] * p[2]);
     }
-    x[(size_t)c * N + n] = dm[(size_t)c * N + n] ? T(0) : (T)v;
+    x[(size_t)c * N + n] = dv[c] ? T(0) : (T)v;
   }
 }
 
@@ -333,14 +346,41 @@ k_restrict(int64_t N, int64_t nc, const int64_t *__restrict__ cptr, const int32_
   __shared__ double red[3 * NCZ][RST_NT];
   const int64_t J = blockIdx.x;
   double acc[3][NCZ] = {};
-  for (int64_t k = cptr[J] + threadIdx.x; k < cptr[J + 1]; k += RST_NT) {
-    const int32_t n = cnode[k];
-    double l[NCZ];
-    zprof(zeta[n], l);
-    const double wv = cwt[k];
-    for (int c = 0; c < 3; ++c) {
-      const double rv = dm[(size_t)c * N + n] ? 0.0 : (double)r[(size_t)c * N + n];
-      for (int m = 0; m < NCZ; ++m) acc[c][m] += wv * l[m] * rv;
+  // each thread takes list entries k = k0 + tid + RST_NT i in increasing i, UB at a time: all their
+  // loads are requested before any is used (entries past the end read entry k0, in bounds, and add
+  // zero: a conditional accumulation lets the compiler move the loads into the branches)
+  constexpr int UB = 4;
+  const int64_t k0 = cptr[J], k1 = cptr[J + 1];
+  for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += UB * RST_NT) {
+    uint32_t nn[UB];   // unsigned: widening it to an address needs no wait for the loaded value
+    double wv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int64_t k = kb + (int64_t)u * RST_NT, kc = k < k1 ? k : k0;
+      nn[u] = (uint32_t)cnode[kc];
+      wv[u] = cwt[kc];
+    }
+    double z[UB], rv[UB][3];
+    int dv[UB][3];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      z[u] = zeta[nn[u]];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dv[u][c] = dm[(size_t)c * N + nn[u]];
+        rv[u][c] = (double)r[(size_t)c * N + nn[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const bool in = kb + (int64_t)u * RST_NT < k1;
+      double l[NCZ];
+      zprof(z[u], l);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v = (dv[u][c] || !in) ? 0.0 : rv[u][c];
+        for (int m = 0; m < NCZ; ++m) acc[c][m] += wv[u] * l[m] * v;
+      }
     }
   }
   for (int c = 0; c < 3; ++c)
