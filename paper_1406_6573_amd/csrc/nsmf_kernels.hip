@@ -1323,6 +1323,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
   const int64_t e = tile_elem<E>(m, lb, el);
   const bool act = e >= 0;
   const int els = el < E ? el : E - 1;
+  const int fid = act ? m.bface_of[e] : -1;   // basal face, requested with the element's first data
   Ws<T, P> w{smem + els * Ws<T, P>::ES};
   const int64_t N = m.n_nodes;
   const uint32_t cm = act ? m.cmask[e] : 0u;
@@ -1379,14 +1380,15 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
   T y[3][P];
 #pragma unroll
   for (int c = 0; c < 3; ++c) grad_bwd<T, P, true>(fr[c][0], fr[c][1], fr[c][2], f0[c], y[c], w, tb, t, act);
-  const int fid = act ? m.bface_of[e] : -1;
-  if (__syncthreads_or(fid >= 0)) {
-    T tq[3] = {0, 0, 0}, out[3];
-    if (fid >= 0) {
-      const T *fs = fst + (size_t)fid * NFACEST * P2;
+  // the basal term's face data are requested before the vote's barriers
+  T tq[3] = {0, 0, 0};
+  if (fid >= 0) {
+    const T *fs = fst + (size_t)fid * NFACEST * P2;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) tq[c] = beta[fid] * fs[c * P2 + t];
-    }
+    for (int c = 0; c < 3; ++c) tq[c] = beta[fid] * fs[c * P2 + t];
+  }
+  if (__syncthreads_or(fid >= 0)) {
+    T out[3];
     face_test<T, P>(tq, out, w, tb, t, act);
     if (fid >= 0)
 #pragma unroll
