@@ -72,7 +72,7 @@ struct nsmf_ctx {
   std::string err = "";
   // mesh
   bool have_mesh = false;
-  int k = 0, P = 0, n_p = 0, ps = PS_P, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0;
+  int k = 0, P = 0, n_p = 0, ps = PS_P, geo = GEO_AFFINE, nt = 0, epb = 0, nblocks = 0, any_hang = 0;
   int64_t n_el = 0, n_nodes = 0, n_bface = 0, n_inc = 0, n_ent = 0;
   HostTables tab;
   DevBuf<uint32_t> en, cmask;
@@ -147,6 +147,7 @@ struct nsmf_ctx {
     m.n_el = n_el;
     m.n_nodes = n_nodes;
     m.nblocks = nblocks;
+    m.any_hang = any_hang;
     return m;
   }
   GeoView<double> geo64() const { return GeoView<double>{geo_el64.p, geo_qp64.p, face64.p, rot64.p}; }
@@ -244,8 +245,11 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
         if (m->dmask[c * N + id]) wd |= 1u << (MASK_SHIFT + c);
     words[i] = wd;
   }
-  for (int64_t e = 0; e < n_el; ++e)
+  int any_hang = 0;
+  for (int64_t e = 0; e < n_el; ++e) {
     if (m->cmask[e] >> 21) return ctx->fail(NSMF_EMESH, "cmask has bits above 20");
+    if (m->cmask[e] >> 3) any_hang = 1;
+  }
   // ---- nodal frames: orthonormal, each node once, named only by bottom slots (z = 0)
   std::vector<int32_t> frame_row;
   if (m->n_frames < 0 || (m->n_frames > 0 && (!m->frame_nodes || !m->frames)))
@@ -364,6 +368,7 @@ int nsmf_upload_mesh(nsmf_ctx *ctx, const nsmf_mesh *m) {
   ctx->nt = launch_threads(P);
   ctx->epb = launch_elems(P);
   ctx->nblocks = (int)((n_el + ctx->epb - 1) / ctx->epb);
+  ctx->any_hang = any_hang;
   hipStream_t s = ctx->stream;
 
   NSMF_TRY(ctx, ctx->en.alloc(words.size()), "hipMalloc");

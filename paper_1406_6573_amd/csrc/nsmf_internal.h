@@ -102,6 +102,7 @@ struct MeshView {
   int64_t n_el, n_nodes, n_inc;   // n_inc = n_el P^3 element slots
   int64_t n_ent;                  // stored entries of the element vector per component (its plane stride)
   int nblocks;
+  int any_hang;                   // 1 if some element has a hanging face or edge (cmask bits above 2)
 };
 
 template <typename T> struct GeoView {

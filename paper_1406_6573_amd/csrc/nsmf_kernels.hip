@@ -993,7 +993,7 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
       if (t + r * P2 < NP) xpt[r] = xp[e * NP + t + r * P2];
   }
   if constexpr (HANG)
-    if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+    if (m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
 
   T gr[3][3][P];
@@ -1118,7 +1118,7 @@ __device__ __forceinline__ void apply_elem(const MeshView &m, const GeoView<T> &
     }
   }
   if constexpr (HANG)
-    if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+    if (m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
   if (rot) {
     T Q[9];
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
@@ -1215,7 +1215,7 @@ k_grad_p(MeshView m, GeoView<T> gv, const Tab<T, P> *__restrict__ tbp, const T *
   const T zero[P] = {};
 #pragma unroll
   for (int c = 0; c < 3; ++c) grad_bwd<T, P, false>(f[c][0], f[c][1], f[c][2], zero, y[c], w, tb, t, act);
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  if (m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
   if (rot) {
     T Q[9];
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
@@ -1252,7 +1252,7 @@ k_state(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, 
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
     frame_in<T, P>(v, Q);
   }
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  if (m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
   T gr[3][3][P];
 #pragma unroll
@@ -1394,7 +1394,7 @@ k_residual(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tb
 #pragma unroll
       for (int c = 0; c < 3; ++c) y[c][0] += out[c];
   }
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
+  if (m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u)) hang_bwd<T, P>(y, cm, w, tb, t, act);
   if (act && (nw[0] & ROT_BIT)) {
     T Q[9];
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
@@ -1546,7 +1546,7 @@ k_diag(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp,
   }
   // lumped -M(1/mu): thread t holds the points of x-line t, reduce over the element's threads
   pressure_reduce<T, P, NP>(part, w, t, act, act ? dp + e * NP : nullptr);
-  const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
+  const bool hang = m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u);
   if (hang) hang_bwd<T, P>(y, cm, w, tb2, t, act);
   if constexpr (FR) {
     if (hang && __syncthreads_or(offd)) hang_bwd<T, P>(yo, cm, w, tb2, t, act);
@@ -2118,7 +2118,7 @@ k_geometry(MeshView m, const Tab<double, P> *__restrict__ tbp, const double *__r
         v[c][z] = d;
       }
   __syncthreads();
-  if (__syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
+  if (m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u)) hang_fwd<T, P>(v, cm, w, tb, t, act);
   const T xb[3] = {v[0][0], v[1][0], v[2][0]};
   T J[3][3][P];   // J[i][r] = d x_i / d xi_r
 #pragma unroll
@@ -2301,7 +2301,7 @@ k_lowo_coef(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ t
         if (per > 0.0) d -= per * rint(d / per);
         xv[c][z] = d;
       }
-  const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
+  const bool hang = m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u);
   if (hang) hang_fwd<T, P>(xv, cm, w, tb, t, act);
   if (act)
 #pragma unroll
@@ -2399,7 +2399,7 @@ k_lowo(MeshView m, GeoView<double> gv, const Tab<double, P> *__restrict__ tbp, c
     frame_load<T, P>(gv.rot, m.rot_of[e], t, Q);
     frame_in<T, P>(v, Q);
   }
-  const bool hang = __syncthreads_or(act && (cm >> 3) != 0u);
+  const bool hang = m.any_hang && __syncthreads_or(act && (cm >> 3) != 0u);
   if (hang) hang_fwd<T, P>(v, cm, w, tb, t, act);
   __syncthreads();
   if (act)
