@@ -1917,7 +1917,9 @@ k_line_apply(int64_t N, int64_t n_lines, int64_t NR, const int32_t *__restrict__
              const int32_t *__restrict__ line_node, const int32_t *__restrict__ lrow,
              const int32_t *__restrict__ first, const T *__restrict__ F, const T *__restrict__ x,
              T *__restrict__ y) {
-  constexpr int K = W - 1, LB = 8, CH = LINE_CH, LPR = LINE_GROUP / CH;   // lines per round
+  // LB: factor rows requested ahead of the recurrence (16 in FP32: 5% faster on the Q4 terrain; FP64
+  // keeps 8 for its registers); LPR: lines per round
+  constexpr int K = W - 1, LB = sizeof(T) == 4 ? 16 : 8, CH = LINE_CH, LPR = LINE_GROUP / CH;
   static_assert(LINE_GROUP % CH == 0 && CH % LB == 0, "chunk shape");
   __shared__ T buf[LINE_GROUP][CH + 1];
   __shared__ int32_t mlen[LINE_GROUP], mfirst[LINE_GROUP], mb0[LINE_GROUP];
